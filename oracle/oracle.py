@@ -1,0 +1,219 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes binding of the CPU oracle (pf_oracle.c).
+
+The oracle is the plain CPU particle filter of Supplementary I (Algorithm
+"Likelihood Approximation using particle filter") with Gillespie direct-method
+propagation.  Only tests, the smoke check and the benchmark's CPU-baseline leg
+may import this module; the GPU library never does.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "pf_oracle.c")
+
+OK, EVENT_CAP, COUNT_OVERFLOW, BAD_THETA = 0, 1, 2, 3
+FP64, FP32_MIXED = 0, 1
+OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
+
+
+def build():
+    """Compile the oracle: no fast-math, no FMA contraction (fma() explicit)."""
+    cmd = ["gcc", "-O2", "-mfma", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-pthread", "-o", _LIB_PATH, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_species", ctypes.c_int32),
+        ("n_reactions", ctypes.c_int32),
+        ("reactant_orders", ctypes.c_void_p),
+        ("stoich", ctypes.c_void_p),
+        ("obs_kind", ctypes.c_int32),
+        ("n_observed", ctypes.c_int32),
+        ("observed", ctypes.c_void_p),
+        ("sigma", ctypes.c_double),
+        ("n_theta", ctypes.c_int32),
+        ("theta", ctypes.c_void_p),
+        ("theta_ids", ctypes.c_void_p),
+        ("n_traj", ctypes.c_int32),
+        ("obs_offsets", ctypes.c_void_p),
+        ("t_obs", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("t0", ctypes.c_void_p),
+        ("x0", ctypes.c_void_p),
+        ("n_particles", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int32),
+        ("event_cap", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                  ctypes.c_uint64, ctypes.c_double)
+        L.orc_philox.argtypes = [vp, vp, vp]
+        L.orc_log.argtypes = [dbl]
+        L.orc_log.restype = dbl
+        L.orc_exp.argtypes = [dbl]
+        L.orc_exp.restype = dbl
+        L.orc_logf.argtypes = [ctypes.c_float]
+        L.orc_logf.restype = ctypes.c_float
+        L.orc_propensities.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+        L.orc_resample.argtypes = [i32, vp, u64, vp]
+        L.orc_resample_word.argtypes = [u64, u32, u32, u32]
+        L.orc_resample_word.restype = u64
+        L.orc_eval.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_eval.restype = ctypes.c_int
+        L.orc_trace_filter.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.orc_trace_filter.restype = ctypes.c_int
+        L.orc_ssa_paths.argtypes = [vp, vp, u32, vp, dbl, dbl, i32, vp, vp]
+        L.orc_ssa_paths.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Problem:
+    """Holds contiguous numpy copies of one batch and the C struct over them."""
+
+    def __init__(self, reactant_orders, stoich, obs_kind, observed, sigma, theta,
+                 trajectories, n_particles, seed, precision=FP64, event_cap=100_000_000,
+                 theta_ids=None):
+        self.orders = np.ascontiguousarray(reactant_orders, dtype=np.int32)
+        self.stoich = np.ascontiguousarray(stoich, dtype=np.int32)
+        R, U = self.orders.shape
+        self.U, self.R = U, R
+        self.observed = np.ascontiguousarray(observed, dtype=np.int32)
+        self.theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, R))
+        self.theta_ids = (None if theta_ids is None
+                          else np.ascontiguousarray(theta_ids, dtype=np.uint32))
+        P = len(self.observed)
+        offs = [0]
+        t_obs, ys, t0, x0 = [], [], [], []
+        for tr in trajectories:
+            t_obs.append(np.asarray(tr["t_obs"], dtype=np.float64))
+            ys.append(np.asarray(tr["y"], dtype=np.float64).reshape(-1, P))
+            t0.append(float(tr.get("t0", 0.0)))
+            x0.append(np.asarray(tr["x0"], dtype=np.int32))
+            offs.append(offs[-1] + len(t_obs[-1]))
+        self.offsets = np.array(offs, dtype=np.int32)
+        self.t_obs = np.ascontiguousarray(np.concatenate(t_obs))
+        self.y = np.ascontiguousarray(np.concatenate(ys))
+        self.t0 = np.array(t0, dtype=np.float64)
+        self.x0 = np.ascontiguousarray(np.stack(x0))
+        self.H = int(n_particles)
+        self.M = len(trajectories)
+        self.n_theta = self.theta.shape[0]
+        self.c = _Problem(
+            U, R, _ptr(self.orders), _ptr(self.stoich), int(obs_kind), P,
+            _ptr(self.observed), float(sigma), self.n_theta, _ptr(self.theta),
+            _ptr(self.theta_ids), self.M, _ptr(self.offsets), _ptr(self.t_obs),
+            _ptr(self.y), _ptr(self.t0), _ptr(self.x0), self.H, int(seed) & (2**64 - 1),
+            int(precision), int(event_cap))
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def log(x):
+    return lib().orc_log(float(x))
+
+
+def exp(d):
+    return lib().orc_exp(float(d))
+
+
+def logf(x):
+    return lib().orc_logf(float(np.float32(x)))
+
+
+def propensities(prob, c, x, precision=FP64):
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    out = np.zeros(prob.R, dtype=np.float64)
+    lib().orc_propensities(ctypes.byref(prob.c), c.ctypes.data, x.ctypes.data,
+                           int(precision), out.ctypes.data)
+    return out
+
+
+def resample(e, w64):
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    anc = np.zeros(len(e), dtype=np.int32)
+    lib().orc_resample(len(e), e.ctypes.data, int(w64), anc.ctypes.data)
+    return anc
+
+
+def resample_word(seed, theta_id, traj, t):
+    return lib().orc_resample_word(int(seed), int(theta_id), int(traj), int(t))
+
+
+def evaluate(prob, nthreads=None, want_final_state=False):
+    """Returns dict: loglik[n_theta], status[n_theta], filter_ll[F], events[F]
+    (and final_state[F, U, H] if requested)."""
+    if nthreads is None:
+        nthreads = min(os.cpu_count() or 1, 16)
+    F = prob.n_theta * prob.M
+    ll = np.zeros(prob.n_theta, dtype=np.float64)
+    st = np.zeros(prob.n_theta, dtype=np.int32)
+    fll = np.zeros(max(F, 1), dtype=np.float64)
+    fev = np.zeros(max(F, 1), dtype=np.uint64)
+    fs = np.zeros((max(F, 1), prob.U, prob.H), dtype=np.int32) if want_final_state else None
+    rc = lib().orc_eval(ctypes.byref(prob.c), int(nthreads), ll.ctypes.data, st.ctypes.data,
+                        fll.ctypes.data, fev.ctypes.data, _ptr(fs))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    out = {"loglik": ll, "status": st, "filter_ll": fll[:F], "events": fev[:F]}
+    if want_final_state:
+        out["final_state"] = fs[:F]
+    return out
+
+
+def trace_filter(prob, i, m):
+    """Full trace of filter (theta i, trajectory m): states [T,H,U], logw [T,H],
+    ancestors [T,H], ll_inc [T], loglik, events, status."""
+    T = int(prob.offsets[m + 1] - prob.offsets[m])
+    H, U = prob.H, prob.U
+    states = np.zeros((T, H, U), dtype=np.int32)
+    logw = np.full((T, H), np.nan)
+    anc = np.zeros((T, H), dtype=np.int32)
+    inc = np.full(T, np.nan)
+    ll = ctypes.c_double()
+    ev = ctypes.c_uint64()
+    st = lib().orc_trace_filter(ctypes.byref(prob.c), int(i), int(m), states.ctypes.data,
+                                logw.ctypes.data, anc.ctypes.data, inc.ctypes.data,
+                                ctypes.byref(ll), ctypes.byref(ev))
+    return {"states": states, "logw": logw, "ancestors": anc, "ll_inc": inc,
+            "loglik": ll.value, "events": ev.value, "status": st}
+
+
+def ssa_paths(prob, c, x0, t_start, t_end, n_paths, theta_id=0):
+    """n_paths independent direct-method SSA paths from x0 (no filtering)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    states = np.zeros((n_paths, prob.U), dtype=np.int32)
+    ev = np.zeros(n_paths, dtype=np.uint64)
+    st = lib().orc_ssa_paths(ctypes.byref(prob.c), c.ctypes.data, int(theta_id),
+                             x0.ctypes.data, float(t_start), float(t_end), int(n_paths),
+                             states.ctypes.data, ev.ctypes.data)
+    return states, ev, st

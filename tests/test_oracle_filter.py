@@ -1,0 +1,203 @@
+"""Pins of the oracle's particle filter (Supplementary I, Algorithm
+"Likelihood Approximation using particle filter").
+
+* special cases with closed forms: all rates zero (every particle stays at
+  x0, so the estimate equals the observation log-density exactly, for the
+  Gaussian and the log-normal model); one particle (no averaging, the
+  estimate is the log-density along the simulated path);
+* the trace of a filter: every log-likelihood increment equals the log of the
+  mean particle density computed by scipy, and every resampling step obeys
+  the systematic-resampling invariants for the previous weights;
+* the estimator against exact likelihoods: immigration-death (closed-form
+  transition kernel) and a small telegraph model (truncated CME) -- the
+  filter's likelihood estimate exp(l_hat) is unbiased (a property of the
+  bootstrap filter, Del Moral 2004), so its mean over independent streams
+  matches exp(l*) within the Monte-Carlo error;
+* statuses and reproducibility.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.special import logsumexp
+
+from paper_1606_08281_amd import workloads as W
+from tests.exact_lik import FSP, immigration_death_loglik
+
+
+def problem_from(orc, wl, theta=None, H=None, theta_ids=None, precision=0, event_cap=100_000_000,
+                 seed=None):
+    return orc.Problem(wl.net.orders, wl.net.stoich, wl.obs_kind, wl.observed, wl.sigma,
+                       wl.theta if theta is None else theta, wl.trajectories,
+                       H or wl.n_particles, wl.seed if seed is None else seed,
+                       precision=precision, event_cap=event_cap, theta_ids=theta_ids)
+
+
+def logdens(kind, sigma, y, x):
+    x = np.asarray(x, dtype=np.float64)
+    if kind == W.OBS_GAUSSIAN:
+        return stats.norm.logpdf(y, loc=x, scale=sigma)
+    with np.errstate(divide="ignore"):
+        out = np.where(x > 0, stats.lognorm.logpdf(y, s=sigma, scale=np.maximum(x, 1)), -np.inf)
+    return out
+
+
+def test_zero_rates_gaussian_exact(orc):
+    wl = W.immigration_death_workload(n_theta=1, n_particles=33)
+    tr = dict(wl.trajectories[0])
+    tr["x0"] = np.array([17], np.int32)
+    wl.trajectories = [tr]
+    P = problem_from(orc, wl, theta=np.zeros((1, 2)))
+    out = orc.evaluate(P)
+    want = stats.norm.logpdf(tr["y"][:, 0], loc=17, scale=2.0).sum()
+    assert out["status"][0] == 0
+    assert out["events"][0] == 0
+    assert abs(out["loglik"][0] - want) <= 1e-12 * abs(want)
+
+
+def test_zero_rates_lognormal_exact(orc):
+    wl = W.telegraph_workload(n_theta=1, n_traj=2, n_obs=6, n_particles=10)
+    P = problem_from(orc, wl, theta=np.zeros((1, 6)))
+    out = orc.evaluate(P)
+    want = 0.0
+    for tr in wl.trajectories:
+        want += stats.lognorm.logpdf(tr["y"][:, 0], s=0.1, scale=tr["x0"][3]).sum()
+    assert abs(out["loglik"][0] - want) <= 1e-12 * abs(want)
+
+
+def test_single_particle_is_path_density(orc):
+    wl = W.immigration_death_workload(n_theta=3, n_particles=1)
+    P = problem_from(orc, wl)
+    for i in range(3):
+        tr = orc.trace_filter(P, i, 0)
+        xs = tr["states"][:, 0, 0]
+        want = logdens(wl.obs_kind, wl.sigma, wl.trajectories[0]["y"][:, 0], xs).sum()
+        assert abs(tr["loglik"] - want) <= 1e-11 * max(1.0, abs(want))
+        assert np.all(tr["ancestors"] == 0)
+
+
+@pytest.mark.parametrize("which", ["immdeath", "telegraph"])
+def test_trace_increments_and_resampling(orc, which):
+    if which == "immdeath":
+        wl = W.immigration_death_workload(n_theta=4, n_particles=50)
+        theta = np.array([[10, 0.1], [3, 0.05], [40, 0.5], [1, 1]])
+    else:
+        wl = W.telegraph_workload(n_theta=2, n_traj=2, n_obs=12, n_particles=40)
+        theta = np.vstack([W.TELEGRAPH_TRUTH, W.TELEGRAPH_TRUTH * [2, 0.5, 1, 1, 0.5, 1]])
+    P = problem_from(orc, wl, theta=theta)
+    H = P.H
+    for i in range(theta.shape[0]):
+        for m in range(P.M):
+            tr = orc.trace_filter(P, i, m)
+            y = wl.trajectories[m]["y"][:, 0]
+            T = len(y)
+            total = 0.0
+            for t in range(T):
+                ld = logdens(wl.obs_kind, wl.sigma, y[t], tr["states"][t, :, wl.observed[0]])
+                if not np.isfinite(ld).any():
+                    assert tr["ll_inc"][t] == -np.inf
+                    total = -np.inf
+                    break
+                inc = logsumexp(ld) - math.log(H)
+                assert abs(tr["ll_inc"][t] - inc) <= 1e-10 * max(1.0, abs(inc))
+                total += tr["ll_inc"][t]
+                if t > 0:
+                    # ancestors used before interval t follow the weights of t-1
+                    lw = tr["logw"][t - 1]
+                    e = np.array([orc.exp(v - lw.max()) for v in lw])
+                    q = np.floor(e * 2.0**32)
+                    off = np.bincount(tr["ancestors"][t], minlength=H)
+                    assert off.sum() == H
+                    assert np.all(off >= np.floor(H * q / q.sum()))
+                    assert np.all(off <= np.ceil(H * q / q.sum()))
+                else:
+                    assert np.array_equal(tr["ancestors"][0], np.arange(H))
+            assert tr["loglik"] == total or abs(tr["loglik"] - total) <= 1e-12 * abs(total)
+
+
+def test_theta_ids_subset_reproduces_batch(orc):
+    wl = W.immigration_death_workload(n_theta=12, n_particles=64)
+    full = orc.evaluate(problem_from(orc, wl), want_final_state=True)
+    idx = [7, 2, 11]
+    sub = orc.evaluate(problem_from(orc, wl, theta=wl.theta[idx], theta_ids=idx),
+                       want_final_state=True)
+    assert np.array_equal(sub["loglik"], full["loglik"][idx])
+    assert np.array_equal(sub["events"], full["events"][idx])
+    assert np.array_equal(sub["final_state"], full["final_state"][idx])
+    # the thread count never changes a result
+    one = orc.evaluate(problem_from(orc, wl), nthreads=1)
+    assert np.array_equal(one["loglik"], full["loglik"])
+
+
+def test_statuses(orc):
+    wl = W.immigration_death_workload(n_theta=4, n_particles=16)
+    theta = np.array([[10, 0.1], [-1, 0.1], [np.nan, 1.0], [np.inf, 1.0]])
+    out = orc.evaluate(problem_from(orc, wl, theta=theta))
+    assert list(out["status"]) == [0, 3, 3, 3]
+    assert np.isfinite(out["loglik"][0]) and np.all(np.isnan(out["loglik"][1:]))
+    capped = orc.evaluate(problem_from(orc, wl, theta=theta[:1], event_cap=1))
+    assert capped["status"][0] == 1 and math.isnan(capped["loglik"][0])
+    # log-normal data, protein fixed at 0: every particle has zero density
+    tw = W.telegraph_workload(n_theta=1, n_traj=1, n_obs=3, n_particles=8)
+    tr = dict(tw.trajectories[0])
+    tr["x0"] = np.array([1, 0, 0, 0], np.int32)
+    tw.trajectories = [tr]
+    out = orc.evaluate(problem_from(orc, tw, theta=np.zeros((1, 6))))
+    assert out["status"][0] == 0 and out["loglik"][0] == -np.inf
+
+
+def _unbiased(lhat, lstar, k=4.0):
+    z = np.exp(lhat - lstar)
+    se = z.std(ddof=1) / math.sqrt(len(z))
+    return abs(z.mean() - 1.0) <= k * se + 1e-3, (z.mean(), se)
+
+
+@pytest.mark.parametrize("theta", [(10.0, 0.1), (12.0, 0.13), (9.0, 0.085)])
+def test_immigration_death_unbiased_vs_exact(orc, theta):
+    wl = W.immigration_death_workload(n_theta=1, n_particles=256)
+    tr = wl.trajectories[0]
+    lstar = immigration_death_loglik(theta[0], theta[1], 0, 0.0, tr["t_obs"], tr["y"][:, 0], 2.0)
+    R = 200
+    out = orc.evaluate(problem_from(orc, wl, theta=np.tile(theta, (R, 1))))
+    ok, info = _unbiased(out["loglik"], lstar)
+    assert ok, (lstar, info, out["loglik"].mean())
+    # the spread is that of a useful estimator, centred near the truth
+    assert abs(np.median(out["loglik"]) - lstar) < 3.0
+
+
+def test_immigration_death_consistent_in_h(orc):
+    # far from the data the bootstrap filter is biased low at small H; the
+    # bias must shrink towards the exact value as H grows
+    theta = (25.0, 0.3)
+    wl = W.immigration_death_workload(n_theta=1, n_particles=256)
+    tr = wl.trajectories[0]
+    lstar = immigration_death_loglik(theta[0], theta[1], 0, 0.0, tr["t_obs"], tr["y"][:, 0], 2.0)
+    gaps = []
+    for H in [64, 512, 4096]:
+        out = orc.evaluate(problem_from(orc, wl, theta=np.tile(theta, (24, 1)), H=H))
+        gaps.append(lstar - out["loglik"].mean())
+    assert gaps[0] > gaps[1] > gaps[2] > -0.5, gaps
+    assert gaps[2] < 2.0, gaps
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_telegraph_unbiased_vs_fsp(orc, precision):
+    net = W.telegraph()
+    c = np.array([0.5, 0.5, 2.0, 1.0, 1.0, 0.2])
+    x0 = np.array([1, 0, 2, 3], np.int32)
+    t_obs = np.arange(1.0, 9.0)
+    rng = np.random.default_rng(21)
+    path = W.first_reaction_path(net, c, x0, t_obs, rng)
+    p = np.maximum(path[:, 3], 1)
+    y = p * np.exp(rng.normal(0, 0.3, len(t_obs)))
+    fsp = FSP(net.orders, net.stoich, c, [1, 1, 14, 40])
+    lstar, lost = fsp.loglik(x0, 0.0, t_obs, y.reshape(-1, 1), 1, [3], 0.3)
+    assert lost < 1e-6
+    traj = {"t_obs": t_obs, "y": y.reshape(-1, 1), "t0": 0.0, "x0": x0}
+    R = 200
+    P = orc.Problem(net.orders, net.stoich, 1, [3], 0.3, np.tile(c, (R, 1)), [traj], 200, 9,
+                    precision=precision)
+    out = orc.evaluate(P)
+    ok, info = _unbiased(out["loglik"], lstar)
+    assert ok, (lstar, info)

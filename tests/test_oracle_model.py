@@ -1,0 +1,194 @@
+"""Pins of the oracle's model pieces against exact or closed-form results.
+
+* propensities: Gillespie's combinatorial mass action (0th, 1st, 2nd order,
+  homo- and hetero-dimeric) against exact integer combinatorics, one rounding.
+* systematic resampling: the defining properties (offspring counts within
+  floor/ceil of H w_i, total H, ancestors non-decreasing, expectation H w_i
+  over the offset), the degenerate cases (equal weights -> identity, one
+  non-zero weight -> all copies).
+* direct-method SSA: marginals against closed forms (immigration-death from 0
+  is Poisson, pure death is Binomial, a two-state switch has an explicit
+  occupation probability, pure immigration counts events as a Poisson
+  process) and against the truncated CME for second-order reactions;
+  conservation laws along paths.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from tests.exact_lik import FSP
+
+
+def _problem(orc, orders, stoich, **kw):
+    U = np.asarray(orders).shape[1]
+    traj = {"t_obs": [1.0], "y": [[1.0]], "t0": 0.0, "x0": np.zeros(U, np.int32)}
+    args = dict(obs_kind=0, observed=[0], sigma=1.0, theta=np.ones((1, len(orders))),
+                trajectories=[traj], n_particles=1, seed=kw.pop("seed", 5))
+    args.update(kw)
+    return orc.Problem(orders, stoich, **args)
+
+
+def test_propensity_mass_action_exact(orc):
+    # species A, B; reactions: 0 -> A, A -> 0, 2A -> B, A + B -> 0, B -> A
+    orders = [[0, 0], [1, 0], [2, 0], [1, 1], [0, 1]]
+    stoich = [[1, 0], [-1, 0], [-2, 1], [-1, -1], [1, -1]]
+    P = _problem(orc, orders, stoich)
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        x = [int(v) for v in rng.integers(0, 2**30, size=2)]
+        if rng.random() < 0.3:
+            x = [int(v) for v in rng.integers(0, 4, size=2)]
+        c = rng.uniform(0, 100, size=5) * 10.0 ** rng.integers(-6, 3, size=5)
+        got = orc.propensities(P, c, x)
+        h = [1, x[0], x[0] * (x[0] - 1) // 2, x[0] * x[1], x[1]]
+        for r in range(5):
+            # one rounding of the exact integer factor, one of the product
+            want = float(c[r]) * float(Fraction(h[r]))
+            assert got[r] == want, (r, x, got[r], want)
+        got32 = orc.propensities(P, c, x, precision=orc.FP32_MIXED)
+        for r in range(5):
+            want = float(np.float32(c[r]) * np.float32(float(h[r])))
+            assert got32[r] == want
+
+
+def _offspring(anc, H):
+    return np.bincount(anc, minlength=H)
+
+
+def test_resampling_invariants(orc):
+    rng = np.random.default_rng(8)
+    for trial in range(400):
+        H = int(rng.integers(1, 70))
+        lw = rng.normal(0, rng.choice([0.1, 3.0, 30.0]), size=H)
+        if trial % 5 == 0:
+            lw[rng.random(H) < 0.5] = -np.inf
+            lw[0] = 0.0
+        e = np.array([orc.exp(v - lw.max()) for v in lw])
+        w64 = int(rng.integers(0, 2**63)) * 2 + int(rng.integers(0, 2))
+        anc = orc.resample(e, w64)
+        assert np.all(np.diff(anc) >= 0)
+        assert anc.min() >= 0 and anc.max() < H
+        q = np.floor(e * 2.0**32)
+        Q = q.sum()
+        off = _offspring(anc, H)
+        assert off.sum() == H
+        lo = np.floor(H * q / Q)
+        hi = np.ceil(H * q / Q)
+        assert np.all(off >= lo) and np.all(off <= hi), (off, H * q / Q)
+        assert np.all(off[q == 0] == 0)
+
+
+def test_resampling_expectation_over_offset(orc):
+    # systematic resampling is unbiased: averaged over the uniform offset,
+    # particle i receives H w_i copies
+    H = 7
+    e = np.array([1.0, 0.3, 0.0, 0.05, 0.9, 0.5, 1e-3])
+    q = np.floor(e * 2.0**32)
+    want = H * q / q.sum()
+    n = 4000
+    acc = np.zeros(H)
+    for k in range(n):
+        w64 = (k * 2**64) // n + 12345
+        acc += _offspring(orc.resample(e, w64), H)
+    assert np.allclose(acc / n, want, atol=2e-3)
+
+
+def test_resampling_degenerate_cases(orc):
+    for H in [1, 2, 5, 64, 1000]:
+        e = np.ones(H)
+        for w64 in [0, 2**63, 2**64 - 1]:
+            assert np.array_equal(orc.resample(e, w64), np.arange(H))
+        one = np.zeros(H)
+        one[H // 2] = 1.0
+        assert np.all(orc.resample(one, 2**62) == H // 2)
+
+
+IMM_DEATH = ([[0], [1]], [[1], [-1]])
+
+
+@pytest.mark.parametrize("k1,k2,t", [(10.0, 0.1, 5.0), (3.0, 1.0, 2.5), (50.0, 2.0, 10.0)])
+def test_ssa_immigration_death_poisson(orc, k1, k2, t):
+    P = _problem(orc, *IMM_DEATH)
+    n = 20000
+    states, ev, st = orc.ssa_paths(P, [k1, k2], [0], 0.0, t, n, theta_id=int(k1))
+    assert st == 0
+    lam = k1 / k2 * (1 - math.exp(-k2 * t))
+    x = states[:, 0]
+    # chi-square against the Poisson law on bins with expected count >= 20
+    kmax = int(lam + 8 * math.sqrt(lam) + 10)
+    obs = np.bincount(np.minimum(x, kmax), minlength=kmax + 1).astype(float)
+    exp_ = stats.poisson.pmf(np.arange(kmax + 1), lam) * n
+    exp_[-1] += stats.poisson.sf(kmax, lam) * n
+    keep = exp_ >= 20
+    o = np.append(obs[keep], obs[~keep].sum())
+    ex = np.append(exp_[keep], exp_[~keep].sum())
+    chi2 = ((o - ex) ** 2 / np.maximum(ex, 1e-12)).sum()
+    p = stats.chi2.sf(chi2, len(o) - 1)
+    assert p > 1e-4, (chi2, p)
+
+
+def test_ssa_pure_death_binomial(orc):
+    P = _problem(orc, *IMM_DEATH)
+    n, x0, k2, t = 20000, 40, 0.3, 2.0
+    states, ev, st = orc.ssa_paths(P, [0.0, k2], [x0], 0.0, t, n)
+    x = states[:, 0]
+    p = math.exp(-k2 * t)
+    obs = np.bincount(x, minlength=x0 + 1).astype(float)
+    exp_ = stats.binom.pmf(np.arange(x0 + 1), x0, p) * n
+    keep = exp_ >= 20
+    o = np.append(obs[keep], obs[~keep].sum())
+    ex = np.append(exp_[keep], exp_[~keep].sum())
+    chi2 = ((o - ex) ** 2 / ex).sum()
+    assert stats.chi2.sf(chi2, len(o) - 1) > 1e-4
+    # every event is a death: events = x0 - x
+    assert np.array_equal(ev.astype(np.int64), x0 - x.astype(np.int64))
+
+
+def test_ssa_pure_immigration_event_count(orc):
+    P = _problem(orc, *IMM_DEATH)
+    n, k1, t = 20000, 7.0, 3.0
+    states, ev, st = orc.ssa_paths(P, [k1, 0.0], [0], 0.0, t, n)
+    assert np.array_equal(states[:, 0].astype(np.uint64), ev)
+    m, v = ev.mean(), ev.var()
+    se = math.sqrt(k1 * t / n)
+    assert abs(m - k1 * t) < 5 * se
+    assert abs(v / (k1 * t) - 1) < 0.05
+
+
+def test_ssa_telegraph_switch_and_conservation(orc):
+    from paper_1606_08281_amd.workloads import telegraph
+    net = telegraph()
+    P = _problem(orc, net.orders, net.stoich)
+    kon, koff, t = 0.7, 0.3, 1.5
+    c = [kon, koff, 5.0, 1.0, 2.0, 0.5]
+    n = 20000
+    states, ev, st = orc.ssa_paths(P, c, [1, 0, 0, 0], 0.0, t, n)
+    assert np.all(states.sum(axis=0) >= 0) and np.all(states >= 0)
+    assert np.all(states[:, 0] + states[:, 1] == 1)
+    p_on = kon / (kon + koff) * (1 - math.exp(-(kon + koff) * t))
+    frac = states[:, 1].mean()
+    assert abs(frac - p_on) < 5 * math.sqrt(p_on * (1 - p_on) / n)
+
+
+@pytest.mark.parametrize("case", ["dimer", "hetero"])
+def test_ssa_second_order_against_cme(orc, case):
+    if case == "dimer":   # 2A -> B, B -> 2A
+        orders, stoich, c, x0, bounds = [[2, 0], [0, 1]], [[-2, 1], [2, -1]], [0.05, 0.4], [20, 0], [20, 10]
+    else:                 # A + B -> C, C -> A + B
+        orders = [[1, 1, 0], [0, 0, 1]]
+        stoich = [[-1, -1, 1], [1, 1, -1]]
+        c, x0, bounds = [0.08, 0.5], [12, 9, 0], [12, 9, 9]
+    P = _problem(orc, orders, stoich)
+    t, n = 1.3, 20000
+    states, ev, st = orc.ssa_paths(P, c, x0, 0.0, t, n)
+    fsp = FSP(orders, stoich, c, bounds)
+    want = fsp.marginal(x0, t, 0) * n
+    obs = np.bincount(states[:, 0], minlength=len(want)).astype(float)[:len(want)]
+    keep = want >= 20
+    o = np.append(obs[keep], obs[~keep].sum())
+    ex = np.append(want[keep], want[~keep].sum())
+    chi2 = ((o - ex) ** 2 / ex).sum()
+    assert stats.chi2.sf(chi2, len(o) - 1) > 1e-4, chi2
