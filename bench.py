@@ -1,0 +1,175 @@
+"""Throughput of the particle-filter likelihood on one MI355X.
+
+A step is one lik_eval_batch_device call: the whole hot path (direct-method
+SSA propagation, observation weighting, log-sum-exp, systematic resampling,
+per-theta reduction) over the telegraph gene-expression batch: 1,024 rate
+vectors x 10 observed trajectories x 1,000 filter particles x 50 log-normal
+observations, binary64.  Inputs are resident in device memory before the
+timed region.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one wave64 instruction per SIMD per 4 cycles), in lane-operations/s.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def ops_per_event(R, U, precision):
+    """Algorithmic VALU issue slots one direct-method SSA event needs (lane
+    operations, quarter-rate instructions counted 4x).  The derivation is
+    itemised in the design notes; it is the count for the method's arithmetic,
+    independent of how the kernel realises it."""
+    if precision == 0:
+        philox = 10 * (2 * 4 + 2)       # 10 rounds: two 32x32->64 products, two 3-way xors
+        uniforms = 2 * 6                # 53-bit assembly, int->binary64, scale (two uniforms)
+        log = 7 + 12 + 3 + 10 + 5       # reduction, IEEE divide, squares, series, recombination
+        tau = 12                        # IEEE binary64 divide
+    else:
+        philox = (10 * (2 * 4 + 2)) / 2  # one block serves two events
+        uniforms = 2 * 3
+        log = 7 + 10 + 3 + 6 + 5
+        tau = 10
+    propensity = 3 * R                  # count -> float, times rate, running sum
+    select = 1 + 2 * (R - 1)            # target, compare + select per reaction
+    update = 2                          # species changed by one reaction (at most two here)
+    clock = 3                           # a0 > 0, clock + tau, compare
+    count = 2                           # event counter, cap test
+    return philox + uniforms + log + tau + propensity + select + update + clock + count
+
+
+def cpu_baseline(wl, budget_s=15.0, threads=16):
+    """Time the CPU oracle on a seeded random sample of theta (all
+    trajectories, full particle count and length), two theta per call."""
+    from oracle import oracle
+    rng = np.random.default_rng(7)
+    order = rng.permutation(wl.n_theta)
+    nthreads = min(threads, os.cpu_count() or 1)
+    done, t_total, events = [], 0.0, 0
+    k = 0
+    while t_total < budget_s and k < len(order):
+        idx = order[k:k + 2]
+        k += len(idx)
+        P = oracle.Problem(wl.net.orders, wl.net.stoich, wl.obs_kind, wl.observed, wl.sigma,
+                           wl.theta[idx], wl.trajectories, wl.n_particles, wl.seed,
+                           theta_ids=idx)
+        t0 = time.perf_counter()
+        out = oracle.evaluate(P, nthreads=nthreads)
+        t_total += time.perf_counter() - t0
+        events += int(out["events"].sum())
+        done += idx.tolist()
+    return {"value": len(done) / t_total, "unit": "likelihood evals/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{len(done)} theta of the same batch (seeded random pick: "
+                      f"{done}), all {wl.n_traj} trajectories, H={wl.n_particles}, "
+                      f"T={len(wl.trajectories[0]['t_obs'])}; {t_total:.1f} s wall, "
+                      f"{events / t_total:.3g} SSA events/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the likelihood path is built and timed on a "
+              "single MI355X (see the design notes for how it shards); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1606_08281_amd import lik
+    from paper_1606_08281_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.telegraph_workload()
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
+                         wl.n_particles, precision=args.precision)
+    theta = torch.from_numpy(wl.theta).cuda()
+    stream = torch.cuda.current_stream()
+    print(f"[bench] workload ready: {wl.n_theta} theta x {wl.n_traj} traj x "
+          f"{wl.n_particles} particles x {len(wl.trajectories[0]['t_obs'])} obs", flush=True,
+          file=sys.stderr)
+
+    for w in range(args.warmup):
+        db.run(theta, wl.seed, stream=stream)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", flush=True, file=sys.stderr)
+
+    lik.timing_read()
+    lik.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    events = 0
+    for k in range(args.steps):
+        db.run(theta, wl.seed + k, stream=stream)
+        events += int(db.events.sum().item())  # synchronises: counted per step
+        print(f"[bench] step {k + 1}/{args.steps} done", flush=True, file=sys.stderr)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lik.timing_enable(False)
+    tm = lik.timing_read()
+    status = db.status.cpu().numpy()
+
+    evals = wl.n_theta * args.steps
+    ope = ops_per_event(wl.net.R, wl.net.U, args.precision)
+    prop_s = tm["propagate_ms"] / 1e3
+    achieved = events * ope / prop_s / 1e12 if prop_s > 0 else None
+    peak = VALU_PEAK_LANE_OPS / 1e12
+    out = {
+        "metric": "likelihood evals/s",
+        "value": evals / elapsed,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32-mixed (f64 clock/weights)",
+        "data": "synthetic",
+        "config": {
+            "workload": "telegraph gene expression, 6 mass-action rates log-uniform over two "
+                        "decades; 1024 theta x 10 trajectories x 1000 filter particles x 50 "
+                        "log-normal observations (sigma 0.1)",
+            "n_theta": wl.n_theta, "n_traj": wl.n_traj, "n_particles": wl.n_particles,
+            "n_obs": len(wl.trajectories[0]["t_obs"]), "precision": args.precision,
+        },
+        "reaction_events_per_s": events / elapsed,
+        "events_per_step": events // args.steps,
+        "status_counts": {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+        "kernel_ms_per_step": {"propagate": tm["propagate_ms"] / args.steps,
+                               "weigh_resample": tm["weigh_ms"] / args.steps},
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
+            "frac": achieved / peak if achieved else None, "traffic": None,
+            "kernel": "k_propagate (direct-method SSA + log-weight)",
+            "ops_per_event": ope,
+            "avg_launch_ms": tm["propagate_ms"] / max(tm["propagate_launches"], 1),
+            "launches": tm["propagate_launches"],
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", flush=True, file=sys.stderr)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * lik.h -- C ABI of the MI355X particle-filter likelihood library (liblik.so).
+ *
+ * The library evaluates, for a batch of rate vectors theta, the bootstrap
+ * particle-filter estimate of log p(y | theta) for a stochastic mass-action
+ * reaction network observed through noisy measurements (Mikelson & Khammash,
+ * arXiv 1606.08281):
+ *   - network: U species, R reactions, reaction r consumes p_ru and produces
+ *     q_ru molecules of species u (Sec. "Chemical Reaction Networks");
+ *   - observations: Y ~ p(. | X, theta) at T time points of M trajectories
+ *     (Sec. "General Task");
+ *   - likelihood: product over trajectories and time points, each factor the
+ *     mean particle weight (Supplementary I, the recursion and the Algorithm
+ *     "Likelihood Approximation using particle filter");
+ *   - propagation: Gillespie's direct-method SSA between observation times.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - propensity a_r = c_r * prod_u C(x_u, p_ru) (Gillespie's combinatorial
+ *     mass-action form); theta[r] = c_r, so the parameter dimension is R;
+ *   - resampling before every propagation step after the first, systematic,
+ *     with integer (2^-32 fixed-point) weights;
+ *   - random numbers from Philox4x32-10 keyed by the seed, with counters made
+ *     of (event index, particle slot, (trajectory << 16) | interval,
+ *     (theta id << 2) | purpose); results depend only on the inputs, the seed
+ *     and the theta ids, never on batch composition or launch shape;
+ *   - log-likelihoods are natural logs in binary64; -inf is a valid result
+ *     (every particle has zero density under the noise model).
+ *
+ * Errors: every entry point returns LIK_OK (0) or a negative LIK_E* code and
+ * then lik_last_error() (thread-local) describes the failure.  Per-theta
+ * outcomes are not call errors: they are reported in status_out.
+ *
+ * Ownership: the caller owns every buffer it passes.  Entry points copy what
+ * they keep (network tables).  Handles are immutable after creation and may
+ * be shared by threads.
+ */
+#ifndef LIK_H
+#define LIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define LIK_OK 0
+#define LIK_EINVAL (-1)
+#define LIK_ENOMEM (-2)
+#define LIK_EDEVICE (-3)
+#define LIK_EUNSUPPORTED (-4)
+
+/* per-theta status (status_out) */
+#define LIK_STATUS_OK 0
+#define LIK_STATUS_EVENT_CAP 1      /* a particle needed more events in one interval than the cap */
+#define LIK_STATUS_COUNT_OVERFLOW 2 /* a count exceeded 2^30 at the end of an interval */
+#define LIK_STATUS_BAD_THETA 3      /* a rate was negative, infinite or NaN */
+
+/* observation noise models (Sec. "General Task": Y ~ p(. | X, theta)) */
+#define LIK_OBS_GAUSSIAN 0  /* y = x_s + N(0, sigma^2) per observed species s */
+#define LIK_OBS_LOGNORMAL 1 /* log y = log x_s + N(0, sigma^2); y > 0 required */
+
+/* arithmetic of the SSA step */
+#define LIK_FP64 0       /* binary64 propensities, event times and clock */
+#define LIK_FP32_MIXED 1 /* binary32 propensities / event times, binary64 clock and weights */
+
+/* limits */
+#define LIK_MAX_SPECIES 32
+#define LIK_MAX_REACTIONS 64
+#define LIK_MAX_OBSERVED 8
+#define LIK_MAX_PARTICLES 4096
+#define LIK_MAX_OBS_PER_TRAJ 65535
+#define LIK_MAX_TRAJ 65535
+#define LIK_MAX_EVENT_CAP 134217728ull /* 2^27 events per particle per interval */
+#define LIK_DEFAULT_EVENT_CAP 100000000ull
+
+typedef struct lik_network *lik_network_t;
+
+/*
+ * lik_create_network -- validate and copy a reaction network (Sec. "Chemical
+ * Reaction Networks").
+ *   n_species U in [1, LIK_MAX_SPECIES], n_reactions R in [1, LIK_MAX_REACTIONS].
+ *   reactant_orders [R*U], row-major by reaction: p_ru >= 0, sum_u p_ru <= 2
+ *     (mass action of order 0, 1 or 2).
+ *   stoichiometry [R*U], row-major by reaction: net change nu_ru = q_ru - p_ru,
+ *     with nu_ru >= -p_ru (no reaction consumes what it does not use) and
+ *     |nu_ru| <= 7.
+ *   out: receives the handle.  Host pointers; the arrays are copied.
+ * Returns LIK_EINVAL on any violated rule, LIK_ENOMEM on allocation failure.
+ */
+int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *reactant_orders,
+                       const int32_t *stoichiometry, lik_network_t *out);
+
+/* Releases a handle.  The caller guarantees no evaluation using it is in flight. */
+int lik_destroy_network(lik_network_t net);
+
+/* Observation model: kind, observed species (in order) and noise scale sigma > 0. */
+typedef struct lik_obs_model {
+    int32_t kind;
+    int32_t n_observed;                 /* P in [1, LIK_MAX_OBSERVED] */
+    int32_t species[LIK_MAX_OBSERVED];  /* species index of observed component k */
+    double sigma;
+} lik_obs_model;
+
+/*
+ * Observed trajectories (Sec. "General Task": y_t^m for m < M, t < T_m).
+ * Trajectory m owns observations obs_offsets[m] .. obs_offsets[m+1]-1.
+ *   obs_offsets [M+1] int32, non-decreasing, obs_offsets[0] = 0, T_m >= 1;
+ *   t_obs [total] binary64 observation times, strictly increasing within a
+ *     trajectory and > t0[m];
+ *   y [total * P] binary64 observed values, component k of observation n at
+ *     y[n*P + k];
+ *   t0 [M] start times; x0 [M*U] int32 known initial counts (>= 0, <= 2^30).
+ * Whether these are host or device pointers is fixed by the entry point.
+ */
+typedef struct lik_data {
+    int32_t n_traj;
+    const int32_t *obs_offsets;
+    const double *t_obs;
+    const double *y;
+    const double *t0;
+    const int32_t *x0;
+} lik_data;
+
+/* Evaluation options; a NULL pointer means all defaults. */
+typedef struct lik_eval_opts {
+    int32_t precision;          /* LIK_FP64 (default) or LIK_FP32_MIXED */
+    int32_t reserved;           /* must be 0 */
+    uint64_t event_cap;         /* per particle per interval; 0 = LIK_DEFAULT_EVENT_CAP */
+    const uint32_t *theta_ids;  /* [n_theta] random-stream ids (< 2^30), NULL = 0..n_theta-1;
+                                   same memory space as theta */
+} lik_eval_opts;
+
+/* Optional per-filter outputs (filter f = theta index i * M + trajectory m);
+ * any pointer may be NULL.  Same memory space as loglik_out. */
+typedef struct lik_aux {
+    uint64_t *filter_events;    /* [n_theta*M] SSA events applied */
+    double *filter_loglik;      /* [n_theta*M] log-likelihood of each filter */
+    int32_t *final_state;       /* [n_theta*M][U][H] counts after the last interval run */
+} lik_aux;
+
+/*
+ * lik_eval_batch -- log-likelihood of every theta against all M trajectories
+ * (Supplementary I: log p(y | theta) = sum_m log p(y^m | theta)), with
+ * n_particles filter particles per (theta, trajectory) pair.  Synchronous.
+ *   theta [n_theta * R] host, rate constants c_r per theta (row-major).
+ *   data: host pointers.
+ *   loglik_out [n_theta] host: the estimate, -inf if some filter had every
+ *     particle at zero density, NaN when status is not LIK_STATUS_OK.
+ *   status_out [n_theta] host or NULL.
+ *   aux: host pointers or NULL.
+ * The library allocates and frees its device memory internally.
+ */
+int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
+                   int32_t n_theta, const double *theta, const lik_data *data,
+                   int32_t n_particles, uint64_t seed, double *loglik_out,
+                   int32_t *status_out, const lik_aux *aux);
+
+/*
+ * lik_workspace_size -- bytes of device workspace lik_eval_batch_device needs.
+ */
+size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
+                          int32_t n_particles);
+
+/*
+ * lik_eval_batch_device -- the same computation on device-resident buffers,
+ * enqueued on `stream` (a hipStream_t; NULL = the default stream).  Returns
+ * after enqueueing; results are valid when the stream reaches them.
+ *   theta, data (all arrays), opts->theta_ids, loglik_out, status_out (may be
+ *   NULL) and aux arrays are DEVICE pointers.
+ *   obs_offsets_host [M+1]: a host copy of data->obs_offsets, used to plan
+ *   the launches.
+ *   workspace: device memory of at least lik_workspace_size(...) bytes,
+ *   256-byte aligned, not used by anything else until the stream has passed
+ *   this call.
+ * Invalid theta values are reported per theta (LIK_STATUS_BAD_THETA);
+ * observation values are not inspected on the host in this entry point.
+ */
+int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs,
+                          const lik_eval_opts *opts, int32_t n_theta, const double *theta,
+                          const lik_data *data, const int32_t *obs_offsets_host,
+                          int32_t n_particles, uint64_t seed, double *loglik_out,
+                          int32_t *status_out, const lik_aux *aux, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/*
+ * Kernel timing for measurement tools.  While enabled, every propagation
+ * launch and every weighting/resampling launch is bracketed by HIP events
+ * recorded on the stream it is enqueued on.  lik_timing_read waits for the
+ * recorded events, returns the summed kernel durations and launch counts
+ * since the previous read, and releases the events.  Process-global, not
+ * thread-safe: for single-threaded benchmark drivers.
+ */
+typedef struct lik_timing {
+    double propagate_ms;        /* summed duration of SSA propagation launches */
+    int64_t propagate_launches;
+    double weigh_ms;            /* summed duration of weight/resampling launches */
+    int64_t weigh_launches;
+} lik_timing;
+
+int lik_timing_enable(int enable);
+int lik_timing_read(lik_timing *out);
+
+/* Thread-local description of the last error returned on this thread. */
+const char *lik_last_error(void);
+
+/* Library version string. */
+const char *lik_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIK_H */

@@ -1,0 +1,137 @@
+// devmath.hpp -- device-side random streams and elementary functions.
+//
+// Every decision of the particle filter (when an interval ends, which
+// reaction fires, which ancestor a slot takes) depends on these values, so
+// they are built only from correctly rounded IEEE-754 operations (+ - * /,
+// fma, exact scalings) in a fixed order.  The library is compiled with
+// -ffp-contract=off; fused multiply-adds appear only where written.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lik {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round two
+// 32x32->64-bit products, the high halves xor'ed with the other words and
+// the round key; the key advances by the Weyl constants between rounds.
+struct Block4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
+// ln 2 split: 32 leading significant bits (so e * LN2_HI is exact for any
+// binary64 exponent) and the binary64 nearest to the remainder.
+constexpr double kLn2Hi = 0x1.62e42feep-1;
+constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+constexpr double kHalfSqrt2 = 0x1.6a09e667f3bcdp-1;  // (nearest sqrt 2) / 2, exact halving
+
+// Natural logarithm of x > 0 (x = 0 -> -inf).  Reduction x = 2^e m,
+// m in [sqrt(1/2), sqrt(2)]; with f = m - 1 and s = f / (2 + f),
+// log m = 2 atanh s = t + t z Q(z), t = 2s, z = s^2,
+// Q(z) = 1/3 + z/5 + ... + z^9/21; log x = e ln2_hi + (e ln2_lo + log m).
+__device__ __forceinline__ double dlog(double x) {
+    if (x == 0.0) return -__builtin_inf();
+    const double mant = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1), exact, subnormals too
+    int e = __builtin_amdgcn_frexp_exp(x);
+    double m;
+    if (mant > kHalfSqrt2) {
+        m = mant;
+    } else {
+        m = mant * 2.0;
+        e = e - 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double q = 1.0 / 21.0;
+    q = __builtin_fma(q, z, 1.0 / 19.0);
+    q = __builtin_fma(q, z, 1.0 / 17.0);
+    q = __builtin_fma(q, z, 1.0 / 15.0);
+    q = __builtin_fma(q, z, 1.0 / 13.0);
+    q = __builtin_fma(q, z, 1.0 / 11.0);
+    q = __builtin_fma(q, z, 1.0 / 9.0);
+    q = __builtin_fma(q, z, 1.0 / 7.0);
+    q = __builtin_fma(q, z, 1.0 / 5.0);
+    q = __builtin_fma(q, z, 1.0 / 3.0);
+    const double t = 2.0 * s;
+    const double w = t * z;
+    const double lm = __builtin_fma(w, q, t);
+    const double ed = (double)e;
+    return ed * kLn2Hi + (ed * kLn2Lo + lm);
+}
+
+// exp(d) for d <= 0 (d < -708 or -inf -> 0): k = floor(d/ln2 + 1/2),
+// r = (d - k ln2_hi) - k ln2_lo, exp r = sum_{i<=13} r^i / i! (Horner),
+// result exp(r) 2^k (always a normal number in this range).
+__device__ __forceinline__ double dexp_nonpos(double d) {
+    if (!(d >= -708.0)) return 0.0;
+    const double kd = __builtin_floor(d * kInvLn2 + 0.5);
+    const double r = (d - kd * kLn2Hi) - kd * kLn2Lo;
+    double p = 1.0 / 6227020800.0;  // 1/13!
+    p = __builtin_fma(p, r, 1.0 / 479001600.0);
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 1.0 / 2.0);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)kd);
+}
+
+// binary32 logarithm (FP32-mixed event times): the same reduction, series
+// to z^4/11, ln 2 split as 16 significant bits + remainder.
+constexpr float kLn2HiF = 0x1.62e4p-1f;
+constexpr float kLn2LoF = 0x1.7f7d1cp-20f;
+constexpr float kHalfSqrt2F = 0x1.6a09e6p-1f;
+
+__device__ __forceinline__ float flog(float x) {
+    if (x == 0.0f) return -__builtin_inff();
+    const float mant = __builtin_amdgcn_frexp_mantf(x);
+    int e = __builtin_amdgcn_frexp_expf(x);
+    float m;
+    if (mant > kHalfSqrt2F) {
+        m = mant;
+    } else {
+        m = mant * 2.0f;
+        e = e - 1;
+    }
+    const float f = m - 1.0f;
+    const float s = f / (2.0f + f);
+    const float z = s * s;
+    float q = 1.0f / 11.0f;
+    q = __builtin_fmaf(q, z, 1.0f / 9.0f);
+    q = __builtin_fmaf(q, z, 1.0f / 7.0f);
+    q = __builtin_fmaf(q, z, 1.0f / 5.0f);
+    q = __builtin_fmaf(q, z, 1.0f / 3.0f);
+    const float t = 2.0f * s;
+    const float w = t * z;
+    const float lm = __builtin_fmaf(w, q, t);
+    const float ef = (float)e;
+    return ef * kLn2HiF + (ef * kLn2LoF + lm);
+}
+
+}  // namespace lik

@@ -1,0 +1,241 @@
+"""ctypes binding of liblik.so (include/lik.h): argument marshalling only.
+
+Every step of the likelihood runs in the library's HIP kernels.  There is no
+fallback: if the library or a GPU is missing, calls raise.  PyTorch is used
+only to hold device buffers and to name the stream work is enqueued on.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblik.so")
+
+LIK_OK, LIK_EINVAL, LIK_ENOMEM, LIK_EDEVICE, LIK_EUNSUPPORTED = 0, -1, -2, -3, -4
+STATUS_OK, STATUS_EVENT_CAP, STATUS_COUNT_OVERFLOW, STATUS_BAD_THETA = 0, 1, 2, 3
+OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
+FP64, FP32_MIXED = 0, 1
+MAX_OBSERVED = 8
+
+EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_eval_batch",
+            "lik_workspace_size", "lik_eval_batch_device", "lik_timing_enable",
+            "lik_timing_read", "lik_last_error", "lik_version"]
+
+
+class LikError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblik error {code}: {msg}")
+        self.code = code
+
+
+class ObsModel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_observed", ctypes.c_int32),
+                ("species", ctypes.c_int32 * MAX_OBSERVED), ("sigma", ctypes.c_double)]
+
+
+class Data(ctypes.Structure):
+    _fields_ = [("n_traj", ctypes.c_int32), ("obs_offsets", ctypes.c_void_p),
+                ("t_obs", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t0", ctypes.c_void_p),
+                ("x0", ctypes.c_void_p)]
+
+
+class EvalOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("event_cap", ctypes.c_uint64), ("theta_ids", ctypes.c_void_p)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("propagate_ms", ctypes.c_double), ("propagate_launches", ctypes.c_int64),
+                ("weigh_ms", ctypes.c_double), ("weigh_launches", ctypes.c_int64)]
+
+
+class Aux(ctypes.Structure):
+    _fields_ = [("filter_events", ctypes.c_void_p), ("filter_loglik", ctypes.c_void_p),
+                ("final_state", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblik.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1606_08281_amd.build`")
+        # liblik is linked against the HIP runtime bundled with PyTorch-ROCm.
+        # Loading torch first makes the dynamic loader resolve liblik's HIP
+        # dependency to that same, already loaded copy, so the process has one
+        # HIP runtime shared by torch's allocator/streams and our kernels.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
+        L.lik_create_network.argtypes = [i32, i32, vp, vp, ctypes.POINTER(vp)]
+        L.lik_create_network.restype = ctypes.c_int
+        L.lik_destroy_network.argtypes = [vp]
+        L.lik_destroy_network.restype = ctypes.c_int
+        L.lik_eval_batch.argtypes = [vp, vp, vp, i32, vp, vp, i32, u64, vp, vp, vp]
+        L.lik_eval_batch.restype = ctypes.c_int
+        L.lik_workspace_size.argtypes = [vp, i32, i32, i32]
+        L.lik_workspace_size.restype = sz
+        L.lik_eval_batch_device.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, u64, vp, vp, vp,
+                                            vp, sz, vp]
+        L.lik_eval_batch_device.restype = ctypes.c_int
+        L.lik_timing_enable.argtypes = [ctypes.c_int]
+        L.lik_timing_enable.restype = ctypes.c_int
+        L.lik_timing_read.argtypes = [vp]
+        L.lik_timing_read.restype = ctypes.c_int
+        L.lik_last_error.restype = ctypes.c_char_p
+        L.lik_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != LIK_OK:
+        raise LikError(rc, lib().lik_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def timing_enable(on=True):
+    _check(lib().lik_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """Summed kernel durations (ms) and launch counts since the last read."""
+    t = Timing()
+    _check(lib().lik_timing_read(ctypes.byref(t)))
+    return {"propagate_ms": t.propagate_ms, "propagate_launches": t.propagate_launches,
+            "weigh_ms": t.weigh_ms, "weigh_launches": t.weigh_launches}
+
+
+class Network:
+    """A validated reaction network (reactant orders p_ru, net changes nu_ru)."""
+
+    def __init__(self, reactant_orders, stoichiometry):
+        self.orders = np.ascontiguousarray(reactant_orders, dtype=np.int32)
+        self.stoich = np.ascontiguousarray(stoichiometry, dtype=np.int32)
+        self.R, self.U = self.orders.shape
+        h = ctypes.c_void_p()
+        _check(lib().lik_create_network(self.U, self.R, self.orders.ctypes.data,
+                                        self.stoich.ctypes.data, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.lik_destroy_network(h)
+            self.handle = None
+
+
+def obs_model(kind, observed, sigma):
+    o = ObsModel()
+    o.kind = int(kind)
+    o.n_observed = len(observed)
+    for k, s in enumerate(observed):
+        o.species[k] = int(s)
+    o.sigma = float(sigma)
+    return o
+
+
+def pack_trajectories(trajectories, P):
+    offs = [0]
+    for tr in trajectories:
+        offs.append(offs[-1] + len(tr["t_obs"]))
+    return {
+        "obs_offsets": np.array(offs, dtype=np.int32),
+        "t_obs": np.ascontiguousarray(np.concatenate([np.asarray(tr["t_obs"], np.float64)
+                                                      for tr in trajectories])),
+        "y": np.ascontiguousarray(np.concatenate([np.asarray(tr["y"], np.float64).reshape(-1, P)
+                                                  for tr in trajectories])),
+        "t0": np.array([float(tr.get("t0", 0.0)) for tr in trajectories], dtype=np.float64),
+        "x0": np.ascontiguousarray(np.stack([np.asarray(tr["x0"], np.int32)
+                                             for tr in trajectories])),
+    }
+
+
+def eval_batch(net, obs_kind, observed, sigma, theta, trajectories, n_particles, seed,
+               precision=FP64, event_cap=0, theta_ids=None, aux=False):
+    """Host-pointer entry point lik_eval_batch.  Returns a dict with loglik
+    [n_theta], status [n_theta] and, if aux, filter_events, filter_loglik
+    [n_theta*M] and final_state [n_theta*M, U, H]."""
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, net.R))
+    n_theta = theta.shape[0]
+    P = len(observed)
+    d = pack_trajectories(trajectories, P)
+    M = len(trajectories)
+    data = Data(M, _ptr(d["obs_offsets"]), _ptr(d["t_obs"]), _ptr(d["y"]), _ptr(d["t0"]),
+                _ptr(d["x0"]))
+    ids = None if theta_ids is None else np.ascontiguousarray(theta_ids, dtype=np.uint32)
+    opts = EvalOpts(int(precision), 0, int(event_cap), _ptr(ids))
+    om = obs_model(obs_kind, observed, sigma)
+    ll = np.zeros(n_theta, dtype=np.float64)
+    st = np.zeros(n_theta, dtype=np.int32)
+    out = {"loglik": ll, "status": st}
+    aux_s = None
+    if aux:
+        F = n_theta * M
+        out["filter_events"] = np.zeros(F, dtype=np.uint64)
+        out["filter_loglik"] = np.zeros(F, dtype=np.float64)
+        out["final_state"] = np.zeros((F, net.U, int(n_particles)), dtype=np.int32)
+        aux_s = Aux(_ptr(out["filter_events"]), _ptr(out["filter_loglik"]),
+                    _ptr(out["final_state"]))
+    _check(lib().lik_eval_batch(net.handle, ctypes.byref(om), ctypes.byref(opts), n_theta,
+                                theta.ctypes.data, ctypes.byref(data), int(n_particles),
+                                int(seed) & (2**64 - 1), ll.ctypes.data, st.ctypes.data,
+                                None if aux_s is None else ctypes.byref(aux_s)))
+    return out
+
+
+class DeviceBatch:
+    """Device-resident inputs + workspace for repeated lik_eval_batch_device
+    calls (torch tensors on the current CUDA/HIP device)."""
+
+    def __init__(self, net, obs_kind, observed, sigma, trajectories, n_theta, n_particles,
+                 precision=FP64, event_cap=0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.net = net
+        self.P = len(observed)
+        d = pack_trajectories(trajectories, self.P)
+        self.offsets_host = d["obs_offsets"]
+        self.dev = {k: torch.from_numpy(v).to(device) for k, v in d.items()}
+        self.M = len(trajectories)
+        self.n_theta = int(n_theta)
+        self.H = int(n_particles)
+        self.om = obs_model(obs_kind, observed, sigma)
+        self.precision = int(precision)
+        self.event_cap = int(event_cap)
+        self.data = Data(self.M, self.dev["obs_offsets"].data_ptr(), self.dev["t_obs"].data_ptr(),
+                         self.dev["y"].data_ptr(), self.dev["t0"].data_ptr(),
+                         self.dev["x0"].data_ptr())
+        self.ws_bytes = int(lib().lik_workspace_size(net.handle, self.n_theta, self.M, self.H))
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        self.loglik = torch.empty(self.n_theta, dtype=torch.float64, device=device)
+        self.status = torch.empty(self.n_theta, dtype=torch.int32, device=device)
+        F = self.n_theta * self.M
+        self.events = torch.empty(F, dtype=torch.int64, device=device)
+        self.filter_loglik = torch.empty(F, dtype=torch.float64, device=device)
+
+    def run(self, theta_dev, seed, theta_ids_dev=None, stream=None, final_state=None):
+        """Enqueue one evaluation on `stream` (default: torch's current stream)."""
+        torch = self.torch
+        assert theta_dev.dtype == torch.float64 and theta_dev.is_contiguous()
+        assert theta_dev.numel() == self.n_theta * self.net.R
+        s = stream if stream is not None else torch.cuda.current_stream()
+        opts = EvalOpts(self.precision, 0, self.event_cap,
+                        None if theta_ids_dev is None else theta_ids_dev.data_ptr())
+        aux = Aux(self.events.data_ptr(), self.filter_loglik.data_ptr(),
+                  None if final_state is None else final_state.data_ptr())
+        ws = self.workspace.data_ptr()
+        _check(lib().lik_eval_batch_device(
+            self.net.handle, ctypes.byref(self.om), ctypes.byref(opts), self.n_theta,
+            theta_dev.data_ptr(), ctypes.byref(self.data), self.offsets_host.ctypes.data,
+            self.H, int(seed) & (2**64 - 1), self.loglik.data_ptr(), self.status.data_ptr(),
+            ctypes.byref(aux), ws, self.ws_bytes + 256, ctypes.c_void_p(s.cuda_stream)))
+        return self.loglik, self.status

@@ -189,3 +189,87 @@ def telegraph_workload(n_theta=1024, n_traj=10, n_obs=50, n_particles=1000, dt=2
                         TELEGRAPH_TRUTH / 10.0, TELEGRAPH_TRUTH * 10.0, n_theta)
     return Workload("telegraph", net, OBS_LOGNORMAL, [3], 0.1, theta, trajs,
                     n_particles, truth=TELEGRAPH_TRUTH)
+
+
+def random_network(n_species=20, n_reactions=40, seed=SEED_NET):
+    """Seeded random mass-action network: orders 0-2, net changes in -2..2,
+    net change >= -order for every reactant (nothing consumed that is not
+    used), zeroth-order reactions only create, and every reaction of order
+    >= 1 conserves or destroys molecules overall (no autocatalytic blow-up)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U, R = n_species, n_reactions
+    orders = np.zeros((R, U), dtype=np.int32)
+    stoich = np.zeros((R, U), dtype=np.int32)
+    for r in range(R):
+        order = int(rng.choice([0, 1, 1, 1, 2, 2])) if r >= 4 else (0 if r < 2 else 1)
+        if order == 1:
+            orders[r, rng.integers(U)] = 1
+        elif order == 2:
+            if rng.random() < 0.3:
+                orders[r, rng.integers(U)] = 2
+            else:
+                a, b = rng.choice(U, size=2, replace=False)
+                orders[r, a] = orders[r, b] = 1
+        while True:
+            nu = np.zeros(U, dtype=np.int32)
+            for u in np.nonzero(orders[r])[0]:
+                nu[u] = -rng.integers(0, orders[r, u] + 1)   # consume some of each reactant
+            for _ in range(int(rng.integers(1, 3))):           # and produce one or two species
+                nu[rng.integers(U)] += int(rng.integers(1, 3))
+            nu = np.clip(nu, -2, 2)
+            nu = np.maximum(nu, -orders[r])
+            if order == 0 and (nu < 0).any():
+                continue
+            if order >= 1 and nu.sum() > 0:
+                continue
+            if not nu.any():
+                continue
+            break
+        stoich[r] = nu
+    # every species needs a way out, otherwise zeroth-order inflow accumulates
+    for u in range(U):
+        if not ((stoich[:, u] < 0)).any():
+            r = 4 + u % (R - 4)
+            orders[r] = 0
+            orders[r, u] = 1
+            stoich[r] = 0
+            stoich[r, u] = -1
+    return Network("random-20x40", [f"S{u}" for u in range(U)], orders, stoich)
+
+
+def tau_leap_path(net, c, x0, t_points, rng, n_sub=200):
+    """Approximate path for synthetic data only: Poisson tau-leaping with
+    n_sub sub-steps per observation interval, counts clipped at zero."""
+    x = np.array(x0, dtype=np.int64)
+    out = np.zeros((len(t_points), net.U), dtype=np.int64)
+    t_prev = 0.0
+    for k, t in enumerate(t_points):
+        tau = (t - t_prev) / n_sub
+        for _ in range(n_sub):
+            a = c * net.propensity_factor(x)
+            fires = rng.poisson(np.maximum(a, 0.0) * tau)
+            x = np.maximum(x + fires @ net.stoich, 0)
+        out[k] = x
+        t_prev = t
+    return out
+
+
+def random_network_workload(n_theta=4096, n_particles=512, n_obs=100, events_per_interval=1e4):
+    """20 species / 40 reactions, x0 ~ Poisson(100) once, rates log-uniform on
+    [1e-3, 1]; the observation interval is set so that the median over the
+    drawn rate vectors of the total propensity at x0 times the interval is
+    `events_per_interval`; Gaussian noise sigma 10 on species 0 and 1."""
+    net = random_network()
+    x0 = np.random.Generator(np.random.PCG64(SEED_NET + 100)).poisson(100, net.U).astype(np.int32)
+    theta = log_uniform(np.random.Generator(np.random.PCG64(SEED_THETA)),
+                        np.full(net.R, 1e-3), np.full(net.R, 1.0), n_theta)
+    a0 = np.array([(th * net.propensity_factor(x0)).sum() for th in theta])
+    dt = float(events_per_interval / np.median(a0))
+    t_obs = dt * np.arange(1, n_obs + 1, dtype=np.float64)
+    truth = np.full(net.R, 10 ** -1.5)
+    rng = np.random.Generator(np.random.PCG64(SEED_DATA))
+    states = tau_leap_path(net, truth, x0, t_obs, rng, n_sub=20)
+    y = states[:, :2] + np.random.Generator(np.random.PCG64(SEED_NOISE)).normal(0, 10.0, (n_obs, 2))
+    traj = {"t_obs": t_obs, "y": y, "t0": 0.0, "x0": x0, "x_true": states}
+    return Workload("random-20x40", net, OBS_GAUSSIAN, [0, 1], 10.0, theta, [traj],
+                    n_particles, truth=truth)

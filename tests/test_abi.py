@@ -1,0 +1,106 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/lik.h declares, and rejects invalid networks and arguments on the
+host before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1606_08281_amd import lik
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lik.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*(lik_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = lik.lib()
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lik.EXPORTED)
+    assert lik.lib().lik_version().startswith(b"lik")
+
+
+def test_compiled_for_gfx950_only():
+    # the device code in the library is built for gfx950
+    data = open(lik.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+@pytest.mark.parametrize("orders,stoich,code", [
+    ([[3]], [[-1]], lik.LIK_EINVAL),          # order 3
+    ([[1, 1]], [[-1, -2]], lik.LIK_EINVAL),   # consumes more than it uses
+    ([[-1]], [[1]], lik.LIK_EINVAL),          # negative order
+    ([[0]], [[9]], lik.LIK_EUNSUPPORTED),     # |net change| > 7
+    ([[2, 0]], [[-2, 1]], lik.LIK_OK),        # dimerisation
+    ([[1, 1]], [[-1, -1]], lik.LIK_OK),       # hetero second order
+])
+def test_network_validation(orders, stoich, code):
+    if code == lik.LIK_OK:
+        net = lik.Network(orders, stoich)
+        assert net.U == len(orders[0])
+    else:
+        with pytest.raises(lik.LikError) as e:
+            lik.Network(orders, stoich)
+        assert e.value.code == code
+
+
+def test_network_size_limits():
+    with pytest.raises(lik.LikError):
+        lik.Network(np.zeros((65, 1)), np.zeros((65, 1)))
+    with pytest.raises(lik.LikError):
+        lik.Network(np.zeros((1, 33)), np.zeros((1, 33)))
+    lik.Network(np.zeros((64, 32)), np.zeros((64, 32)))
+
+
+def _args(**kw):
+    from paper_1606_08281_amd import workloads as W
+    wl = W.immigration_death_workload(n_theta=2, n_particles=8)
+    a = dict(obs_kind=0, observed=[0], sigma=2.0, theta=wl.theta,
+             trajectories=wl.trajectories, n_particles=8, seed=1)
+    a.update(kw)
+    return wl, a
+
+
+@pytest.mark.parametrize("bad", [
+    dict(sigma=0.0), dict(sigma=-1.0), dict(observed=[1]), dict(obs_kind=7),
+    dict(n_particles=0), dict(n_particles=4097), dict(precision=5),
+])
+def test_host_validation_rejects_before_device_work(bad):
+    wl, a = _args(**bad)
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    with pytest.raises(lik.LikError) as e:
+        lik.eval_batch(net, **a)
+    assert e.value.code == lik.LIK_EINVAL
+
+
+def test_observation_checks():
+    wl, a = _args()
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    tr = dict(wl.trajectories[0])
+    tr["t_obs"] = tr["t_obs"][::-1].copy()
+    with pytest.raises(lik.LikError):
+        lik.eval_batch(net, **dict(a, trajectories=[tr]))
+    tr = dict(wl.trajectories[0])
+    tr["y"] = -np.abs(tr["y"])
+    with pytest.raises(lik.LikError):   # log-normal needs y > 0
+        lik.eval_batch(net, **dict(a, trajectories=[tr], obs_kind=1))
+    tr = dict(wl.trajectories[0])
+    tr["x0"] = np.array([-1], np.int32)
+    with pytest.raises(lik.LikError):
+        lik.eval_batch(net, **dict(a, trajectories=[tr]))
+
+
+def test_empty_batch_is_ok_without_device():
+    wl, a = _args(theta=np.zeros((0, 2)))
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    out = lik.eval_batch(net, **a)
+    assert out["loglik"].shape == (0,)
