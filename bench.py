@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--kernel", type=int, default=0,
+                    help="0 auto, 1 generic, 2 network-specialised propagation kernel")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the likelihood path is built and timed on a "
@@ -98,7 +100,7 @@ def main():
     wl = W.telegraph_workload()
     net = lik.Network(wl.net.orders, wl.net.stoich)
     db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
-                         wl.n_particles, precision=args.precision)
+                         wl.n_particles, precision=args.precision, kernel=args.kernel)
     theta = torch.from_numpy(wl.theta).cuda()
     stream = torch.cuda.current_stream()
     print(f"[bench] workload ready: {wl.n_theta} theta x {wl.n_traj} traj x "
@@ -149,6 +151,7 @@ def main():
                         "log-normal observations (sigma 0.1)",
             "n_theta": wl.n_theta, "n_traj": wl.n_traj, "n_particles": wl.n_particles,
             "n_obs": len(wl.trajectories[0]["t_obs"]), "precision": args.precision,
+            "kernel": ["auto", "generic", "specialised"][args.kernel],
         },
         "reaction_events_per_s": events / elapsed,
         "events_per_step": events // args.steps,

@@ -37,8 +37,10 @@
 #ifndef LIK_H
 #define LIK_H
 
+#ifndef __HIPCC_RTC__
 #include <stddef.h>
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -64,6 +66,11 @@ extern "C" {
 /* arithmetic of the SSA step */
 #define LIK_FP64 0       /* binary64 propensities, event times and clock */
 #define LIK_FP32_MIXED 1 /* binary32 propensities / event times, binary64 clock and weights */
+
+/* propagation kernel variants (lik_eval_opts.kernel) */
+#define LIK_KERNEL_AUTO 0        /* specialised when the batch amortises compiling it */
+#define LIK_KERNEL_GENERIC 1     /* reaction tables read at run time */
+#define LIK_KERNEL_SPECIALIZED 2 /* reaction tables compiled in (hipRTC, cached on disk) */
 
 /* limits */
 #define LIK_MAX_SPECIES 32
@@ -94,6 +101,15 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
 
 /* Releases a handle.  The caller guarantees no evaluation using it is in flight. */
 int lik_destroy_network(lik_network_t net);
+
+/*
+ * lik_network_precompile -- compile the network-specialised propagation
+ * kernel for `precision` (LIK_FP64 / LIK_FP32_MIXED) into the on-disk kernel
+ * cache ($LIK_KERNEL_CACHE, else $HOME/.cache/lik-kernels) so that the first
+ * evaluation does not pay for it.  Needs no GPU.  Returns LIK_EDEVICE with a
+ * compiler log in lik_last_error() if compilation fails.
+ */
+int lik_network_precompile(lik_network_t net, int32_t precision);
 
 /* Observation model: kind, observed species (in order) and noise scale sigma > 0. */
 typedef struct lik_obs_model {
@@ -126,11 +142,20 @@ typedef struct lik_data {
 /* Evaluation options; a NULL pointer means all defaults. */
 typedef struct lik_eval_opts {
     int32_t precision;          /* LIK_FP64 (default) or LIK_FP32_MIXED */
-    int32_t reserved;           /* must be 0 */
+    int32_t kernel;             /* LIK_KERNEL_*; every variant gives identical results */
     uint64_t event_cap;         /* per particle per interval; 0 = LIK_DEFAULT_EVENT_CAP */
     const uint32_t *theta_ids;  /* [n_theta] random-stream ids (< 2^30), NULL = 0..n_theta-1;
                                    same memory space as theta */
+    int32_t flags;              /* LIK_FLAG_* */
+    int32_t reserved;           /* must be 0 */
 } lik_eval_opts;
+
+/* lik_eval_batch_device: capture the whole launch sequence into a HIP graph
+ * the first time a given set of buffers, sizes and options is seen (per
+ * network), and replay it on later calls with only the seed updated.  The
+ * caller must not free or reuse any of those buffers for other shapes while
+ * the network lives.  Results are identical to eager launches. */
+#define LIK_FLAG_GRAPH 1
 
 /* Optional per-filter outputs (filter f = theta index i * M + trajectory m);
  * any pointer may be NULL.  Same memory space as loglik_out. */
@@ -183,6 +208,78 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs,
                           int32_t n_particles, uint64_t seed, double *loglik_out,
                           int32_t *status_out, const lik_aux *aux, void *workspace,
                           size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Continuous-batching server                                               */
+/* ------------------------------------------------------------------------ */
+/*
+ * A server owns one HIP stream, a device arena and a worker thread.  Requests
+ * (a batch of rate vectors of one network against its trajectories, with its
+ * own particle count, lengths, observation model, precision and seed) are
+ * admitted while filter slots and arena memory are free, first come first
+ * served.  Each worker iteration advances every resident filter by one
+ * observation interval in shared launches, so requests that arrive while
+ * others run join the next iteration; a request's slots and memory are
+ * released when its last interval is done.  A request's result depends only
+ * on its own inputs and seed: it is bit-identical to lik_eval_batch on the
+ * same inputs, alone or in any mix.
+ */
+#define LIK_ETIMEOUT (-5)
+
+typedef struct lik_server *lik_server_t;
+
+typedef struct lik_server_opts {
+    size_t arena_bytes;     /* device memory for resident requests; 0 = 1 GiB */
+    size_t staging_bytes;   /* pinned host memory for inputs in flight; 0 = 64 MiB */
+    int32_t max_filters;    /* filter slots (theta x trajectory pairs); 0 = 65536 */
+    int32_t kernel;         /* LIK_KERNEL_GENERIC or LIK_KERNEL_SPECIALIZED (default, 0) */
+    int32_t max_inflight;   /* iterations enqueued ahead of the GPU; 0 = 2 */
+    int32_t reserved;       /* must be 0 */
+} lik_server_opts;
+
+typedef struct lik_request {
+    lik_network_t net;
+    lik_obs_model obs;
+    int32_t precision;          /* LIK_FP64 or LIK_FP32_MIXED */
+    int32_t n_theta;
+    const double *theta;        /* host [n_theta * R] */
+    const uint32_t *theta_ids;  /* host [n_theta] random-stream ids or NULL (0..n_theta-1) */
+    lik_data data;              /* host pointers */
+    int32_t n_particles;
+    int32_t reserved;           /* must be 0 */
+    uint64_t seed;
+    uint64_t event_cap;         /* 0 = default */
+} lik_request;
+
+typedef struct lik_server_stats {
+    uint64_t submitted, completed, evals;   /* requests and rate vectors */
+    uint64_t iterations;                    /* engine iterations run */
+    double p50_latency_us, p99_latency_us;  /* submit -> result available, completed requests */
+    double busy_s;                          /* wall time with resident work */
+} lik_server_stats;
+
+/* Creates a server on the current device.  LIK_ENOMEM if the arena cannot be allocated. */
+int lik_server_create(const lik_server_opts *opts, lik_server_t *out);
+
+/*
+ * Validates and copies a request (the caller may free its buffers when this
+ * returns) and queues it.  LIK_EINVAL for invalid requests or requests that
+ * could never fit the server's arena or slots.  *ticket identifies it.
+ */
+int lik_server_submit(lik_server_t srv, const lik_request *req, uint64_t *ticket);
+
+/*
+ * Waits up to timeout_us (< 0: forever) for a ticket; on LIK_OK writes
+ * loglik_out[n_theta] and status_out[n_theta] (may be NULL) and forgets the
+ * ticket.  LIK_ETIMEOUT if it is not done yet (the ticket stays valid).
+ */
+int lik_server_wait(lik_server_t srv, uint64_t ticket, double *loglik_out, int32_t *status_out,
+                    int64_t timeout_us);
+
+int lik_server_stats_get(lik_server_t srv, lik_server_stats *out);
+
+/* Finishes every submitted request, then stops the worker and frees the server. */
+int lik_server_destroy(lik_server_t srv);
 
 /*
  * Kernel timing for measurement tools.  While enabled, every propagation

@@ -10,24 +10,25 @@
 #include <vector>
 
 #include "../../include/lik.h"
+#include "host.hpp"
 #include "lik_internal.hpp"
 
 using namespace lik;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const std::string &msg) {
+int lik::fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
 
-int hip_fail(hipError_t e, const char *where) {
+int lik::hip_fail(hipError_t e, const char *where) {
     return fail(LIK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+namespace {
 
 // Kernel timing (lik_timing_enable / lik_timing_read).
 struct TimedLaunches {
@@ -48,17 +49,6 @@ hipEvent_t timing_mark(hipStream_t s) {
 
 }  // namespace
 
-struct lik_network {
-    int32_t U, R;
-    int32_t umax, rmax;  // kernel size bucket
-    std::vector<int32_t> orders, stoich;
-    int32_t kind[LIK_MAX_REACTIONS];
-    int32_t s1[LIK_MAX_REACTIONS], s2[LIK_MAX_REACTIONS];
-    uint32_t nu[LIK_MAX_REACTIONS][4];
-    Net4x8 n4;
-    Net8x16 n8;
-    Net32x64 n32;
-};
 
 template <int RMAX, int W>
 static void fill_net(const lik_network &src, NetArgs<RMAX, W> &dst) {
@@ -161,12 +151,53 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
     return LIK_OK;
 }
 
+int lik_network_precompile(lik_network_t net, int32_t precision) {
+    if (!net) return fail(LIK_EINVAL, "network is NULL");
+    if (precision != LIK_FP64 && precision != LIK_FP32_MIXED)
+        return fail(LIK_EINVAL, "unknown precision");
+    std::string err;
+    if (!precompile_specialized(*net, precision, &err)) return fail(LIK_EDEVICE, err);
+    return LIK_OK;
+}
+
 int lik_destroy_network(lik_network_t net) {
+    if (net) release_specialized(*net);
     delete net;
     return LIK_OK;
 }
 
-static int check_common(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
+}  // extern "C"
+
+int lik::check_host_data(const lik_network *net, const lik_obs_model *obs, const lik_data *data,
+                         int32_t n_theta, const uint32_t *theta_ids) {
+    const int M = data->n_traj, U = net->U, P = obs->n_observed;
+    for (int m = 0; m < M; ++m) {
+        double prev = data->t0[m];
+        if (!isfinite(prev)) return fail(LIK_EINVAL, "t0 must be finite");
+        for (int k = data->obs_offsets[m]; k < data->obs_offsets[m + 1]; ++k) {
+            if (!(data->t_obs[k] > prev) || !isfinite(data->t_obs[k]))
+                return fail(LIK_EINVAL, "observation times must increase strictly from t0");
+            prev = data->t_obs[k];
+            for (int q = 0; q < P; ++q) {
+                const double v = data->y[(size_t)k * P + q];
+                if (!isfinite(v)) return fail(LIK_EINVAL, "observations must be finite");
+                if (obs->kind == LIK_OBS_LOGNORMAL && !(v > 0.0))
+                    return fail(LIK_EINVAL, "log-normal observations must be > 0");
+            }
+        }
+        for (int u = 0; u < U; ++u) {
+            const int32_t v = data->x0[(size_t)m * U + u];
+            if (v < 0 || v > kCountLimit) return fail(LIK_EINVAL, "x0 out of [0, 2^30]");
+        }
+    }
+    if (theta_ids)
+        for (int i = 0; i < n_theta; ++i)
+            if (theta_ids[i] >= (1u << 30)) return fail(LIK_EINVAL, "theta id >= 2^30");
+
+    return LIK_OK;
+}
+
+int lik::check_common(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
                         int32_t n_theta, int32_t n_traj, int32_t n_particles) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     if (!obs) return fail(LIK_EINVAL, "observation model is NULL");
@@ -188,13 +219,16 @@ static int check_common(lik_network_t net, const lik_obs_model *obs, const lik_e
     if (opts) {
         if (opts->precision != LIK_FP64 && opts->precision != LIK_FP32_MIXED)
             return fail(LIK_EINVAL, "unknown precision");
-        if (opts->reserved != 0) return fail(LIK_EINVAL, "reserved must be 0");
+        if (opts->kernel < LIK_KERNEL_AUTO || opts->kernel > LIK_KERNEL_SPECIALIZED)
+            return fail(LIK_EINVAL, "unknown kernel variant");
+        if ((opts->flags & ~LIK_FLAG_GRAPH) != 0 || opts->reserved != 0)
+            return fail(LIK_EINVAL, "unknown flags or nonzero reserved field");
         if (opts->event_cap > LIK_MAX_EVENT_CAP) return fail(LIK_EINVAL, "event_cap above 2^27");
     }
     return LIK_OK;
 }
 
-static int check_offsets(const int32_t *offs, int32_t M, int *t_max, int64_t *total) {
+int lik::check_offsets(const int32_t *offs, int32_t M, int *t_max, int64_t *total) {
     if (!offs) return fail(LIK_EINVAL, "obs_offsets is NULL");
     if (offs[0] != 0) return fail(LIK_EINVAL, "obs_offsets[0] must be 0");
     int tm = 0;
@@ -209,21 +243,104 @@ static int check_offsets(const int32_t *offs, int32_t M, int *t_max, int64_t *to
     return LIK_OK;
 }
 
+extern "C" {
+
 size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
                           int32_t n_particles) {
     if (!net || n_theta < 0 || n_traj < 1 || n_particles < 1) return 0;
     const size_t F = (size_t)n_theta * n_traj;
-    const size_t Hp = (size_t)((n_particles + 63) / 64) * 64;
+    const int Hp = (n_particles + 63) / 64 * 64;
     size_t b = 0;
-    b += align256(F * net->U * Hp * 4) * 2;  // xa, xb
-    b += align256(F * Hp * 8);               // lw
-    b += align256(F * Hp * 4);               // anc
-    b += align256(F * 8);                    // fll
-    b += align256(F * 4) * 2;                // fstatus, fflags
-    b += align256(F * 8);                    // fevents
-    b += align256(F * 4) * 3;                // fsteps, order, cost
+    b += align256(F * sizeof(FilterDesc));
+    b += align256(F * 4) * 4;                 // tcur, fstatus, fflags, cost
+    b += align256(F * 8) * 2;                 // fll, fevents
+    b += align256(F * (Hp / 64) * 4);         // items
+    b += align256(kMaxGroups * 4);            // item_count
+    b += align256(request_state_bytes((int64_t)F, net->U, Hp));
     return b + 256;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Slices an engine's device memory (filter table, state, work items) out of
+// one buffer, for `slots` filters with at most `items` work items.
+struct EngineLayout {
+    FilterDesc *desc;
+    EngineArgs e;
+    int32_t *state;
+};
+
+EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_bytes) {
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += align256(bytes);
+        return q;
+    };
+    EngineLayout L;
+    memset(&L.e, 0, sizeof(L.e));
+    L.desc = (FilterDesc *)take(slots * sizeof(FilterDesc));
+    L.e.desc = L.desc;
+    L.e.tcur = (int32_t *)take(slots * 4);
+    L.e.fstatus = (int32_t *)take(slots * 4);
+    L.e.fflags = (uint32_t *)take(slots * 4);
+    L.e.cost = (uint32_t *)take(slots * 4);
+    L.e.fll = (double *)take(slots * 8);
+    L.e.fevents = (uint64_t *)take(slots * 8);
+    L.e.items = (uint32_t *)take(items * 4);
+    L.e.item_count = (uint32_t *)take(kMaxGroups * 4);
+    L.state = (int32_t *)take(state_bytes);
+    return L;
+}
+
+}  // namespace
+
+hipError_t lik::engine_iteration(const EngineArgs &e, const GroupLaunch *groups, int n_groups,
+                                 hipStream_t s) {
+    hipError_t err = launch_order(e, s);
+    if (err != hipSuccess) return err;
+    for (int g = 0; g < n_groups; ++g) {
+        const GroupLaunch &G = groups[g];
+        if (G.max_items == 0) continue;
+        hipEvent_t e0 = g_timing.enabled ? timing_mark(s) : nullptr;
+        if (G.spec) {
+            int group = g;
+            void *params[] = {(void *)&e, (void *)&group};
+            err = hipModuleLaunchKernel(G.spec, G.max_items, 1, 1, kPropBlock, 1, 1, 0, s, params,
+                                        nullptr);
+        } else {
+            err = launch_propagate(e, g, G.max_items, G.netargs, G.umax, G.rmax, G.precision, s);
+        }
+        if (err != hipSuccess) return err;
+        if (g_timing.enabled) g_timing.prop.push_back({e0, timing_mark(s)});
+    }
+    hipEvent_t w0 = g_timing.enabled ? timing_mark(s) : nullptr;
+    err = launch_weigh(e, s);
+    if (err == hipSuccess && g_timing.enabled) g_timing.weigh.push_back({w0, timing_mark(s)});
+    return err;
+}
+
+bool lik::choose_specialized(lik_network &net, int precision, int variant, double work,
+                             hipFunction_t *fn, std::string *err) {
+    *fn = nullptr;
+    // Specialise when the work is large enough to amortise a compile (or a
+    // cache read): >= 2^22 particle-intervals.
+    if (variant == LIK_KERNEL_SPECIALIZED ||
+        (variant == LIK_KERNEL_AUTO && work >= 4194304.0)) {
+        *fn = specialized_kernel(net, precision, err);
+        if (!*fn && variant == LIK_KERNEL_SPECIALIZED) return false;
+    }
+    return true;
+}
+
+const void *lik::generic_netargs(const lik_network &net) {
+    return net.umax == 4 ? (const void *)&net.n4
+           : net.umax == 8 ? (const void *)&net.n8
+                           : (const void *)&net.n32;
+}
+
+extern "C" {
 
 int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
                           int32_t n_theta, const double *theta, const lik_data *data,
@@ -249,72 +366,57 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     const size_t F = (size_t)n_theta * M;
     const int H = n_particles;
     const int Hp = (H + 63) / 64 * 64;
-    EvalArgs a;
-    memset(&a, 0, sizeof(a));
-    a.theta = theta;
-    a.theta_ids = opts ? opts->theta_ids : nullptr;
-    a.obs_offsets = data->obs_offsets;
-    a.t_obs = data->t_obs;
-    a.y = data->y;
-    a.t0 = data->t0;
-    a.x0 = data->x0;
-    a.n_theta = n_theta;
-    a.M = M;
-    a.H = H;
-    a.Hp = Hp;
-    a.U = net->U;
-    a.R = net->R;
-    a.P = obs->n_observed;
-    a.nchunk = (H + kPropBlock - 1) / kPropBlock;
-    a.obs_kind = obs->kind;
-    for (int k = 0; k < LIK_MAX_OBSERVED; ++k) a.obs_species[k] = k < a.P ? obs->species[k] : 0;
-    a.sigma = obs->sigma;
-    a.seed = seed;
-    a.event_cap = (uint32_t)((opts && opts->event_cap) ? opts->event_cap : LIK_DEFAULT_EVENT_CAP);
-
+    const int nchunk = Hp / 64;
     char *p = (char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-    auto take = [&](size_t bytes) {
-        char *q = p;
-        p += align256(bytes);
-        return q;
-    };
-    a.xa = (int32_t *)take(F * a.U * Hp * 4);
-    a.xb = (int32_t *)take(F * a.U * Hp * 4);
-    a.lw = (double *)take(F * Hp * 8);
-    a.anc = (int32_t *)take(F * Hp * 4);
-    a.fll = (double *)take(F * 8);
-    a.fstatus = (int32_t *)take(F * 4);
-    a.fflags = (uint32_t *)take(F * 4);
-    a.fevents = (uint64_t *)take(F * 8);
-    a.fsteps = (int32_t *)take(F * 4);
-    a.order = (uint32_t *)take(F * 4);
-    a.cost = (uint32_t *)take(F * 4);
+    EngineLayout L = carve_engine(p, F, F * nchunk, request_state_bytes((int64_t)F, net->U, Hp));
+    L.e.f_lo = 0;
+    L.e.f_hi = (int32_t)F;
 
-    const void *netargs = net->umax == 4 ? (const void *)&net->n4
-                          : net->umax == 8 ? (const void *)&net->n8
-                                           : (const void *)&net->n32;
     const int precision = opts ? opts->precision : LIK_FP64;
+    const int variant = opts ? opts->kernel : LIK_KERNEL_AUTO;
+    GroupLaunch G;
+    G.max_items = (unsigned)(F * nchunk);
+    G.netargs = generic_netargs(*net);
+    G.umax = net->umax;
+    G.rmax = net->rmax;
+    G.precision = precision;
+    std::string err;
+    if (!choose_specialized(*net, precision, variant, (double)F * H * t_max, &G.spec, &err))
+        return fail(LIK_EDEVICE, "specialised kernel unavailable: " + err);
+
+    RequestArgs r;
+    memset(&r, 0, sizeof(r));
+    r.theta = theta;
+    r.theta_ids = opts ? opts->theta_ids : nullptr;
+    r.obs_offsets = data->obs_offsets;
+    r.t_obs = data->t_obs;
+    r.y = data->y;
+    r.t0 = data->t0;
+    r.x0 = data->x0;
+    r.state = L.state;
+    r.n_theta = n_theta;
+    r.M = M;
+    r.H = H;
+    r.Hp = Hp;
+    r.U = net->U;
+    r.R = net->R;
+    r.P = obs->n_observed;
+    r.obs_kind = obs->kind;
+    r.group = 0;
+    for (int k = 0; k < LIK_MAX_OBSERVED; ++k) r.obs_species[k] = k < r.P ? obs->species[k] : 0;
+    r.sigma = obs->sigma;
+    r.seed = seed;
+    r.event_cap = (uint32_t)((opts && opts->event_cap) ? opts->event_cap : LIK_DEFAULT_EVENT_CAP);
+    r.base = 0;
+
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_init(a, s);
-    if (e != hipSuccess) return hip_fail(e, "init launch");
+    hipError_t e = launch_admit(L.desc, L.e, r, s);
+    if (e != hipSuccess) return hip_fail(e, "admit launch");
     for (int t = 0; t < t_max; ++t) {
-        if (t > 0) {
-            e = launch_order(a, t, s);
-            if (e != hipSuccess) return hip_fail(e, "order launch");
-        }
-        hipEvent_t e0 = g_timing.enabled ? timing_mark(s) : nullptr;
-        e = launch_propagate(a, netargs, net->umax, net->rmax, precision, t, s);
-        if (e != hipSuccess) return hip_fail(e, "propagate launch");
-        hipEvent_t e1 = g_timing.enabled ? timing_mark(s) : nullptr;
-        e = launch_weigh(a, t, s);
-        if (e != hipSuccess) return hip_fail(e, "weigh launch");
-        if (g_timing.enabled) {
-            hipEvent_t e2 = timing_mark(s);
-            g_timing.prop.push_back({e0, e1});
-            g_timing.weigh.push_back({e1, e2});
-        }
+        e = engine_iteration(L.e, &G, 1, s);
+        if (e != hipSuccess) return hip_fail(e, "iteration launch");
     }
-    e = launch_finish(a, loglik_out, status_out, aux, s);
+    e = launch_finish(L.e, 0, n_theta, M, loglik_out, status_out, aux, s);
     if (e != hipSuccess) return hip_fail(e, "finish launch");
     return LIK_OK;
 }
@@ -334,29 +436,8 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
     if (n_theta == 0) return LIK_OK;
     if (!theta || !loglik_out || !data->t_obs || !data->y || !data->t0 || !data->x0)
         return fail(LIK_EINVAL, "NULL input or output pointer");
-    // host-side checks of the observations
-    for (int m = 0; m < M; ++m) {
-        double prev = data->t0[m];
-        if (!isfinite(prev)) return fail(LIK_EINVAL, "t0 must be finite");
-        for (int k = data->obs_offsets[m]; k < data->obs_offsets[m + 1]; ++k) {
-            if (!(data->t_obs[k] > prev) || !isfinite(data->t_obs[k]))
-                return fail(LIK_EINVAL, "observation times must increase strictly from t0");
-            prev = data->t_obs[k];
-            for (int q = 0; q < P; ++q) {
-                const double v = data->y[(size_t)k * P + q];
-                if (!isfinite(v)) return fail(LIK_EINVAL, "observations must be finite");
-                if (obs->kind == LIK_OBS_LOGNORMAL && !(v > 0.0))
-                    return fail(LIK_EINVAL, "log-normal observations must be > 0");
-            }
-        }
-        for (int u = 0; u < U; ++u) {
-            const int32_t v = data->x0[(size_t)m * U + u];
-            if (v < 0 || v > kCountLimit) return fail(LIK_EINVAL, "x0 out of [0, 2^30]");
-        }
-    }
-    if (opts && opts->theta_ids)
-        for (int i = 0; i < n_theta; ++i)
-            if (opts->theta_ids[i] >= (1u << 30)) return fail(LIK_EINVAL, "theta id >= 2^30");
+    rc = check_host_data(net, obs, data, n_theta, opts ? opts->theta_ids : nullptr);
+    if (rc) return rc;
 
     const size_t F = (size_t)n_theta * M;
     const size_t ws = lik_workspace_size(net, n_theta, M, n_particles);
@@ -408,7 +489,7 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
             if ((e = hipMemcpyAsync(u.d, u.h, u.n, hipMemcpyHostToDevice, s)) != hipSuccess) break;
         }
         if (e != hipSuccess) { rc = hip_fail(e, "copy to device"); break; }
-        lik_eval_opts o = opts ? *opts : lik_eval_opts{LIK_FP64, 0, 0, nullptr};
+        lik_eval_opts o = opts ? *opts : lik_eval_opts{LIK_FP64, LIK_KERNEL_AUTO, 0, nullptr, 0, 0};
         o.theta_ids = sz_ids ? d_ids : nullptr;
         lik_data dd = {M, d_off, d_t, d_y, d_t0, d_x0};
         lik_aux da = {sz_ev ? d_ev : nullptr, sz_fl ? d_fl : nullptr, sz_fs ? d_fs : nullptr};

@@ -6,8 +6,10 @@
 // fma, exact scalings) in a fixed order.  The library is compiled with
 // -ffp-contract=off; fused multiply-adds appear only where written.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 namespace lik {
 

@@ -1,0 +1,97 @@
+// host.hpp -- host-side objects of liblik: network handles and the
+// network-specialised propagation kernels compiled at run time.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lik.h"
+#include "lik_internal.hpp"
+
+struct lik_network {
+    int32_t U, R;
+    int32_t umax, rmax;  // size bucket of the generic kernels
+    std::vector<int32_t> orders, stoich;
+    int32_t kind[LIK_MAX_REACTIONS];
+    int32_t s1[LIK_MAX_REACTIONS], s2[LIK_MAX_REACTIONS];
+    uint32_t nu[LIK_MAX_REACTIONS][4];
+    lik::Net4x8 n4;
+    lik::Net8x16 n8;
+    lik::Net32x64 n32;
+    // (device, precision) -> loaded specialised kernel
+    std::mutex spec_lock;
+    std::map<std::pair<int, int>, std::pair<hipModule_t, hipFunction_t>> spec;
+    // captured launch sequences of lik_eval_batch_device (LIK_FLAG_GRAPH)
+    struct Graph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t admit = nullptr;  // the node whose seed changes per call
+        lik::FilterDesc *desc = nullptr;
+        lik::EngineArgs e;
+        lik::RequestArgs r;
+        unsigned admit_blocks = 0;
+    };
+    std::mutex graph_lock;
+    std::map<std::string, Graph> graphs;
+};
+
+namespace lik {
+
+// Source of the propagation kernel with this network's reaction tables as
+// compile-time constants (same body as the generic kernels).
+std::string specialized_source(const lik_network &net, int precision);
+
+// The specialised kernel for the current device, compiled with hipRTC on
+// first use (or read from the on-disk cache).  Returns nullptr and sets *err
+// on failure.
+hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err);
+
+// Compile (or find in the disk cache) without loading: needs no device.
+bool precompile_specialized(const lik_network &net, int precision, std::string *err);
+
+// Release every captured graph of this network.
+void release_graphs(lik_network &net);
+
+// Release every module loaded for this network.
+void release_specialized(lik_network &net);
+
+// Error reporting (thread-local message for lik_last_error).
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *where);
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Argument checks shared by the entry points.
+int check_common(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
+                 int32_t n_theta, int32_t n_traj, int32_t n_particles);
+int check_offsets(const int32_t *offs, int32_t M, int *t_max, int64_t *total);
+int check_host_data(const lik_network *net, const lik_obs_model *obs, const lik_data *data,
+                    int32_t n_theta, const uint32_t *theta_ids);
+
+// One (network, precision) group of an engine iteration.
+struct GroupLaunch {
+    hipFunction_t spec = nullptr;    // network-specialised kernel, or null for generic
+    const void *netargs = nullptr;   // generic kernel's network tables
+    int umax = 0, rmax = 0, precision = 0;
+    unsigned max_items = 0;          // upper bound on the group's work items
+};
+
+// One iteration: order the work, propagate every group, weigh/resample.
+hipError_t engine_iteration(const EngineArgs &e, const GroupLaunch *groups, int n_groups,
+                            hipStream_t s);
+
+// The specialised kernel if the variant and the amount of work call for it.
+// Returns false only when LIK_KERNEL_SPECIALIZED was asked for and failed.
+bool choose_specialized(lik_network &net, int precision, int variant, double work,
+                        hipFunction_t *fn, std::string *err);
+
+const void *generic_netargs(const lik_network &net);
+
+// Embedded kernel headers for run-time compilation (generated at build time).
+int rtc_headers(const char *const **sources, const char *const **names);
+
+}  // namespace lik

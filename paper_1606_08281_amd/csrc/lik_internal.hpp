@@ -1,7 +1,16 @@
-// lik_internal.hpp -- structures shared by the host API and the kernels.
+// lik_internal.hpp -- structures shared by the host engine and the kernels.
+//
+// Every filter (one rate vector against one observed trajectory) lives in a
+// slot of a filter table: an immutable descriptor (where its inputs and its
+// particle state are, its sizes, its random-stream ids) plus mutable
+// per-slot state (next interval, log-likelihood, status).  One engine
+// iteration advances every active slot by one observation interval, whatever
+// request, network, particle count or trajectory length it belongs to.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include "../../include/lik.h"
 
@@ -9,6 +18,8 @@ namespace lik {
 
 constexpr int kPropBlock = 64;    // one wavefront per propagation work item
 constexpr int kWeighBlock = 256;  // one workgroup per filter for weights/resampling
+constexpr int kMaxGroups = 16;    // (network, precision) groups per iteration
+constexpr int kCostKeys = 33;     // bit length of last-interval events, 0..32
 constexpr uint32_t kFlagStopped = 1u;
 constexpr int32_t kCountLimit = 1 << 30;
 
@@ -27,47 +38,79 @@ struct NetArgs {
     uint32_t nu[RMAX][W];
 };
 
-// Everything a launch needs besides the network: inputs, workspace, shape.
-struct EvalArgs {
-    // inputs (device)
-    const double *theta;
-    const uint32_t *theta_ids;
-    const int32_t *obs_offsets;
+// Immutable description of one filter slot.
+struct FilterDesc {
+    const double *theta;   // [R] rate constants
+    const double *t_obs;   // [T] observation times
+    const double *y;       // [T * P] observations
+    const int32_t *x0;     // [U] initial counts
+    int32_t *xa;           // [U][Hp] counts after even-numbered intervals
+    int32_t *xb;           // [U][Hp] counts after odd-numbered intervals
+    double *lw;            // [Hp] particle log-weights (particle-dependent part)
+    int32_t *anc;          // [Hp] ancestors for the next interval
+    double t0;             // start time
+    double sigma;          // observation noise scale
+    uint64_t seed;         // Philox key
+    uint32_t theta_id;     // random-stream id of the rate vector
+    uint32_t traj;         // trajectory index within its request
+    int32_t H, Hp, T, U, R, P;
+    int32_t obs_kind;
+    int32_t group;         // (network, precision) group of this slot
+    uint32_t event_cap;
+    int32_t pad;
+    int32_t obs_species[LIK_MAX_OBSERVED];
+};
+
+// Everything an iteration's kernels need: the filter table, its mutable
+// state and the grouped work items.
+struct EngineArgs {
+    const FilterDesc *desc;   // [slots]
+    int32_t *tcur;            // [slots] next interval to propagate
+    double *fll;              // [slots] running log-likelihood
+    int32_t *fstatus;         // [slots]
+    uint32_t *fflags;         // [slots]
+    uint64_t *fevents;        // [slots] SSA events applied
+    uint32_t *cost;           // [slots] events of the last interval (ordering key)
+    uint32_t *items;          // propagation work items (slot << 6 | chunk), grouped
+    uint32_t *item_count;     // [kMaxGroups] items written per group
+    int32_t f_lo, f_hi;       // slot range that may hold active filters
+    uint32_t group_off[kMaxGroups];  // first item of each group
+};
+
+#ifndef __HIPCC_RTC__
+// Host-side launchers (kernels.hip).
+hipError_t launch_order(const EngineArgs &e, hipStream_t s);
+hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, const void *net,
+                            int umax, int rmax, int precision, hipStream_t s);
+hipError_t launch_weigh(const EngineArgs &e, hipStream_t s);
+
+// Per-request setup / results.  A request is n_theta rate vectors against M
+// trajectories, occupying slots base .. base + n_theta*M - 1.
+struct RequestArgs {
+    const double *theta;        // [n_theta * R]
+    const uint32_t *theta_ids;  // [n_theta] or null
+    const int32_t *obs_offsets; // [M + 1]
     const double *t_obs;
     const double *y;
-    const double *t0;
-    const int32_t *x0;
-    // shape
-    int32_t n_theta, M, H, Hp, U, R, P, nchunk;
-    int32_t obs_kind;
+    const double *t0;           // [M]
+    const int32_t *x0;          // [M * U]
+    int32_t *state;             // particle state arena of the request
+    int32_t n_theta, M, H, Hp, U, R, P, obs_kind, group;
     int32_t obs_species[LIK_MAX_OBSERVED];
     double sigma;
     uint64_t seed;
     uint32_t event_cap;
-    // workspace (device)
-    int32_t *xa;        // [F][U][Hp] counts, state after even-numbered intervals
-    int32_t *xb;        // [F][U][Hp] counts, state after odd-numbered intervals
-    double *lw;         // [F][Hp] particle log-weights (particle-dependent part)
-    int32_t *anc;       // [F][Hp] ancestors for the next interval
-    double *fll;        // [F] running log-likelihood
-    int32_t *fstatus;   // [F]
-    uint32_t *fflags;   // [F]
-    uint64_t *fevents;  // [F]
-    int32_t *fsteps;    // [F] intervals propagated
-    uint32_t *order;    // [F] filter processing order (heaviest first)
-    uint32_t *cost;     // [F] cost key for ordering
+    int32_t base;               // first slot
 };
+size_t request_state_bytes(int64_t F, int32_t U, int32_t Hp);
+hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs &r,
+                        hipStream_t s);
+const void *admit_kernel();  // k_admit, for updating captured graph nodes
+hipError_t launch_finish(const EngineArgs &e, int32_t base, int32_t n_theta, int32_t M,
+                         double *loglik, int32_t *status, const lik_aux *aux, hipStream_t s);
+#endif  // __HIPCC_RTC__
 
-// Host-side launchers (kernels.hip).
-hipError_t launch_init(const EvalArgs &a, hipStream_t s);
-hipError_t launch_order(const EvalArgs &a, int t, hipStream_t s);
-hipError_t launch_propagate(const EvalArgs &a, const void *net, int umax, int rmax,
-                            int precision, int t, hipStream_t s);
-hipError_t launch_weigh(const EvalArgs &a, int t, hipStream_t s);
-hipError_t launch_finish(const EvalArgs &a, double *loglik, int32_t *status,
-                         const lik_aux *aux, hipStream_t s);
-
-// Size-bucketed network argument blocks the launchers accept.
+// Size-bucketed network argument blocks the generic launchers accept.
 using Net4x8 = NetArgs<8, 1>;    // U <= 4, R <= 8
 using Net8x16 = NetArgs<16, 1>;  // U <= 8, R <= 16
 using Net32x64 = NetArgs<64, 4>; // U <= 32, R <= 64

@@ -12,15 +12,17 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblik.so")
 
-LIK_OK, LIK_EINVAL, LIK_ENOMEM, LIK_EDEVICE, LIK_EUNSUPPORTED = 0, -1, -2, -3, -4
+LIK_OK, LIK_EINVAL, LIK_ENOMEM, LIK_EDEVICE, LIK_EUNSUPPORTED, LIK_ETIMEOUT = 0, -1, -2, -3, -4, -5
 STATUS_OK, STATUS_EVENT_CAP, STATUS_COUNT_OVERFLOW, STATUS_BAD_THETA = 0, 1, 2, 3
 OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
 FP64, FP32_MIXED = 0, 1
+KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
 MAX_OBSERVED = 8
 
-EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_eval_batch",
-            "lik_workspace_size", "lik_eval_batch_device", "lik_timing_enable",
-            "lik_timing_read", "lik_last_error", "lik_version"]
+EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile", "lik_eval_batch",
+            "lik_workspace_size", "lik_eval_batch_device", "lik_server_create",
+            "lik_server_submit", "lik_server_wait", "lik_server_stats_get", "lik_server_destroy",
+            "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version"]
 
 
 class LikError(RuntimeError):
@@ -41,13 +43,35 @@ class Data(ctypes.Structure):
 
 
 class EvalOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("event_cap", ctypes.c_uint64), ("theta_ids", ctypes.c_void_p)]
+    _fields_ = [("precision", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("event_cap", ctypes.c_uint64), ("theta_ids", ctypes.c_void_p),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
     _fields_ = [("propagate_ms", ctypes.c_double), ("propagate_launches", ctypes.c_int64),
                 ("weigh_ms", ctypes.c_double), ("weigh_launches", ctypes.c_int64)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("staging_bytes", ctypes.c_size_t),
+                ("max_filters", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("net", ctypes.c_void_p), ("obs", ObsModel), ("precision", ctypes.c_int32),
+                ("n_theta", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("theta_ids", ctypes.c_void_p), ("data", Data), ("n_particles", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("event_cap", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("evals", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
+                ("p50_latency_us", ctypes.c_double), ("p99_latency_us", ctypes.c_double),
+                ("busy_s", ctypes.c_double)]
 
 
 class Aux(ctypes.Structure):
@@ -74,6 +98,8 @@ def lib():
         vp, i32, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
         L.lik_create_network.argtypes = [i32, i32, vp, vp, ctypes.POINTER(vp)]
         L.lik_create_network.restype = ctypes.c_int
+        L.lik_network_precompile.argtypes = [vp, i32]
+        L.lik_network_precompile.restype = ctypes.c_int
         L.lik_destroy_network.argtypes = [vp]
         L.lik_destroy_network.restype = ctypes.c_int
         L.lik_eval_batch.argtypes = [vp, vp, vp, i32, vp, vp, i32, u64, vp, vp, vp]
@@ -83,6 +109,16 @@ def lib():
         L.lik_eval_batch_device.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, u64, vp, vp, vp,
                                             vp, sz, vp]
         L.lik_eval_batch_device.restype = ctypes.c_int
+        L.lik_server_create.argtypes = [vp, ctypes.POINTER(vp)]
+        L.lik_server_create.restype = ctypes.c_int
+        L.lik_server_submit.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.lik_server_submit.restype = ctypes.c_int
+        L.lik_server_wait.argtypes = [vp, ctypes.c_uint64, vp, vp, ctypes.c_int64]
+        L.lik_server_wait.restype = ctypes.c_int
+        L.lik_server_stats_get.argtypes = [vp, vp]
+        L.lik_server_stats_get.restype = ctypes.c_int
+        L.lik_server_destroy.argtypes = [vp]
+        L.lik_server_destroy.restype = ctypes.c_int
         L.lik_timing_enable.argtypes = [ctypes.c_int]
         L.lik_timing_enable.restype = ctypes.c_int
         L.lik_timing_read.argtypes = [vp]
@@ -126,6 +162,10 @@ class Network:
                                         self.stoich.ctypes.data, ctypes.byref(h)))
         self.handle = h
 
+    def precompile(self, precision=FP64):
+        """Compile the network-specialised kernel into the disk cache (no GPU)."""
+        _check(lib().lik_network_precompile(self.handle, int(precision)))
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value and _lib is not None:
@@ -160,7 +200,7 @@ def pack_trajectories(trajectories, P):
 
 
 def eval_batch(net, obs_kind, observed, sigma, theta, trajectories, n_particles, seed,
-               precision=FP64, event_cap=0, theta_ids=None, aux=False):
+               precision=FP64, event_cap=0, theta_ids=None, aux=False, kernel=KERNEL_AUTO):
     """Host-pointer entry point lik_eval_batch.  Returns a dict with loglik
     [n_theta], status [n_theta] and, if aux, filter_events, filter_loglik
     [n_theta*M] and final_state [n_theta*M, U, H]."""
@@ -172,7 +212,7 @@ def eval_batch(net, obs_kind, observed, sigma, theta, trajectories, n_particles,
     data = Data(M, _ptr(d["obs_offsets"]), _ptr(d["t_obs"]), _ptr(d["y"]), _ptr(d["t0"]),
                 _ptr(d["x0"]))
     ids = None if theta_ids is None else np.ascontiguousarray(theta_ids, dtype=np.uint32)
-    opts = EvalOpts(int(precision), 0, int(event_cap), _ptr(ids))
+    opts = EvalOpts(int(precision), int(kernel), int(event_cap), _ptr(ids))
     om = obs_model(obs_kind, observed, sigma)
     ll = np.zeros(n_theta, dtype=np.float64)
     st = np.zeros(n_theta, dtype=np.int32)
@@ -197,7 +237,7 @@ class DeviceBatch:
     calls (torch tensors on the current CUDA/HIP device)."""
 
     def __init__(self, net, obs_kind, observed, sigma, trajectories, n_theta, n_particles,
-                 precision=FP64, event_cap=0, device="cuda"):
+                 precision=FP64, event_cap=0, device="cuda", kernel=KERNEL_AUTO):
         import torch
         self.torch = torch
         self.net = net
@@ -211,6 +251,7 @@ class DeviceBatch:
         self.om = obs_model(obs_kind, observed, sigma)
         self.precision = int(precision)
         self.event_cap = int(event_cap)
+        self.kernel = int(kernel)
         self.data = Data(self.M, self.dev["obs_offsets"].data_ptr(), self.dev["t_obs"].data_ptr(),
                          self.dev["y"].data_ptr(), self.dev["t0"].data_ptr(),
                          self.dev["x0"].data_ptr())
@@ -228,7 +269,7 @@ class DeviceBatch:
         assert theta_dev.dtype == torch.float64 and theta_dev.is_contiguous()
         assert theta_dev.numel() == self.n_theta * self.net.R
         s = stream if stream is not None else torch.cuda.current_stream()
-        opts = EvalOpts(self.precision, 0, self.event_cap,
+        opts = EvalOpts(self.precision, self.kernel, self.event_cap,
                         None if theta_ids_dev is None else theta_ids_dev.data_ptr())
         aux = Aux(self.events.data_ptr(), self.filter_loglik.data_ptr(),
                   None if final_state is None else final_state.data_ptr())
@@ -239,3 +280,70 @@ class DeviceBatch:
             self.H, int(seed) & (2**64 - 1), self.loglik.data_ptr(), self.status.data_ptr(),
             ctypes.byref(aux), ws, self.ws_bytes + 256, ctypes.c_void_p(s.cuda_stream)))
         return self.loglik, self.status
+
+
+class Server:
+    """Continuous-batching server (lik_server_*): requests of any network,
+    particle count and trajectory length share the GPU as they arrive."""
+
+    def __init__(self, arena_bytes=0, staging_bytes=0, max_filters=0, kernel=0, max_inflight=0):
+        o = ServerOpts(int(arena_bytes), int(staging_bytes), int(max_filters), int(kernel),
+                       int(max_inflight), 0)
+        h = ctypes.c_void_p()
+        _check(lib().lik_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self._n_theta = {}
+
+    def submit(self, net, obs_kind, observed, sigma, theta, trajectories, n_particles, seed,
+               precision=FP64, event_cap=0, theta_ids=None):
+        """Copies the request's inputs; returns a ticket."""
+        theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, net.R))
+        P = len(observed)
+        d = pack_trajectories(trajectories, P)
+        ids = None if theta_ids is None else np.ascontiguousarray(theta_ids, dtype=np.uint32)
+        q = Request()
+        q.net = net.handle.value
+        q.obs = obs_model(obs_kind, observed, sigma)
+        q.precision = int(precision)
+        q.n_theta = theta.shape[0]
+        q.theta = theta.ctypes.data
+        q.theta_ids = _ptr(ids)
+        q.data = Data(len(trajectories), _ptr(d["obs_offsets"]), _ptr(d["t_obs"]), _ptr(d["y"]),
+                      _ptr(d["t0"]), _ptr(d["x0"]))
+        q.n_particles = int(n_particles)
+        q.reserved = 0
+        q.seed = int(seed) & (2**64 - 1)
+        q.event_cap = int(event_cap)
+        t = ctypes.c_uint64()
+        _check(lib().lik_server_submit(self.handle, ctypes.byref(q), ctypes.byref(t)))
+        self._n_theta[t.value] = theta.shape[0]
+        return t.value
+
+    def wait(self, ticket, timeout_s=None):
+        """(loglik, status) of a finished request; None on timeout."""
+        n = self._n_theta[ticket]
+        ll = np.zeros(n, dtype=np.float64)
+        st = np.zeros(n, dtype=np.int32)
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        rc = lib().lik_server_wait(self.handle, ticket, ll.ctypes.data, st.ctypes.data, us)
+        if rc == LIK_ETIMEOUT:
+            return None
+        _check(rc)
+        del self._n_theta[ticket]
+        return ll, st
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().lik_server_stats_get(self.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _check(lib().lik_server_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -26,7 +26,7 @@ def _oracle(orc, wl, theta=None, theta_ids=None, H=None, precision=0, event_cap=
 
 
 def _gpu(wl, theta=None, theta_ids=None, H=None, precision=0, event_cap=0, trajectories=None,
-         seed=None):
+         seed=None, kernel=1):
     from paper_1606_08281_amd import lik
     net = lik.Network(wl.net.orders, wl.net.stoich)
     return lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma,
@@ -34,7 +34,7 @@ def _gpu(wl, theta=None, theta_ids=None, H=None, precision=0, event_cap=0, traje
                           wl.trajectories if trajectories is None else trajectories,
                           H or wl.n_particles, wl.seed if seed is None else seed,
                           precision=precision, event_cap=event_cap, theta_ids=theta_ids,
-                          aux=True)
+                          aux=True, kernel=kernel)
 
 
 def assert_parity(got, ref, check_state=True):
@@ -60,11 +60,16 @@ def _say(*a):
     print("[gpu case]", *a, flush=True)
 
 
+KERNELS = [1, 2]   # generic, network-specialised
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_immigration_death_full_batch(orc, precision):
+def test_immigration_death_full_batch(orc, precision, kernel):
     wl = W.immigration_death_workload()
-    _say("immigration-death 64x256x20", "precision", precision)
-    assert_parity(_gpu(wl, precision=precision), _oracle(orc, wl, precision=precision))
+    _say("immigration-death 64x256x20", "precision", precision, "kernel", kernel)
+    assert_parity(_gpu(wl, precision=precision, kernel=kernel),
+                  _oracle(orc, wl, precision=precision))
 
 
 def _telegraph_subset(n_obs=50):
@@ -78,22 +83,25 @@ def _telegraph_subset(n_obs=50):
     return wl, np.sort(idx)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_telegraph_subset_full_shape(orc, precision):
+def test_telegraph_subset_full_shape(orc, precision, kernel):
     wl, idx = _telegraph_subset()
     trajs = wl.trajectories[:3]
-    _say("telegraph subset", idx.tolist(), "M=3 H=1000 T=50 precision", precision)
-    got = _gpu(wl, theta=wl.theta[idx], theta_ids=idx, trajectories=trajs, precision=precision)
+    _say("telegraph subset", idx.tolist(), "M=3 H=1000 T=50 precision", precision, "kernel", kernel)
+    got = _gpu(wl, theta=wl.theta[idx], theta_ids=idx, trajectories=trajs, precision=precision,
+               kernel=kernel)
     ref = _oracle(orc, wl, theta=wl.theta[idx], theta_ids=idx, trajectories=trajs,
                   precision=precision)
     assert_parity(got, ref)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("H", [1, 63, 64, 65, 200, 4096])
-def test_particle_counts_ragged(orc, H):
+def test_particle_counts_ragged(orc, H, kernel):
     wl = W.immigration_death_workload(n_theta=5, n_particles=H)
-    _say("ragged H", H)
-    assert_parity(_gpu(wl), _oracle(orc, wl))
+    _say("ragged H", H, "kernel", kernel)
+    assert_parity(_gpu(wl, kernel=kernel), _oracle(orc, wl))
 
 
 def test_uneven_trajectory_lengths(orc):
@@ -110,20 +118,21 @@ def test_uneven_trajectory_lengths(orc):
                   _oracle(orc, wl, theta=theta, trajectories=trajs))
 
 
-def test_statuses_and_degenerate_inputs(orc):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_statuses_and_degenerate_inputs(orc, kernel):
     wl = W.immigration_death_workload(n_theta=6, n_particles=70)
     theta = np.array([[10, 0.1], [-1, 0.1], [np.nan, 1], [np.inf, 1], [0, 0], [1e-300, 1e-300]])
-    _say("statuses")
-    assert_parity(_gpu(wl, theta=theta), _oracle(orc, wl, theta=theta))
+    _say("statuses kernel", kernel)
+    assert_parity(_gpu(wl, theta=theta, kernel=kernel), _oracle(orc, wl, theta=theta))
     _say("event cap 3")
-    assert_parity(_gpu(wl, theta=wl.theta[:3], event_cap=3),
+    assert_parity(_gpu(wl, theta=wl.theta[:3], event_cap=3, kernel=kernel),
                   _oracle(orc, wl, theta=wl.theta[:3], event_cap=3), check_state=False)
     tw = W.telegraph_workload(n_theta=2, n_traj=1, n_obs=4, n_particles=16)
     tr = dict(tw.trajectories[0])
     tr["x0"] = np.array([1, 0, 0, 0], np.int32)
     th = np.vstack([np.zeros(6), [0.1, 0.1, 0.0, 1.0, 0.0, 1.0]])
     _say("log-normal, zero protein -> -inf")
-    got = _gpu(tw, theta=th, trajectories=[tr])
+    got = _gpu(tw, theta=th, trajectories=[tr], kernel=kernel)
     assert np.all(got["loglik"] == -np.inf)
     assert_parity(got, _oracle(orc, tw, theta=th, trajectories=[tr]))
 
@@ -156,3 +165,15 @@ def test_device_entry_point_matches_host_entry_point(orc):
         torch.cuda.synchronize()
         assert np.array_equal(ll.cpu().numpy(), host["loglik"])
         assert np.array_equal(st.cpu().numpy(), host["status"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_random_network_20x40_small(orc, precision):
+    # 20 species, 40 reactions of orders 0-2: both kernel variants, short run
+    wl = W.random_network_workload(n_theta=64, n_particles=96, n_obs=3, events_per_interval=300)
+    idx = np.arange(0, 64, 8)
+    for kernel in KERNELS:
+        _say("random 20x40 theta", idx.tolist(), "H=96 T=3 precision", precision, "kernel", kernel)
+        got = _gpu(wl, theta=wl.theta[idx], theta_ids=idx, precision=precision, kernel=kernel)
+        ref = _oracle(orc, wl, theta=wl.theta[idx], theta_ids=idx, precision=precision)
+        assert_parity(got, ref)

@@ -1,0 +1,116 @@
+"""Continuous-batching server: every request's result is bit-identical to the
+same request evaluated alone (lik_eval_batch), whatever else shares the GPU;
+admission by memory; statistics; shutdown drains."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1606_08281_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu case]", *a, flush=True)
+
+
+def _mixed_requests():
+    """Requests of two networks, several particle counts, lengths and
+    precisions, each with its own seed."""
+    imm = W.immigration_death_workload(n_theta=24, n_particles=128)
+    tel = W.telegraph_workload(n_theta=16, n_traj=3, n_obs=20, n_particles=128)
+    reqs = []
+    for k in range(10):
+        if k % 2 == 0:
+            wl = imm
+            th = imm.theta[2 * k:2 * k + 3]
+            trajs = imm.trajectories
+            T = 5 + 3 * k
+            trajs = [dict(trajs[0], t_obs=trajs[0]["t_obs"][:T], y=trajs[0]["y"][:T])]
+        else:
+            wl = tel
+            th = np.vstack([W.TELEGRAPH_TRUTH * (1 + 0.1 * k), W.TELEGRAPH_TRUTH / (1 + 0.05 * k)])
+            trajs = [dict(tr, t_obs=tr["t_obs"][:4 + k], y=tr["y"][:4 + k])
+                     for tr in tel.trajectories]
+        reqs.append(dict(wl=wl, theta=th, trajs=trajs, H=[64, 128, 200, 1000, 65][k % 5],
+                         seed=100 + k, precision=k % 3 == 2))
+    return reqs
+
+
+def _alone(lik, req, nets):
+    wl = req["wl"]
+    return lik.eval_batch(nets[wl.name], wl.obs_kind, wl.observed, wl.sigma, req["theta"],
+                          req["trajs"], req["H"], req["seed"], precision=int(req["precision"]))
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_served_results_equal_alone(kernel):
+    from paper_1606_08281_amd import lik
+    reqs = _mixed_requests()
+    nets = {r["wl"].name: lik.Network(r["wl"].net.orders, r["wl"].net.stoich) for r in reqs}
+    _say("server mixed requests, kernel", kernel)
+    with lik.Server(arena_bytes=256 << 20, kernel=kernel) as srv:
+        tickets = []
+        for k, r in enumerate(reqs):
+            wl = r["wl"]
+            tickets.append(srv.submit(nets[wl.name], wl.obs_kind, wl.observed, wl.sigma,
+                                      r["theta"], r["trajs"], r["H"], r["seed"],
+                                      precision=int(r["precision"])))
+            if k % 3 == 0:
+                time.sleep(0.002)  # arrivals while others are resident
+        got = [srv.wait(t, timeout_s=120) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["p99_latency_us"] >= st["p50_latency_us"] > 0
+    for r, g in zip(reqs, got):
+        assert g is not None
+        ref = _alone(lik, r, nets)
+        assert np.array_equal(g[1], ref["status"])
+        assert np.array_equal(g[0], ref["loglik"]), (g[0], ref["loglik"])
+
+
+def test_small_arena_admits_by_memory():
+    from paper_1606_08281_amd import lik
+    wl = W.telegraph_workload(n_theta=6, n_traj=2, n_obs=8, n_particles=512)
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    per_req = 2 * 2 * (2 * 4 * 512 + 3 * 512) * 4   # two theta x two trajectories of state
+    _say("server small arena")
+    with lik.Server(arena_bytes=per_req + (1 << 16), kernel=1) as srv:
+        tickets = [srv.submit(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta[2 * k:2 * k + 2],
+                              wl.trajectories, 512, 7, theta_ids=[2 * k, 2 * k + 1])
+                   for k in range(3)]
+        out = [srv.wait(t, timeout_s=120) for t in tickets]
+    whole = lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta, wl.trajectories,
+                           512, 7)
+    got = np.concatenate([o[0] for o in out])
+    assert np.array_equal(got, whole["loglik"])
+
+
+def test_concurrent_clients_and_shutdown():
+    from paper_1606_08281_amd import lik
+    wl = W.immigration_death_workload(n_theta=32, n_particles=64)
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    results = {}
+    _say("server concurrent clients")
+    srv = lik.Server(kernel=1)
+
+    def client(c):
+        t = srv.submit(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta[4 * c:4 * c + 4],
+                       wl.trajectories, 64, 11, theta_ids=np.arange(4 * c, 4 * c + 4))
+        results[c] = srv.wait(t, timeout_s=120)
+
+    threads = [threading.Thread(target=client, args=(c,)) for c in range(8)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    # requests still queued or running when the server is closed are finished first
+    pending = [srv.submit(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta[:2], wl.trajectories,
+                          64, 11) for _ in range(3)]
+    assert pending
+    srv.close()
+    whole = lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta, wl.trajectories,
+                           64, 11)
+    got = np.concatenate([results[c][0] for c in range(8)])
+    assert np.array_equal(got, whole["loglik"])
