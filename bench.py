@@ -83,6 +83,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the step's launch sequence as a captured HIP graph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device (a known-size reference for "
+                         "hardware byte counters)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 generic, 2 network-specialised propagation kernel")
     args = ap.parse_args()
@@ -100,9 +105,16 @@ def main():
     wl = W.telegraph_workload()
     net = lik.Network(wl.net.orders, wl.net.stoich)
     db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
-                         wl.n_particles, precision=args.precision, kernel=args.kernel)
+                         wl.n_particles, precision=args.precision, kernel=args.kernel,
+                         graph=args.graph)
     theta = torch.from_numpy(wl.theta).cuda()
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] workload ready: {wl.n_theta} theta x {wl.n_traj} traj x "
           f"{wl.n_particles} particles x {len(wl.trajectories[0]['t_obs'])} obs", flush=True,
           file=sys.stderr)
@@ -117,9 +129,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     events = 0
+    max_per_particle = 0.0
     for k in range(args.steps):
         db.run(theta, wl.seed + k, stream=stream)
         events += int(db.events.sum().item())  # synchronises: counted per step
+        max_per_particle = max(max_per_particle, float(db.events.max().item()) / wl.n_particles)
         print(f"[bench] step {k + 1}/{args.steps} done", flush=True, file=sys.stderr)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -152,9 +166,11 @@ def main():
             "n_theta": wl.n_theta, "n_traj": wl.n_traj, "n_particles": wl.n_particles,
             "n_obs": len(wl.trajectories[0]["t_obs"]), "precision": args.precision,
             "kernel": ["auto", "generic", "specialised"][args.kernel],
+            "graph": bool(args.graph),
         },
         "reaction_events_per_s": events / elapsed,
         "events_per_step": events // args.steps,
+        "max_events_per_particle": max_per_particle,
         "status_counts": {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
         "kernel_ms_per_step": {"propagate": tm["propagate_ms"] / args.steps,
                                "weigh_resample": tm["weigh_ms"] / args.steps},

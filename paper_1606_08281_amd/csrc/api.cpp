@@ -161,7 +161,10 @@ int lik_network_precompile(lik_network_t net, int32_t precision) {
 }
 
 int lik_destroy_network(lik_network_t net) {
-    if (net) release_specialized(*net);
+    if (net) {
+        release_graphs(*net);
+        release_specialized(*net);
+    }
     delete net;
     return LIK_OK;
 }
@@ -261,6 +264,15 @@ size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
 }
 
 }  // extern "C"
+
+void lik::release_graphs(lik_network &net) {
+    std::lock_guard<std::mutex> g(net.graph_lock);
+    for (auto &kv : net.graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    net.graphs.clear();
+}
 
 namespace {
 
@@ -410,14 +422,110 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     r.base = 0;
 
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_admit(L.desc, L.e, r, s);
-    if (e != hipSuccess) return hip_fail(e, "admit launch");
-    for (int t = 0; t < t_max; ++t) {
-        e = engine_iteration(L.e, &G, 1, s);
-        if (e != hipSuccess) return hip_fail(e, "iteration launch");
+    auto enqueue = [&](hipStream_t st) -> int {
+        hipError_t e = launch_admit(L.desc, L.e, r, st);
+        if (e != hipSuccess) return hip_fail(e, "admit launch");
+        for (int t = 0; t < t_max; ++t) {
+            e = engine_iteration(L.e, &G, 1, st);
+            if (e != hipSuccess) return hip_fail(e, "iteration launch");
+        }
+        e = launch_finish(L.e, 0, n_theta, M, loglik_out, status_out, aux, st);
+        if (e != hipSuccess) return hip_fail(e, "finish launch");
+        return LIK_OK;
+    };
+    if (!(opts && (opts->flags & LIK_FLAG_GRAPH))) return enqueue(s);
+
+    // Graph path: everything but the seed is fixed by the key below.
+    std::string key;
+    auto add = [&](const void *v, size_t n) { key.append((const char *)v, n); };
+    const void *ptrs[] = {theta, r.theta_ids, data->obs_offsets, data->t_obs, data->y, data->t0,
+                          data->x0, loglik_out, status_out, aux ? aux->filter_events : nullptr,
+                          aux ? aux->filter_loglik : nullptr, aux ? aux->final_state : nullptr,
+                          workspace, (const void *)G.spec};
+    add(ptrs, sizeof(ptrs));
+    const int32_t ints[] = {n_theta, M, H, precision, r.P, r.obs_kind, t_max};
+    add(ints, sizeof(ints));
+    add(obs_offsets_host, (size_t)(M + 1) * 4);
+    add(r.obs_species, sizeof(r.obs_species));
+    add(&r.sigma, 8);
+    add(&r.event_cap, 4);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    add(&dev, 4);
+    std::lock_guard<std::mutex> lock(net->graph_lock);
+    auto it = net->graphs.find(key);
+    if (it == net->graphs.end()) {
+        lik_network::Graph g;
+        // Capture only records the launches, on a private stream (the
+        // caller's may be the legacy default stream, which cannot capture);
+        // the graph is launched on the caller's stream below.
+        hipStream_t cs = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cs);
+            return hip_fail(e, "hipStreamBeginCapture");
+        }
+        const bool timing = g_timing.enabled;
+        g_timing.enabled = false;  // no timing events inside a captured graph
+        int rc2 = enqueue(cs);
+        g_timing.enabled = timing;
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        (void)hipStreamDestroy(cs);
+        if (rc2 != LIK_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc2;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        // the admission kernel node: its arguments carry the seed
+        size_t n = 0;
+        (void)hipGraphGetNodes(graph, nullptr, &n);
+        std::vector<hipGraphNode_t> nodes(n);
+        (void)hipGraphGetNodes(graph, nodes.data(), &n);
+        for (hipGraphNode_t nd : nodes) {
+            hipGraphNodeType ty;
+            if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+            hipKernelNodeParams kp;
+            if (hipGraphKernelNodeGetParams(nd, &kp) == hipSuccess && kp.func == admit_kernel()) {
+                g.admit = nd;
+                g.admit_blocks = kp.gridDim.x;
+            }
+        }
+        if (!g.admit) {
+            (void)hipGraphDestroy(graph);
+            return fail(LIK_EDEVICE, "captured graph has no admission node");
+        }
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        g.graph = graph;
+        g.desc = L.desc;
+        g.e = L.e;
+        g.r = r;
+        it = net->graphs.emplace(key, g).first;
     }
-    e = launch_finish(L.e, 0, n_theta, M, loglik_out, status_out, aux, s);
-    if (e != hipSuccess) return hip_fail(e, "finish launch");
+    lik_network::Graph &g = it->second;
+    RequestArgs rr = g.r;
+    rr.seed = seed;
+    FilterDesc *dsc = g.desc;
+    EngineArgs ee = g.e;
+    void *args[] = {(void *)&dsc, (void *)&ee, (void *)&rr};
+    hipKernelNodeParams kp;
+    memset(&kp, 0, sizeof(kp));
+    kp.func = (void *)admit_kernel();
+    kp.gridDim = dim3(g.admit_blocks);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipError_t e = hipGraphExecKernelNodeSetParams(g.exec, g.admit, &kp);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams");
+    e = hipGraphLaunch(g.exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return LIK_OK;
 }
 

@@ -119,6 +119,7 @@ std::string specialized_source(const lik_network &net, int precision) {
          "typedef __hip_internal::uint64_t uint64_t;\n"
          "typedef __hip_internal::int32_t int32_t;\n"
          "typedef __hip_internal::int64_t int64_t;\n"
+         "typedef __hip_internal::uint8_t uint8_t;\n"
          "#include \"propagate.hpp\"\n"
          "namespace lik {\n"
          "static_assert(sizeof(EngineArgs) == "

@@ -17,6 +17,7 @@ STATUS_OK, STATUS_EVENT_CAP, STATUS_COUNT_OVERFLOW, STATUS_BAD_THETA = 0, 1, 2, 
 OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
 FP64, FP32_MIXED = 0, 1
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
+FLAG_GRAPH = 1
 MAX_OBSERVED = 8
 
 EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile", "lik_eval_batch",
@@ -237,7 +238,7 @@ class DeviceBatch:
     calls (torch tensors on the current CUDA/HIP device)."""
 
     def __init__(self, net, obs_kind, observed, sigma, trajectories, n_theta, n_particles,
-                 precision=FP64, event_cap=0, device="cuda", kernel=KERNEL_AUTO):
+                 precision=FP64, event_cap=0, device="cuda", kernel=KERNEL_AUTO, graph=False):
         import torch
         self.torch = torch
         self.net = net
@@ -252,6 +253,7 @@ class DeviceBatch:
         self.precision = int(precision)
         self.event_cap = int(event_cap)
         self.kernel = int(kernel)
+        self.flags = FLAG_GRAPH if graph else 0
         self.data = Data(self.M, self.dev["obs_offsets"].data_ptr(), self.dev["t_obs"].data_ptr(),
                          self.dev["y"].data_ptr(), self.dev["t0"].data_ptr(),
                          self.dev["x0"].data_ptr())
@@ -270,7 +272,7 @@ class DeviceBatch:
         assert theta_dev.numel() == self.n_theta * self.net.R
         s = stream if stream is not None else torch.cuda.current_stream()
         opts = EvalOpts(self.precision, self.kernel, self.event_cap,
-                        None if theta_ids_dev is None else theta_ids_dev.data_ptr())
+                        None if theta_ids_dev is None else theta_ids_dev.data_ptr(), self.flags, 0)
         aux = Aux(self.events.data_ptr(), self.filter_loglik.data_ptr(),
                   None if final_state is None else final_state.data_ptr())
         ws = self.workspace.data_ptr()

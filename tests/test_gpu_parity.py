@@ -177,3 +177,60 @@ def test_random_network_20x40_small(orc, precision):
         got = _gpu(wl, theta=wl.theta[idx], theta_ids=idx, precision=precision, kernel=kernel)
         ref = _oracle(orc, wl, theta=wl.theta[idx], theta_ids=idx, precision=precision)
         assert_parity(got, ref)
+
+
+def test_graph_replays_match_eager():
+    # the captured launch sequence, replayed with a new seed each time and
+    # with eager work in between, equals eager launches every time
+    import torch
+    from paper_1606_08281_amd import lik
+    wl = W.telegraph_workload(n_theta=24, n_traj=2, n_obs=12, n_particles=200)
+    for kernel in KERNELS:
+        net = lik.Network(wl.net.orders, wl.net.stoich)
+        eager = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories,
+                                wl.n_theta, wl.n_particles, kernel=kernel)
+        graph = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories,
+                                wl.n_theta, wl.n_particles, kernel=kernel, graph=True)
+        theta = torch.from_numpy(wl.theta).cuda()
+        for k in range(4):
+            _say("graph replay", k, "kernel", kernel)
+            ll_e = eager.run(theta, wl.seed + k)[0].clone()
+            ev_e = eager.events.clone()
+            junk = torch.randn(4096, device="cuda").sum()   # eager work between replays
+            ll_g = graph.run(theta, wl.seed + k)[0].clone()
+            ev_g = graph.events.clone()
+            torch.cuda.synchronize()
+            assert float(junk) == float(junk)
+            assert torch.equal(ll_e, ll_g), k
+            assert torch.equal(ev_e, ev_g), k
+        host = lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta, wl.trajectories,
+                              wl.n_particles, wl.seed + 3, kernel=kernel)
+        assert np.array_equal(ll_g.cpu().numpy(), host["loglik"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_telegraph_full_batch_sampled(orc, precision):
+    # the benchmark's batch and launch configuration (device entry point,
+    # automatic kernel choice): 1024 theta x 10 trajectories x 1000 particles
+    # x 50 observations; a sample of theta is recomputed by the oracle
+    import torch
+    from paper_1606_08281_amd import lik
+    wl = W.telegraph_workload()
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
+                         wl.n_particles, precision=precision)
+    _say("telegraph full batch 1024x10x1000x50 precision", precision)
+    ll, st = db.run(torch.from_numpy(wl.theta).cuda(), wl.seed)
+    torch.cuda.synchronize()
+    ll, st = ll.cpu().numpy(), st.cpu().numpy()
+    events = db.events.cpu().numpy().astype(np.uint64).reshape(wl.n_theta, wl.n_traj)
+    th = wl.theta
+    cost = th[:, 2] / th[:, 3] * th[:, 4] + th[:, 2]
+    order = np.argsort(cost)
+    idx = np.sort(np.concatenate([order[:3], order[[200, 450, 700]]]))
+    _say("oracle sample", idx.tolist())
+    ref = _oracle(orc, wl, theta=th[idx], theta_ids=idx, precision=precision)
+    assert np.array_equal(st[idx], ref["status"])
+    assert np.array_equal(events[idx].ravel(), ref["events"])
+    assert np.all(np.abs(ll[idx] - ref["loglik"]) <= REL * np.abs(ref["loglik"]))
+    assert np.all(st == 0) and np.all(np.isfinite(ll))
