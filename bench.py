@@ -36,8 +36,8 @@ def ops_per_event(R, U, precision):
         log = 7 + 12 + 3 + 10 + 5       # reduction, IEEE divide, squares, series, recombination
         tau = 12                        # IEEE binary64 divide
     else:
-        philox = (10 * (2 * 4 + 2)) / 2  # one block serves two events
-        uniforms = 2 * 3
+        philox = 10 * (2 * 4 + 2)       # the binary64 path's block (same stream)
+        uniforms = 2 * 3                # 24-bit shift, int->binary32, scale (two uniforms)
         log = 7 + 10 + 3 + 6 + 5
         tau = 10
     propensity = 3 * R                  # count -> float, times rate, running sum
@@ -88,6 +88,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size reference for "
                          "hardware byte counters)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate work partitionings on this batch first and keep "
+                         "the fastest (default: the library's default partitioning)")
+    ap.add_argument("--tuning", default=None,
+                    help="work partitioning pool_min,pool_max,pool_events,pool_first,refill_min "
+                         "(default: the library's)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 generic, 2 network-specialised propagation kernel")
     args = ap.parse_args()
@@ -119,6 +125,14 @@ def main():
           f"{wl.n_particles} particles x {len(wl.trajectories[0]['t_obs'])} obs", flush=True,
           file=sys.stderr)
 
+    if args.tuning:
+        keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min")
+        net.set_tuning(**dict(zip(keys, (int(v) for v in args.tuning.split(",")))))
+    tuning = net.tuning()
+    if args.autotune:
+        tuning = db.autotune(theta, wl.seed, stream=stream)
+        print(f"[bench] autotuned: {tuning}", flush=True, file=sys.stderr)
+
     for w in range(args.warmup):
         db.run(theta, wl.seed, stream=stream)
         torch.cuda.synchronize()
@@ -140,6 +154,33 @@ def main():
     lik.timing_enable(False)
     tm = lik.timing_read()
     status = db.status.cpu().numpy()
+
+    fp32_error = None
+    if args.precision == 1:
+        # the same seed in binary64: both draw the same random blocks, so the
+        # difference per result is the effect of binary32 arithmetic alone
+        ll32 = db.loglik.cpu().numpy().copy()
+        db64 = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories,
+                               wl.n_theta, wl.n_particles, precision=lik.FP64,
+                               kernel=args.kernel)
+        db64.run(theta, wl.seed + args.steps - 1, stream=stream)
+        ll64 = db64.loglik.cpu().numpy().copy()
+        # Monte Carlo scale: the binary64 estimate under another seed
+        db64.run(theta, wl.seed + args.steps, stream=stream)
+        ll64b = db64.loglik.cpu().numpy().copy()
+
+        def diff(a, b):
+            ok = np.isfinite(a) & np.isfinite(b)
+            err = np.abs(a[ok] - b[ok])
+            if not err.size:
+                return {"n": 0}
+            return {"n": int(ok.sum()), "abs_max": float(err.max()),
+                    "abs_p50": float(np.median(err)), "abs_p99": float(np.percentile(err, 99)),
+                    "rel_max": float((err / np.abs(b[ok])).max()),
+                    "identical": int((err == 0).sum())}
+        fp32_error = dict(diff(ll32, ll64), vs="f64 path, same seed",
+                          f64_seed_to_seed=diff(ll64b, ll64))
+        del db64
 
     evals = wl.n_theta * args.steps
     ope = ops_per_event(wl.net.R, wl.net.U, args.precision)
@@ -183,7 +224,10 @@ def main():
             "launches": tm["propagate_launches"],
         },
         "cpu_baseline": None,
+        "tuning": tuning,
     }
+    if fp32_error is not None:
+        out["fp32_error_vs_fp64"] = fp32_error
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", flush=True, file=sys.stderr)
         out["cpu_baseline"] = cpu_baseline(wl)

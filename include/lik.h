@@ -99,6 +99,31 @@ typedef struct lik_network *lik_network_t;
 int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *reactant_orders,
                        const int32_t *stoichiometry, lik_network_t *out);
 
+/*
+ * Work partitioning of the propagation kernels (never changes a result).
+ * A wavefront runs a pool of G * 64 particles of one filter and hands a lane
+ * the next particle of its pool as soon as the lane's particle reaches the
+ * observation time.  Per filter and interval, G = clamp(pool_events / (events
+ * per particle in the filter's previous interval), pool_min, pool_max), and
+ * pool_first in the first interval; G is at most H / 64 rounded up, and at
+ * most 16 / U (the pool's counts are staged in 4 KiB of LDS).  Idle lanes
+ * take new particles once refill_min of them are idle.
+ */
+typedef struct lik_tuning {
+    int32_t pool_min;      /* >= 1 */
+    int32_t pool_max;      /* >= pool_min, <= 64 */
+    uint32_t pool_events;  /* target events per lane per work item */
+    int32_t pool_first;    /* >= 1, <= 64 */
+    int32_t refill_min;    /* idle lanes of a wavefront that trigger a refill, 1..64 */
+} lik_tuning;
+
+/* Sets (NULL: restores the defaults {2, 2, 0, 2, 1}) / reads a network's
+ * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
+ * evaluation on this network is being enqueued on another thread.  The
+ * server uses the defaults for every network. */
+int lik_network_set_tuning(lik_network_t net, const lik_tuning *tuning);
+int lik_network_get_tuning(lik_network_t net, lik_tuning *out);
+
 /* Releases a handle.  The caller guarantees no evaluation using it is in flight. */
 int lik_destroy_network(lik_network_t net);
 
@@ -298,6 +323,21 @@ typedef struct lik_timing {
 
 int lik_timing_enable(int enable);
 int lik_timing_read(lik_timing *out);
+
+/*
+ * lik_autotune_device -- times lik_eval_batch_device on these exact buffers
+ * for a fixed set of candidate tunings (synchronising `stream` after each),
+ * keeps the fastest as the network's tuning and writes it to *chosen (may be
+ * NULL).  The outputs are overwritten with valid results of `seed`; graph
+ * mode (LIK_FLAG_GRAPH) is ignored while timing.  Arguments as for
+ * lik_eval_batch_device (no aux outputs).  On error the previous tuning is
+ * kept.  Same threading rule as lik_network_set_tuning.
+ */
+int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
+                        int32_t n_theta, const double *theta, const lik_data *data,
+                        const int32_t *obs_offsets_host, int32_t n_particles, uint64_t seed,
+                        double *loglik_out, int32_t *status_out, void *workspace,
+                        size_t workspace_bytes, void *stream, lik_tuning *chosen);
 
 /* Thread-local description of the last error returned on this thread. */
 const char *lik_last_error(void);

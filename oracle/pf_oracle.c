@@ -299,11 +299,11 @@ static uint64_t ssa_interval(const orc_problem *P, const double *c, int32_t *x,
             total = (double)sf;
             if (!(sf > 0.0f)) break;
             if (n >= P->event_cap) { *status = ORC_EVENT_CAP; break; }
-            /* event n uses the word pair 2(n&1), 2(n&1)+1 of block n>>1 */
-            philox_block(P->seed, (uint32_t)(n >> 1), slot, c2, theta_id << 2, w);
-            int k = 2 * (int)(n & 1);
-            float u1 = (float)((w[k] >> 8) + 1u) * 0x1p-24f;
-            float u2 = (float)(w[k + 1] >> 8) * 0x1p-24f;
+            /* event n draws the same block as in binary64 and keeps the
+             * leading 24 bits of the words that lead its two uniforms */
+            philox_block(P->seed, (uint32_t)n, slot, c2, theta_id << 2, w);
+            float u1 = (float)((w[1] >> 8) + 1u) * 0x1p-24f;   /* (0, 1] */
+            float u2 = (float)(w[3] >> 8) * 0x1p-24f;          /* [0, 1) */
             float tau = -orc_logf(u1) / sf;
             if (clock + (double)tau > t_end) break;
             float target = u2 * sf;

@@ -151,6 +151,78 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
     return LIK_OK;
 }
 
+int lik_network_set_tuning(lik_network_t net, const lik_tuning *t) {
+    if (!net) return fail(LIK_EINVAL, "network is NULL");
+    lik_tuning v = t ? *t : kDefaultTuning;
+    if (v.pool_min < 1 || v.pool_max < v.pool_min || v.pool_max > 64 || v.pool_first < 1 ||
+        v.pool_first > 64 || v.refill_min < 1 || v.refill_min > 64)
+        return fail(LIK_EINVAL, "tuning must satisfy 1 <= pool_min <= pool_max <= 64, "
+                                "1 <= pool_first <= 64, 1 <= refill_min <= 64");
+    net->tuning = v;
+    return LIK_OK;
+}
+
+int lik_network_get_tuning(lik_network_t net, lik_tuning *out) {
+    if (!net || !out) return fail(LIK_EINVAL, "network or out is NULL");
+    *out = net->tuning;
+    return LIK_OK;
+}
+
+int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
+                        int32_t n_theta, const double *theta, const lik_data *data,
+                        const int32_t *obs_offsets_host, int32_t n_particles, uint64_t seed,
+                        double *loglik_out, int32_t *status_out, void *workspace,
+                        size_t workspace_bytes, void *stream, lik_tuning *chosen) {
+    if (!net) return fail(LIK_EINVAL, "network is NULL");
+    static const lik_tuning cands[] = {
+        {1, 1, 0, 1, 1},        // one group of 64 particles per wavefront
+        {2, 2, 0, 2, 1},        // default
+        {2, 2, 0, 2, 8},
+        {3, 3, 0, 3, 1},
+        {4, 4, 0, 4, 1},
+        {4, 4, 0, 4, 16},
+        {1, 2, 1024, 1, 1},     // pools of two for filters below 512 events per particle
+    };
+    const lik_tuning saved = net->tuning;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(LIK_EDEVICE, "hipEventCreate failed");
+    float best_ms = -1.0f;
+    lik_tuning best = saved;
+    int rc = LIK_OK;
+    lik_eval_opts o = opts ? *opts : lik_eval_opts{LIK_FP64, LIK_KERNEL_AUTO, 0, nullptr, 0, 0};
+    o.flags &= ~LIK_FLAG_GRAPH;
+    // one untimed run loads kernels and warms caches
+    rc = lik_eval_batch_device(net, obs, &o, n_theta, theta, data, obs_offsets_host, n_particles,
+                               seed, loglik_out, status_out, nullptr, workspace, workspace_bytes,
+                               stream);
+    for (const lik_tuning &c : cands) {
+        if (rc != LIK_OK) break;
+        net->tuning = c;
+        (void)hipEventRecord(a, s);
+        rc = lik_eval_batch_device(net, obs, &o, n_theta, theta, data, obs_offsets_host,
+                                   n_particles, seed, loglik_out, status_out, nullptr, workspace,
+                                   workspace_bytes, stream);
+        (void)hipEventRecord(b, s);
+        if (rc != LIK_OK) break;
+        float ms = 0.0f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+            rc = fail(LIK_EDEVICE, "timing failed");
+            break;
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    net->tuning = rc == LIK_OK ? best : saved;
+    if (rc == LIK_OK && chosen) *chosen = best;
+    return rc;
+}
+
 int lik_network_precompile(lik_network_t net, int32_t precision) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     if (precision != LIK_FP64 && precision != LIK_FP32_MIXED)
@@ -256,6 +328,7 @@ size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
     size_t b = 0;
     b += align256(F * sizeof(FilterDesc));
     b += align256(F * 4) * 4;                 // tcur, fstatus, fflags, cost
+    b += align256(F);                         // pool
     b += align256(F * 8) * 2;                 // fll, fevents
     b += align256(F * (Hp / 64) * 4);         // items
     b += align256(kMaxGroups * 4);            // item_count
@@ -298,6 +371,7 @@ EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_byte
     L.e.fstatus = (int32_t *)take(slots * 4);
     L.e.fflags = (uint32_t *)take(slots * 4);
     L.e.cost = (uint32_t *)take(slots * 4);
+    L.e.pool = (uint8_t *)take(slots);
     L.e.fll = (double *)take(slots * 8);
     L.e.fevents = (uint64_t *)take(slots * 8);
     L.e.items = (uint32_t *)take(items * 4);
@@ -383,6 +457,11 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     EngineLayout L = carve_engine(p, F, F * nchunk, request_state_bytes((int64_t)F, net->U, Hp));
     L.e.f_lo = 0;
     L.e.f_hi = (int32_t)F;
+    L.e.pool_min = net->tuning.pool_min;
+    L.e.pool_max = net->tuning.pool_max;
+    L.e.pool_events = net->tuning.pool_events;
+    L.e.pool_first = net->tuning.pool_first;
+    L.e.refill_min = net->tuning.refill_min;
 
     const int precision = opts ? opts->precision : LIK_FP64;
     const int variant = opts ? opts->kernel : LIK_KERNEL_AUTO;
@@ -449,6 +528,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     add(r.obs_species, sizeof(r.obs_species));
     add(&r.sigma, 8);
     add(&r.event_cap, 4);
+    add(&net->tuning, sizeof(lik_tuning));
     int dev = 0;
     (void)hipGetDevice(&dev);
     add(&dev, 4);

@@ -13,6 +13,11 @@
 #include "../../include/lik.h"
 #include "lik_internal.hpp"
 
+namespace lik {
+// Work partitioning used unless a caller sets another (lik_network_set_tuning).
+constexpr lik_tuning kDefaultTuning = {2, 2, 0, 2, 1};
+}  // namespace lik
+
 struct lik_network {
     int32_t U, R;
     int32_t umax, rmax;  // size bucket of the generic kernels
@@ -23,6 +28,7 @@ struct lik_network {
     lik::Net4x8 n4;
     lik::Net8x16 n8;
     lik::Net32x64 n32;
+    lik_tuning tuning = lik::kDefaultTuning;
     // (device, precision) -> loaded specialised kernel
     std::mutex spec_lock;
     std::map<std::pair<int, int>, std::pair<hipModule_t, hipFunction_t>> spec;

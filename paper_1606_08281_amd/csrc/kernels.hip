@@ -5,16 +5,16 @@
 //   k_order: the work list.  Active slots, grouped by (network, precision),
 //     heaviest first by the events their particles needed in the previous
 //     interval; each slot contributes one item per 64 particles.
-//   k_propagate (body in propagate.hpp): one lane per filter particle, one
-//     wavefront per item.  Gathers the particle's ancestor state, runs
+//   k_propagate (body in propagate.hpp): one wavefront per item, a pool of
+//     particles of one slot.  Gathers each particle's ancestor state and runs
 //     Gillespie's direct method from the previous observation time to the
 //     next one (Supplementary I, Algorithm "Likelihood Approximation using
-//     particle filter", the "Simulate" step), then the particle's log-weight
-//     (the "Compute l_t^i" step).
-//   k_weigh: one workgroup per slot.  Log-sum-exp of the weights into the
-//     running log-likelihood (multiplying p(y_{t-1}|theta) by the mean
-//     weight), then systematic resampling with integer weights for the next
-//     interval (the "Sample H indices according to weights" step).
+//     particle filter", the "Simulate" step).
+//   k_weigh: one workgroup per slot.  The particles' log-weights (the
+//     "Compute l_t^i" step), their log-sum-exp into the running
+//     log-likelihood (multiplying p(y_{t-1}|theta) by the mean weight), then
+//     systematic resampling with integer weights for the next interval (the
+//     "Sample H indices according to weights" step).
 // k_admit fills the slots of a request; k_finish sums its log-likelihoods
 // over trajectories.
 #ifndef __HIPCC_RTC__
@@ -118,6 +118,22 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
 // Order inside a key is arbitrary: it only changes which wavefront starts
 // first, never a result.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c) {
+    const int nchunk = e.desc[f].Hp >> 6;
+    int g;
+    if (e.tcur[f] == 0) {
+        g = e.pool_first;
+    } else {
+        const uint32_t per = c / (uint32_t)e.desc[f].H;  // events per particle last interval
+        const uint32_t want = e.pool_events / (per > 0 ? per : 1u);
+        g = (int)min(want, (uint32_t)e.pool_max);
+        g = max(g, e.pool_min);
+    }
+    const int lds_cap = kPoolLdsWords / (kPropBlock * e.desc[f].U);  // pool counts fit in LDS
+    g = min(g, lds_cap);
+    return min(max(g, 1), nchunk);
+}
+
 __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
     __shared__ uint32_t hist[kMaxGroups * kCostKeys];
     for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x) hist[k] = 0;
@@ -126,7 +142,9 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
         if (!slot_active(e, f)) continue;
         const uint32_t c = e.cost[f];
         const int key = 32 - (c == 0 ? 0 : 32 - __clz(c));
-        atomicAdd(&hist[e.desc[f].group * kCostKeys + key], (uint32_t)(e.desc[f].Hp >> 6));
+        const int nchunk = e.desc[f].Hp >> 6;
+        const int g = pool_size(e, f, c);
+        atomicAdd(&hist[e.desc[f].group * kCostKeys + key], (uint32_t)((nchunk + g - 1) / g));
     }
     __syncthreads();
     if (threadIdx.x < kMaxGroups) {
@@ -144,9 +162,12 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
         if (!slot_active(e, f)) continue;
         const uint32_t c = e.cost[f];
         const int key = 32 - (c == 0 ? 0 : 32 - __clz(c));
-        const uint32_t nchunk = (uint32_t)(e.desc[f].Hp >> 6);
-        const uint32_t pos = atomicAdd(&hist[e.desc[f].group * kCostKeys + key], nchunk);
-        for (uint32_t q = 0; q < nchunk; ++q) e.items[pos + q] = ((uint32_t)f << 6) | q;
+        const int nchunk = e.desc[f].Hp >> 6;
+        const int g = pool_size(e, f, c);
+        const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
+        const uint32_t pos = atomicAdd(&hist[e.desc[f].group * kCostKeys + key], n_items);
+        for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);
+        e.pool[f] = (uint8_t)g;
         e.cost[f] = 0;  // re-accumulated by this iteration's propagation
     }
 }
@@ -189,14 +210,35 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
         }
         return;
     }
-    const double *lw = d.lw;
+    double *lw = d.lw;
     const int per = (H + kWeighBlock - 1) / kWeighBlock;
     const int j0 = tid * per;
     const int j1 = min(j0 + per, H);
+    const int32_t *xs = (t & 1) ? d.xa : d.xb;  // counts at the observation time
+    const double *yt = d.y + (size_t)t * d.P;
 
-    // max
+    // particle-dependent part of log p(y_t | x_j) (the "Compute l_t^i" step),
+    // kept in lw for this thread's second pass; and the maximum
     double mx = -__builtin_inf();
-    for (int j = j0; j < j1; ++j) mx = fmax(mx, lw[j]);
+    for (int j = j0; j < j1; ++j) {
+        double l = 0.0;
+        for (int k = 0; k < d.P; ++k) {
+            const int cnt = xs[(size_t)d.obs_species[k] * d.Hp + j];
+            if (d.obs_kind == LIK_OBS_LOGNORMAL) {
+                if (cnt <= 0) {
+                    l = -__builtin_inf();
+                    break;
+                }
+                const double z = (dlog(yt[k]) - dlog((double)cnt)) / d.sigma;
+                l = l - 0.5 * (z * z);
+            } else {
+                const double z = (yt[k] - (double)cnt) / d.sigma;
+                l = l - 0.5 * (z * z);
+            }
+        }
+        lw[j] = l;
+        mx = fmax(mx, l);
+    }
     mx = wave_max(mx);
     if (lane == 0) red[wave] = mx;
     __syncthreads();
@@ -246,7 +288,6 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
         for (int w = 1; w < kWeighBlock / 64; ++w) S += red[w];
         // running log-likelihood: log of the mean weight plus the
         // particle-independent part of the observation density
-        const double *yt = d.y + (size_t)t * d.P;
         const double per_comp = dlog(d.sigma) + 0.5 * dlog(2.0 * 3.141592653589793);
         double cst = -((double)d.P * per_comp);
         if (d.obs_kind == LIK_OBS_LOGNORMAL)

@@ -1,4 +1,5 @@
-// propagate.hpp -- one propagation work item: 64 particles of one filter.
+// propagate.hpp -- one propagation work item: a pool of particles of one
+// filter run over one observation interval by one wavefront.
 #pragma once
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
@@ -72,19 +73,37 @@ __device__ __forceinline__ void apply_change(int U, const uint32_t *sel, int *x)
         if (u < U) x[u] += __builtin_amdgcn_sbfe(sel[u >> 3], 4 * (u & 7), 4);
 }
 
+template <bool B, class T, class F>
+struct pick_type {
+    using type = T;
+};
+template <class T, class F>
+struct pick_type<false, T, F> {
+    using type = F;
+};
+
 // ---------------------------------------------------------------------------
-// propagate: resample-gather, direct-method SSA to the next observation time,
-// particle log-weight.
-// ---------------------------------------------------------------------------
+// propagate: for every particle of the item's pool, gather its ancestor's
+// counts, run Gillespie's direct method from the previous observation time
+// to the next one, and store its counts (the weights are taken from them by
+// k_weigh).
+//
+// A work item is a pool of G * 64 consecutive particles of one filter (G set
+// per filter by k_order).  Each lane runs one event per loop iteration; a lane
+// whose particle has reached the observation time finishes it and takes the
+// next particle of the pool (ballot + rank among the idle lanes), so lanes are
+// not held up by the slowest particle of a fixed group of 64.  Which lane runs
+// a particle never changes its arithmetic or its random stream.
+//
 // NetT provides U, R, kind[], s1[], s2[], nu[][W] either as kernel-argument
 // data (generic kernels) or as compile-time constants (network-specialised
-// kernels); the arithmetic is the same in both.
+// kernels).
+// ---------------------------------------------------------------------------
 template <class NetT, int UMAX, int RMAX, int W, int PREC>
 __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &net, int group) {
     if (blockIdx.x >= e.item_count[group]) return;
     const uint32_t item = e.items[e.group_off[group] + blockIdx.x];
     const int f = (int)(item >> 6);
-    const int chunk = (int)(item & 63u);
     const FilterDesc &d = e.desc[f];
     const int t = e.tcur[f];
 
@@ -92,117 +111,179 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     const int R = net.R;
     const int H = d.H;
     const int Hp = d.Hp;
-    const int j = chunk * kPropBlock + (int)threadIdx.x;
-    const bool active = j < H;
+    const int lane = (int)threadIdx.x;
+    const int p0 = (int)(item & 63u) * kPropBlock;
+    const int p1 = min(p0 + (int)e.pool[f] * kPropBlock, H);
     const double t_start = (t == 0) ? d.t0 : d.t_obs[t - 1];
     const double t_end = d.t_obs[t];
     const uint32_t c2 = (d.traj << 16) | (uint32_t)t;
     const uint32_t c3 = d.theta_id << 2;  // purpose 0: reaction events
     const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    const int32_t *src = (t & 1) ? d.xb : d.xa;
+    int32_t *dst = (t & 1) ? d.xa : d.xb;
+    // Descriptor fields the event loop uses, read once: the loop's stores
+    // could alias the descriptor as far as the compiler knows.
+    const uint32_t event_cap = d.event_cap;
+    const int32_t *anc_p = d.anc;
+    const int32_t *x0_p = d.x0;
+    const int refill_min = e.refill_min;
 
-    double c[RMAX];
+    using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
+    Real c[RMAX];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? d.theta[r] : 0.0;
+    for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? (Real)d.theta[r] : (Real)0;
+
+    // A pool of more than 64 particles lives in LDS ([u][particle - p0]): its
+    // ancestors' counts are staged there first, a lane taking a new particle
+    // reads them from there, a finished particle's counts replace them, and
+    // the pool is copied out at the end.  The event loop then touches no
+    // global memory, so it never waits on it.  (Only such pools refill: a
+    // pool of at most 64 particles has one per lane.)
+    __shared__ int32_t pool_x[kPoolLdsWords];
+    const int npool = p1 - p0;
+    const bool staged = npool > kPropBlock;
+    if (staged) {
+#pragma unroll 1
+        for (int k = lane; k < npool; k += kPropBlock) {
+            if (t == 0) {
+#pragma unroll
+                for (int u = 0; u < UMAX; ++u)
+                    if (u < U) pool_x[u * npool + k] = x0_p[u];
+            } else {
+                const int a = anc_p[p0 + k];
+#pragma unroll
+                for (int u = 0; u < UMAX; ++u)
+                    if (u < U) pool_x[u * npool + k] = src[(size_t)u * Hp + a];
+            }
+        }
+        __syncthreads();  // the workgroup is this one wavefront
+    }
 
     int x[UMAX];
-    if (t == 0) {
-#pragma unroll
-        for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? d.x0[u] : 0;
-    } else {
-        const int32_t *src = (t & 1) ? d.xb : d.xa;
-        const int anc = active ? d.anc[j] : 0;
-#pragma unroll
-        for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? src[(size_t)u * Hp + anc] : 0;
-    }
-
+    double clock = t_start;
     uint32_t n = 0;
-    int st = LIK_STATUS_OK;
-    if (active) {
-        double clock = t_start;
-        if (PREC == LIK_FP32_MIXED) {
-            float cf[RMAX];
+    int j = p0 + lane;
+    bool have = j < p1;
+    auto load_lds = [&](int jj) {
 #pragma unroll
-            for (int r = 0; r < RMAX; ++r) cf[r] = (float)c[r];
-            // Event n uses words 2(n&1), 2(n&1)+1 of block n>>1: both events
-            // of a pair sit in one iteration, so every lane enters it at an
-            // even n and one block serves two events.
-            float Sf[RMAX];
-            auto fire = [&](uint32_t wa, uint32_t wb, float sf) -> bool {
-                const float u1 = (float)((wa >> 8) + 1u) * 0x1p-24f;
-                const float u2 = (float)(wb >> 8) * 0x1p-24f;
-                const float tau = -flog(u1) / sf;
-                const double tau_d = (double)tau;
-                if (clock + tau_d > t_end) return false;  // the pending event is discarded
-                uint32_t sel[W];
-                select_reaction<NetT, RMAX, W, float>(net, Sf, u2 * sf, sel);
-                apply_change<UMAX, W>(U, sel, x);
-                clock = clock + tau_d;
-                n = n + 1;
-                return true;
-            };
-            for (;;) {
-                float sf = running_sums<NetT, RMAX, float>(net, cf, x, Sf);
-                if (!(sf > 0.0f)) break;
-                if (n >= d.event_cap) { st = LIK_STATUS_EVENT_CAP; break; }
-                const Block4 b = philox4x32_10(n >> 1, (uint32_t)j, c2, c3, k0, k1);
-                if (!fire(b.w0, b.w1, sf)) break;
-                sf = running_sums<NetT, RMAX, float>(net, cf, x, Sf);
-                if (!(sf > 0.0f)) break;
-                if (n >= d.event_cap) { st = LIK_STATUS_EVENT_CAP; break; }
-                if (!fire(b.w2, b.w3, sf)) break;
-            }
+        for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? pool_x[u * npool + (jj - p0)] : 0;
+        clock = t_start;
+        n = 0;
+    };
+    if (have) {
+        if (staged) {
+            load_lds(j);
+        } else if (t == 0) {
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? x0_p[u] : 0;
         } else {
-            double S[RMAX];
-            for (;;) {
-                const double s = running_sums<NetT, RMAX, double>(net, c, x, S);
-                if (!(s > 0.0)) break;
-                if (n >= d.event_cap) { st = LIK_STATUS_EVENT_CAP; break; }
-                const Block4 b = philox4x32_10(n, (uint32_t)j, c2, c3, k0, k1);
-                const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
-                const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
-                const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
-                const double u2 = (double)z2 * 0x1p-53;        // [0, 1)
-                const double tau = -dlog(u1) / s;
-                if (clock + tau > t_end) break;  // the pending event is discarded
-                uint32_t sel[W];
-                select_reaction<NetT, RMAX, W, double>(net, S, u2 * s, sel);
-                apply_change<UMAX, W>(U, sel, x);
-                clock = clock + tau;
-                n = n + 1;
-            }
-        }
+            const int a = anc_p[j];
 #pragma unroll
-        for (int u = 0; u < UMAX; ++u)
-            if (u < U && x[u] > kCountLimit) st = st > LIK_STATUS_COUNT_OVERFLOW ? st : LIK_STATUS_COUNT_OVERFLOW;
-
-        // Particle-dependent part of log p(y_t | x).
-        const double *yt = d.y + (size_t)t * d.P;
-        double lw = 0.0;
-        for (int k = 0; k < d.P; ++k) {
-            const int cnt = x[d.obs_species[k]];
-            if (d.obs_kind == LIK_OBS_LOGNORMAL) {
-                if (cnt <= 0) {
-                    lw = -__builtin_inf();
-                    break;
-                }
-                const double z = (dlog(yt[k]) - dlog((double)cnt)) / d.sigma;
-                lw = lw - 0.5 * (z * z);
-            } else {
-                const double z = (yt[k] - (double)cnt) / d.sigma;
-                lw = lw - 0.5 * (z * z);
-            }
+            for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? src[(size_t)u * Hp + a] : 0;
         }
-        int32_t *dst = (t & 1) ? d.xa : d.xb;
-#pragma unroll
-        for (int u = 0; u < UMAX; ++u)
-            if (u < U) dst[(size_t)u * Hp + j] = x[u];
-        d.lw[j] = lw;
-        if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[f], st);
     }
-    const uint64_t ev = wave_sum_u64((uint64_t)n);
-    if (threadIdx.x == 0 && ev) {
-        atomicAdd((unsigned long long *)&e.fevents[f], (unsigned long long)ev);
-        atomicAdd(&e.cost[f], (uint32_t)(ev > 0xFFFFFFFFull ? 0xFFFFFFFFu : ev));
+    int next = p0 + kPropBlock;  // first particle of the pool no lane has taken (uniform)
+    bool pend = have;            // the lane holds counts not stored yet
+    uint64_t ev = 0;
+    int st = LIK_STATUS_OK;
+    Real S[RMAX];
+    // a finished particle: overflow check, events, and its counts into the
+    // pool's LDS slot (staged) or straight to global memory
+    auto retire = [&](bool to_lds) {
+#pragma unroll
+        for (int u = 0; u < UMAX; ++u)
+            if (u < U && x[u] > kCountLimit)
+                st = st > LIK_STATUS_COUNT_OVERFLOW ? st : LIK_STATUS_COUNT_OVERFLOW;
+        ev += n;
+        if (to_lds) {
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u)
+                if (u < U) pool_x[u * npool + (j - p0)] = x[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u)
+                if (u < U) dst[(size_t)u * Hp + j] = x[u];
+        }
+    };
+
+    for (;;) {
+        if (have) {
+            const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
+            if (!(s > (Real)0)) {
+                have = false;  // no reaction can fire before the observation
+            } else if (n >= event_cap) {
+                st = st > LIK_STATUS_EVENT_CAP ? st : LIK_STATUS_EVENT_CAP;
+                have = false;
+            } else {
+                const Block4 b = philox4x32_10(n, (uint32_t)j, c2, c3, k0, k1);
+                double tau;
+                Real target;
+                if (PREC == LIK_FP32_MIXED) {
+                    // the leading 24 bits of the binary64 uniforms' words
+                    const float u1 = (float)((b.w1 >> 8) + 1u) * 0x1p-24f;  // (0, 1]
+                    const float u2 = (float)(b.w3 >> 8) * 0x1p-24f;         // [0, 1)
+                    tau = (double)(-flog(u1) / (float)s);
+                    target = (Real)(u2 * (float)s);
+                } else {
+                    const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
+                    const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
+                    const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
+                    const double u2 = (double)z2 * 0x1p-53;        // [0, 1)
+                    tau = -dlog(u1) / (double)s;
+                    target = (Real)(u2 * (double)s);
+                }
+                if (clock + tau > t_end) {
+                    have = false;  // the pending event is discarded
+                } else {
+                    uint32_t sel[W];
+                    select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
+                    apply_change<UMAX, W>(U, sel, x);
+                    clock = clock + tau;
+                    n = n + 1;
+                }
+            }
+        }
+        // Once at least refill_min lanes are idle (or all are), the idle
+        // lanes store what they hold and take the next particles of the
+        // pool, in lane order.
+        if (staged && next < p1) {
+            const uint64_t idle = __ballot(!have);
+            const int n_idle = (int)__popcll(idle);
+            if (n_idle >= refill_min || idle == ~0ull) {
+                if (!have) {
+                    if (pend) retire(true);
+                    pend = false;
+                    const int nj = next + (int)__popcll(idle & ((1ull << lane) - 1ull));
+                    if (nj < p1) {
+                        j = nj;
+                        have = true;
+                        pend = true;
+                        load_lds(j);
+                    }
+                }
+                next += n_idle;
+            }
+        }
+        if (__ballot(have) == 0ull) break;
+    }
+    if (staged) {
+        if (pend) retire(true);
+        __syncthreads();
+        // coalesced copy of the pool's counts
+#pragma unroll 1
+        for (int k = lane; k < npool; k += kPropBlock) {
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u)
+                if (u < U) dst[(size_t)u * Hp + p0 + k] = pool_x[u * npool + k];
+        }
+    } else if (pend) {
+        retire(false);
+    }
+    if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[f], st);
+    const uint64_t wev = wave_sum_u64(ev);
+    if (lane == 0 && wev) {
+        atomicAdd((unsigned long long *)&e.fevents[f], (unsigned long long)wev);
+        atomicAdd(&e.cost[f], (uint32_t)(wev > 0xFFFFFFFFull ? 0xFFFFFFFFu : wev));
     }
 }
 

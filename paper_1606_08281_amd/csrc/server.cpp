@@ -373,8 +373,10 @@ void worker_main(lik_server *S) {
             if (r->iterations_left <= 0) continue;
             r->iterations_left -= 1;
             if (r->iterations_left == 0) {
-                launch_finish(S->e, (int32_t)r->slot, r->n_theta, r->M, S->dev_loglik + r->slot,
-                              S->dev_status + r->slot, nullptr, S->stream);
+                if (launch_finish(S->e, (int32_t)r->slot, r->n_theta, r->M,
+                                  S->dev_loglik + r->slot, S->dev_status + r->slot, nullptr,
+                                  S->stream) != hipSuccess)
+                    S->worker_error = "finish launch failed";
                 (void)hipMemcpyAsync(S->res_loglik + r->slot, S->dev_loglik + r->slot,
                                      (size_t)r->n_theta * 8, hipMemcpyDeviceToHost, S->stream);
                 (void)hipMemcpyAsync(S->res_status + r->slot, S->dev_status + r->slot,
@@ -418,6 +420,7 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     if (hipGetDevice(&S->device) != hipSuccess) return fail(LIK_EDEVICE, "no current device");
     const size_t slots = (size_t)o.max_filters;
     const size_t table = align256(slots * sizeof(FilterDesc)) + 4 * align256(slots * 4) +
+                         align256(slots) +
                          2 * align256(slots * 8) + align256(slots * 64 * 4) +
                          align256(kMaxGroups * 4) + align256(slots * 8) + align256(slots * 4);
     hipError_t err = hipMalloc((void **)&S->dev_base, table + o.arena_bytes + 256);
@@ -441,6 +444,7 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->e.fstatus = (int32_t *)take(slots * 4);
     S->e.fflags = (uint32_t *)take(slots * 4);
     S->e.cost = (uint32_t *)take(slots * 4);
+    S->e.pool = (uint8_t *)take(slots);
     S->e.fll = (double *)take(slots * 8);
     S->e.fevents = (uint64_t *)take(slots * 8);
     S->e.items = (uint32_t *)take(slots * 64 * 4);
@@ -453,6 +457,11 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->res_status = (int32_t *)((char *)S->res_loglik + align256(slots * 8));
     S->slots.init(slots, 1);
     S->dmem.init(o.arena_bytes, 256);
+    S->e.pool_min = kDefaultTuning.pool_min;
+    S->e.pool_max = kDefaultTuning.pool_max;
+    S->e.pool_events = kDefaultTuning.pool_events;
+    S->e.pool_first = kDefaultTuning.pool_first;
+    S->e.refill_min = kDefaultTuning.refill_min;
     S->pmem.init(o.staging_bytes, 256);
     // every slot starts inactive (stopped), so stale slots are never ordered
     std::vector<uint32_t> stopped(slots, kFlagStopped);

@@ -23,7 +23,8 @@ MAX_OBSERVED = 8
 EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile", "lik_eval_batch",
             "lik_workspace_size", "lik_eval_batch_device", "lik_server_create",
             "lik_server_submit", "lik_server_wait", "lik_server_stats_get", "lik_server_destroy",
-            "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version"]
+            "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version",
+            "lik_network_set_tuning", "lik_network_get_tuning", "lik_autotune_device"]
 
 
 class LikError(RuntimeError):
@@ -52,6 +53,12 @@ class EvalOpts(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("propagate_ms", ctypes.c_double), ("propagate_launches", ctypes.c_int64),
                 ("weigh_ms", ctypes.c_double), ("weigh_launches", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("pool_min", ctypes.c_int32), ("pool_max", ctypes.c_int32),
+                ("pool_events", ctypes.c_uint32), ("pool_first", ctypes.c_int32),
+                ("refill_min", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -101,6 +108,13 @@ def lib():
         L.lik_create_network.restype = ctypes.c_int
         L.lik_network_precompile.argtypes = [vp, i32]
         L.lik_network_precompile.restype = ctypes.c_int
+        L.lik_network_set_tuning.argtypes = [vp, vp]
+        L.lik_network_set_tuning.restype = ctypes.c_int
+        L.lik_network_get_tuning.argtypes = [vp, vp]
+        L.lik_network_get_tuning.restype = ctypes.c_int
+        L.lik_autotune_device.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, u64, vp, vp, vp, sz,
+                                          vp, vp]
+        L.lik_autotune_device.restype = ctypes.c_int
         L.lik_destroy_network.argtypes = [vp]
         L.lik_destroy_network.restype = ctypes.c_int
         L.lik_eval_batch.argtypes = [vp, vp, vp, i32, vp, vp, i32, u64, vp, vp, vp]
@@ -151,6 +165,10 @@ def timing_read():
             "weigh_ms": t.weigh_ms, "weigh_launches": t.weigh_launches}
 
 
+def _tuning_dict(t):
+    return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+
 class Network:
     """A validated reaction network (reactant orders p_ru, net changes nu_ru)."""
 
@@ -166,6 +184,26 @@ class Network:
     def precompile(self, precision=FP64):
         """Compile the network-specialised kernel into the disk cache (no GPU)."""
         _check(lib().lik_network_precompile(self.handle, int(precision)))
+
+    def set_tuning(self, pool_min=None, pool_max=None, pool_events=None, pool_first=None,
+                   refill_min=None, default=False):
+        """Work partitioning of the propagation kernels (never changes results)."""
+        if default:
+            _check(lib().lik_network_set_tuning(self.handle, None))
+            return self.tuning()
+        t = Tuning(**self.tuning())
+        for k, v in (("pool_min", pool_min), ("pool_max", pool_max),
+                     ("pool_events", pool_events), ("pool_first", pool_first),
+                     ("refill_min", refill_min)):
+            if v is not None:
+                setattr(t, k, int(v))
+        _check(lib().lik_network_set_tuning(self.handle, ctypes.byref(t)))
+        return self.tuning()
+
+    def tuning(self):
+        t = Tuning()
+        _check(lib().lik_network_get_tuning(self.handle, ctypes.byref(t)))
+        return _tuning_dict(t)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -282,6 +320,24 @@ class DeviceBatch:
             self.H, int(seed) & (2**64 - 1), self.loglik.data_ptr(), self.status.data_ptr(),
             ctypes.byref(aux), ws, self.ws_bytes + 256, ctypes.c_void_p(s.cuda_stream)))
         return self.loglik, self.status
+
+    def autotune(self, theta_dev, seed, theta_ids_dev=None, stream=None):
+        """Time the candidate tunings on this batch (synchronous) and keep the
+        fastest as the network's tuning; returns it."""
+        torch = self.torch
+        assert theta_dev.dtype == torch.float64 and theta_dev.is_contiguous()
+        assert theta_dev.numel() == self.n_theta * self.net.R
+        s = stream if stream is not None else torch.cuda.current_stream()
+        opts = EvalOpts(self.precision, self.kernel, self.event_cap,
+                        None if theta_ids_dev is None else theta_ids_dev.data_ptr(), 0, 0)
+        t = Tuning()
+        _check(lib().lik_autotune_device(
+            self.net.handle, ctypes.byref(self.om), ctypes.byref(opts), self.n_theta,
+            theta_dev.data_ptr(), ctypes.byref(self.data), self.offsets_host.ctypes.data,
+            self.H, int(seed) & (2**64 - 1), self.loglik.data_ptr(), self.status.data_ptr(),
+            self.workspace.data_ptr(), self.ws_bytes + 256, ctypes.c_void_p(s.cuda_stream),
+            ctypes.byref(t)))
+        return _tuning_dict(t)
 
 
 class Server:

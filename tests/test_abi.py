@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from paper_1606_08281_amd import lik
+from paper_1606_08281_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -118,3 +119,18 @@ def test_precompile_specialized_kernels_without_gpu(tmp_path, monkeypatch):
     assert len([f for f in files if f.endswith(".co")]) == 6
     for f in files:
         assert b"gfx950" in open(os.path.join(tmp_path, f), "rb").read()
+
+
+def test_tuning_set_get_and_bounds():
+    net = lik.Network(*[np.asarray(a) for a in (W.telegraph().orders, W.telegraph().stoich)])
+    default = {"pool_min": 2, "pool_max": 2, "pool_events": 0, "pool_first": 2, "refill_min": 1}
+    assert net.tuning() == default
+    assert net.set_tuning(pool_min=1, pool_max=16, pool_events=100, pool_first=3,
+                          refill_min=9) == {"pool_min": 1, "pool_max": 16, "pool_events": 100,
+                                            "pool_first": 3, "refill_min": 9}
+    for bad in ({"pool_min": 0}, {"pool_min": 17}, {"pool_max": 65}, {"pool_first": 0},
+                {"pool_first": 65}, {"refill_min": 0}, {"refill_min": 65}):
+        with pytest.raises(lik.LikError):
+            net.set_tuning(**bad)
+    assert net.tuning()["pool_max"] == 16  # a rejected call changes nothing
+    assert net.set_tuning(default=True) == default

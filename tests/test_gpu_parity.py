@@ -234,3 +234,55 @@ def test_telegraph_full_batch_sampled(orc, precision):
     assert np.array_equal(events[idx].ravel(), ref["events"])
     assert np.all(np.abs(ll[idx] - ref["loglik"]) <= REL * np.abs(ref["loglik"]))
     assert np.all(st == 0) and np.all(np.isfinite(ll))
+
+
+TUNINGS = [dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=1),
+           dict(pool_min=2, pool_max=2, pool_events=0, pool_first=2, refill_min=1),
+           dict(pool_min=2, pool_max=8, pool_events=8192, pool_first=2, refill_min=7),
+           dict(pool_min=3, pool_max=5, pool_events=1, pool_first=7, refill_min=64),
+           dict(pool_min=64, pool_max=64, pool_events=0, pool_first=64, refill_min=33)]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_work_partitioning_never_changes_results(orc, kernel):
+    # pools of 1..64 groups of 64 particles per wavefront, lane refill in
+    # any order: every output is bit-identical, and the oracle agrees
+    from paper_1606_08281_amd import lik
+    wl, idx = _telegraph_subset(n_obs=20)
+    trajs = wl.trajectories[:2]
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    first = {}
+    for t in TUNINGS:
+        net.set_tuning(**t)
+        for H in (1000, 4096, 65):
+            _say("partitioning", t, "H", H, "kernel", kernel)
+            got = lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta[idx], trajs,
+                                 H, wl.seed, theta_ids=idx, aux=True, kernel=kernel)
+            if H not in first:
+                first[H] = got
+                continue
+            for k in ("loglik", "status", "filter_events", "filter_loglik", "final_state"):
+                assert np.array_equal(got[k], first[H][k], equal_nan=True), (t, H, k)
+    sub = idx[:4]
+    ref = _oracle(orc, wl, theta=wl.theta[sub], theta_ids=sub, trajectories=trajs)
+    net.set_tuning(**TUNINGS[-1])
+    assert_parity(lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta[sub], trajs,
+                                 wl.n_particles, wl.seed, theta_ids=sub, aux=True, kernel=kernel),
+                  ref)
+
+
+def test_autotune_picks_a_candidate_and_keeps_results():
+    import torch
+    from paper_1606_08281_amd import lik
+    wl = W.telegraph_workload(n_theta=64, n_traj=2, n_obs=10, n_particles=1000)
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
+                         wl.n_particles)
+    theta = torch.from_numpy(wl.theta).cuda()
+    ll0 = db.run(theta, wl.seed)[0].cpu().numpy()
+    _say("autotune 64x2x1000x10")
+    chosen = db.autotune(theta, wl.seed + 1)
+    torch.cuda.synchronize()
+    assert chosen == net.tuning()
+    assert 1 <= chosen["pool_min"] <= chosen["pool_max"] <= 64
+    assert np.array_equal(db.run(theta, wl.seed)[0].cpu().numpy(), ll0)
