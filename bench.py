@@ -92,7 +92,8 @@ def main():
                     help="time the candidate work partitionings on this batch first and keep "
                          "the fastest (default: the library's default partitioning)")
     ap.add_argument("--tuning", default=None,
-                    help="work partitioning pool_min,pool_max,pool_events,pool_first,refill_min "
+                    help="work partitioning pool_min,pool_max,pool_events,pool_first,refill_min,"
+                         "priority "
                          "(default: the library's)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 generic, 2 network-specialised propagation kernel")
@@ -126,7 +127,7 @@ def main():
           file=sys.stderr)
 
     if args.tuning:
-        keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min")
+        keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min", "priority")
         net.set_tuning(**dict(zip(keys, (int(v) for v in args.tuning.split(",")))))
     tuning = net.tuning()
     if args.autotune:

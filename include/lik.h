@@ -115,9 +115,11 @@ typedef struct lik_tuning {
     uint32_t pool_events;  /* target events per lane per work item */
     int32_t pool_first;    /* >= 1, <= 64 */
     int32_t refill_min;    /* idle lanes of a wavefront that trigger a refill, 1..64 */
+    int32_t priority;      /* 1: raise the wavefront priority of the filters whose
+                              particles needed the most events last interval; 0: off */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {2, 2, 0, 2, 1}) / reads a network's
+/* Sets (NULL: restores the defaults {2, 2, 0, 2, 1, 1}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

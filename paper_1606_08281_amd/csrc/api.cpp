@@ -155,9 +155,10 @@ int lik_network_set_tuning(lik_network_t net, const lik_tuning *t) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     lik_tuning v = t ? *t : kDefaultTuning;
     if (v.pool_min < 1 || v.pool_max < v.pool_min || v.pool_max > 64 || v.pool_first < 1 ||
-        v.pool_first > 64 || v.refill_min < 1 || v.refill_min > 64)
+        v.pool_first > 64 || v.refill_min < 1 || v.refill_min > 64 || v.priority < 0 ||
+        v.priority > 1)
         return fail(LIK_EINVAL, "tuning must satisfy 1 <= pool_min <= pool_max <= 64, "
-                                "1 <= pool_first <= 64, 1 <= refill_min <= 64");
+                                "1 <= pool_first <= 64, 1 <= refill_min <= 64, priority 0 or 1");
     net->tuning = v;
     return LIK_OK;
 }
@@ -175,13 +176,12 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
-        {1, 1, 0, 1, 1},        // one group of 64 particles per wavefront
-        {2, 2, 0, 2, 1},        // default
-        {2, 2, 0, 2, 8},
-        {3, 3, 0, 3, 1},
-        {4, 4, 0, 4, 1},
-        {4, 4, 0, 4, 16},
-        {1, 2, 1024, 1, 1},     // pools of two for filters below 512 events per particle
+        {1, 1, 0, 1, 1, 0},        // one group of 64 particles per wavefront
+        {2, 2, 0, 2, 1, 1},        // default
+        {3, 3, 0, 3, 1, 1},
+        {4, 4, 0, 4, 1, 1},
+        {1, 4, 2048, 1, 1, 1},     // pools of up to four for lighter filters
+        {2, 4, 512, 2, 1, 1},
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;
@@ -462,6 +462,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     L.e.pool_events = net->tuning.pool_events;
     L.e.pool_first = net->tuning.pool_first;
     L.e.refill_min = net->tuning.refill_min;
+    L.e.priority = net->tuning.priority;
 
     const int precision = opts ? opts->precision : LIK_FP64;
     const int variant = opts ? opts->kernel : LIK_KERNEL_AUTO;

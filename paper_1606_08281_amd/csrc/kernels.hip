@@ -44,6 +44,12 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // inclusive prefix sum over the 64 lanes of a wavefront
 __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
     const int lane = threadIdx.x & 63;
@@ -77,11 +83,12 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
     d.y = r.y + (size_t)off * r.P;
     d.x0 = r.x0 + (size_t)m * r.U;
     const size_t per = (size_t)r.U * r.Hp;
-    int32_t *st = r.state + (size_t)k * (2 * per + 3 * (size_t)r.Hp);
+    int32_t *st = r.state + (size_t)k * (2 * per + 4 * (size_t)r.Hp);
     d.xa = st;
     d.xb = st + per;
     d.lw = (double *)(st + 2 * per);  // 8-byte aligned: per and Hp are multiples of 64
     d.anc = st + 2 * per + 2 * (size_t)r.Hp;
+    d.pev = (uint32_t *)(st + 2 * per + 3 * (size_t)r.Hp);
     d.t0 = r.t0[m];
     d.sigma = r.sigma;
     d.seed = r.seed;
@@ -129,14 +136,16 @@ __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c)
         g = (int)min(want, (uint32_t)e.pool_max);
         g = max(g, e.pool_min);
     }
-    const int lds_cap = kPoolLdsWords / (kPropBlock * e.desc[f].U);  // pool counts fit in LDS
+    const int lds_cap = kPoolLdsWords / (kPropBlock * (e.desc[f].U + 1));  // pool fits in LDS
     g = min(g, lds_cap);
     return min(max(g, 1), nchunk);
 }
 
 __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
     __shared__ uint32_t hist[kMaxGroups * kCostKeys];
+    __shared__ uint32_t max_per;  // most events per particle of any slot, last interval
     for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x) hist[k] = 0;
+    if (threadIdx.x == 0) max_per = 0;
     __syncthreads();
     for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x) {
         if (!slot_active(e, f)) continue;
@@ -145,6 +154,7 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
         const int nchunk = e.desc[f].Hp >> 6;
         const int g = pool_size(e, f, c);
         atomicAdd(&hist[e.desc[f].group * kCostKeys + key], (uint32_t)((nchunk + g - 1) / g));
+        atomicMax(&max_per, c / (uint32_t)e.desc[f].H);
     }
     __syncthreads();
     if (threadIdx.x < kMaxGroups) {
@@ -167,8 +177,14 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
         const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
         const uint32_t pos = atomicAdd(&hist[e.desc[f].group * kCostKeys + key], n_items);
         for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);
-        e.pool[f] = (uint8_t)g;
-        e.cost[f] = 0;  // re-accumulated by this iteration's propagation
+        // Wavefront priority: the slots whose particles needed the most
+        // events are the ones the iteration waits for; their wavefronts
+        // issue first on a SIMD they share with lighter ones.
+        const uint32_t per = c / (uint32_t)e.desc[f].H;
+        int prio = 0;
+        if (e.priority && per > 0)
+            prio = (uint64_t)per * 4u >= max_per ? 3 : (uint64_t)per * 32u >= max_per ? 1 : 0;
+        e.pool[f] = (uint8_t)((prio << 6) | (g - 1));
     }
 }
 
@@ -201,7 +217,21 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     const int T = d.T;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int H = d.H;
-    __syncthreads();  // every thread has read tcur before thread 0 advances it
+    // events of the interval: the filter's total and its ordering cost
+    {
+        uint64_t evs = 0;
+        for (int j = tid; j < H; j += kWeighBlock) evs += d.pev[j];
+        evs = wave_sum_u64(evs);
+        if (lane == 0) redu[wave] = evs;
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t tot = 0;
+            for (int w = 0; w < kWeighBlock / 64; ++w) tot += redu[w];
+            e.fevents[f] += tot;
+            e.cost[f] = (uint32_t)(tot > 0xFFFFFFFFull ? 0xFFFFFFFFull : tot);
+        }
+    }
+    __syncthreads();  // every thread has read tcur and redu before thread 0 moves on
     if (e.fstatus[f] != LIK_STATUS_OK) {
         if (tid == 0) {
             e.tcur[f] = t + 1;
@@ -366,7 +396,7 @@ __global__ void k_aux_state(EngineArgs e, int32_t base, int32_t F, int32_t *out)
 // launchers
 // ---------------------------------------------------------------------------
 size_t request_state_bytes(int64_t F, int32_t U, int32_t Hp) {
-    return (size_t)F * (2 * (size_t)U * Hp + 3 * (size_t)Hp) * sizeof(int32_t);
+    return (size_t)F * (2 * (size_t)U * Hp + 4 * (size_t)Hp) * sizeof(int32_t);
 }
 
 hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs &r,

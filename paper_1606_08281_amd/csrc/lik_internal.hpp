@@ -22,10 +22,10 @@ constexpr int kMaxGroups = 16;    // (network, precision) groups per iteration
 constexpr int kCostKeys = 33;     // bit length of last-interval events, 0..32
 constexpr uint32_t kFlagStopped = 1u;
 constexpr int32_t kCountLimit = 1 << 30;
-// LDS that stages a pool's ancestor counts, per wavefront (4 KiB: 32
-// wavefronts per CU still fit in its 160 KiB).  A pool holds G * 64 * U
-// counts, so G <= kPoolLdsWords / (64 U).
-constexpr int kPoolLdsWords = 1024;
+// LDS that holds a pool, per wavefront (5 KiB: 32 wavefronts per CU still
+// fit in its 160 KiB).  A pool takes U + 1 words per particle (counts,
+// events), so G <= kPoolLdsWords / (64 (U + 1)).
+constexpr int kPoolLdsWords = 1280;
 
 // Reaction kinds after validation of the reactant orders.
 enum : int32_t { kOrder0 = 0, kOrder1 = 1, kOrder2Homo = 2, kOrder2Hetero = 3 };
@@ -52,6 +52,7 @@ struct FilterDesc {
     int32_t *xb;           // [U][Hp] counts after odd-numbered intervals
     double *lw;            // [Hp] particle log-weights (particle-dependent part)
     int32_t *anc;          // [Hp] ancestors for the next interval
+    uint32_t *pev;         // [Hp] events of each particle in the last interval
     double t0;             // start time
     double sigma;          // observation noise scale
     uint64_t seed;         // Philox key
@@ -75,7 +76,7 @@ struct EngineArgs {
     uint32_t *fflags;         // [slots]
     uint64_t *fevents;        // [slots] SSA events applied
     uint32_t *cost;           // [slots] events of the last interval (ordering key)
-    uint8_t *pool;            // [slots] particles per work item / 64 this interval
+    uint8_t *pool;            // [slots] (wave priority << 6) | (particles per item / 64 - 1)
     uint32_t *items;          // propagation work items (slot << 6 | chunk), grouped
     uint32_t *item_count;     // [kMaxGroups] items written per group
     int32_t f_lo, f_hi;       // slot range that may hold active filters
@@ -84,7 +85,7 @@ struct EngineArgs {
     uint32_t pool_events;
     int32_t pool_min, pool_max, pool_first;
     int32_t refill_min;       // idle lanes that trigger a refill from the pool
-    int32_t pad0;
+    int32_t priority;         // raise the wave priority of the heaviest slots
     uint32_t group_off[kMaxGroups];  // first item of each group
 };
 

@@ -11,12 +11,6 @@
 
 namespace lik {
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Propensities a_r = c_r h_r(x) and their running sums S_r in reaction
 // order (h_r = prod_u C(x_u, p_ru)); returns S_{R-1}.  Real is double for the
 // binary64 step; for the binary32 step the factor h_r (exact in binary64) is
@@ -113,7 +107,9 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     const int Hp = d.Hp;
     const int lane = (int)threadIdx.x;
     const int p0 = (int)(item & 63u) * kPropBlock;
-    const int p1 = min(p0 + (int)e.pool[f] * kPropBlock, H);
+    const int pool = e.pool[f];  // (priority << 6) | (G - 1)
+    const int p1 = min(p0 + ((pool & 63) + 1) * kPropBlock, H);
+
     const double t_start = (t == 0) ? d.t0 : d.t_obs[t - 1];
     const double t_end = d.t_obs[t];
     const uint32_t c2 = (d.traj << 16) | (uint32_t)t;
@@ -125,6 +121,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     // could alias the descriptor as far as the compiler knows.
     const uint32_t event_cap = d.event_cap;
     const int32_t *anc_p = d.anc;
+    uint32_t *pev_p = d.pev;
     const int32_t *x0_p = d.x0;
     const int refill_min = e.refill_min;
 
@@ -133,27 +130,30 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? (Real)d.theta[r] : (Real)0;
 
-    // A pool of more than 64 particles lives in LDS ([u][particle - p0]): its
-    // ancestors' counts are staged there first, a lane taking a new particle
-    // reads them from there, a finished particle's counts replace them, and
-    // the pool is copied out at the end.  The event loop then touches no
-    // global memory, so it never waits on it.  (Only such pools refill: a
-    // pool of at most 64 particles has one per lane.)
-    __shared__ int32_t pool_x[kPoolLdsWords];
+    // A pool of more than 64 particles lives in LDS: per particle its counts
+    // ([u][particle - p0]) and its event count.  The ancestors' counts are
+    // staged there first, a lane taking a new particle reads it from there,
+    // a finished particle's counts and events replace it, and the pool is
+    // copied out at the end: the event loop touches no global memory, so it
+    // never waits on it.  (Only such pools refill: a pool of at most 64 has
+    // one particle per lane.)
+    __shared__ int32_t pool_lds[kPoolLdsWords];
     const int npool = p1 - p0;
     const bool staged = npool > kPropBlock;
+    int32_t *pool_x = pool_lds;                                // [U][npool]
+    uint32_t *pool_n = (uint32_t *)(pool_lds + U * npool);     // [npool]
     if (staged) {
 #pragma unroll 1
-        for (int k = lane; k < npool; k += kPropBlock) {
+        for (int q = lane; q < npool; q += kPropBlock) {
             if (t == 0) {
 #pragma unroll
                 for (int u = 0; u < UMAX; ++u)
-                    if (u < U) pool_x[u * npool + k] = x0_p[u];
+                    if (u < U) pool_x[u * npool + q] = x0_p[u];
             } else {
-                const int a = anc_p[p0 + k];
+                const int a = anc_p[p0 + q];
 #pragma unroll
                 for (int u = 0; u < UMAX; ++u)
-                    if (u < U) pool_x[u * npool + k] = src[(size_t)u * Hp + a];
+                    if (u < U) pool_x[u * npool + q] = src[(size_t)u * Hp + a];
             }
         }
         __syncthreads();  // the workgroup is this one wavefront
@@ -162,7 +162,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     int x[UMAX];
     double clock = t_start;
     uint32_t n = 0;
-    int j = p0 + lane;
+    int j = p0 + lane;  // the lane's particle
     bool have = j < p1;
     auto load_lds = [&](int jj) {
 #pragma unroll
@@ -183,29 +183,34 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
         }
     }
     int next = p0 + kPropBlock;  // first particle of the pool no lane has taken (uniform)
-    bool pend = have;            // the lane holds counts not stored yet
-    uint64_t ev = 0;
+    bool pend = have;            // the lane holds a particle not stored yet
     int st = LIK_STATUS_OK;
     Real S[RMAX];
-    // a finished particle: overflow check, events, and its counts into the
-    // pool's LDS slot (staged) or straight to global memory
+    // a finished particle: overflow check, and its counts and events into
+    // the pool's LDS slot (staged) or straight to global memory
     auto retire = [&](bool to_lds) {
 #pragma unroll
         for (int u = 0; u < UMAX; ++u)
             if (u < U && x[u] > kCountLimit)
                 st = st > LIK_STATUS_COUNT_OVERFLOW ? st : LIK_STATUS_COUNT_OVERFLOW;
-        ev += n;
         if (to_lds) {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u)
                 if (u < U) pool_x[u * npool + (j - p0)] = x[u];
+            pool_n[j - p0] = n;
         } else {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u)
                 if (u < U) dst[(size_t)u * Hp + j] = x[u];
+            pev_p[j] = n;
         }
     };
 
+    if ((pool >> 6) == 3) {
+        __builtin_amdgcn_s_setprio(3);
+    } else if ((pool >> 6) == 1) {
+        __builtin_amdgcn_s_setprio(1);
+    }
     for (;;) {
         if (have) {
             const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
@@ -269,22 +274,18 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     if (staged) {
         if (pend) retire(true);
         __syncthreads();
-        // coalesced copy of the pool's counts
+        // coalesced copy of the pool's counts and events
 #pragma unroll 1
-        for (int k = lane; k < npool; k += kPropBlock) {
+        for (int q = lane; q < npool; q += kPropBlock) {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u)
-                if (u < U) dst[(size_t)u * Hp + p0 + k] = pool_x[u * npool + k];
+                if (u < U) dst[(size_t)u * Hp + p0 + q] = pool_x[u * npool + q];
+            pev_p[p0 + q] = pool_n[q];
         }
     } else if (pend) {
         retire(false);
     }
     if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[f], st);
-    const uint64_t wev = wave_sum_u64(ev);
-    if (lane == 0 && wev) {
-        atomicAdd((unsigned long long *)&e.fevents[f], (unsigned long long)wev);
-        atomicAdd(&e.cost[f], (uint32_t)(wev > 0xFFFFFFFFull ? 0xFFFFFFFFu : wev));
-    }
 }
 
 }  // namespace lik
