@@ -103,9 +103,10 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
  * Work partitioning of the propagation kernels (never changes a result).
  * A wavefront runs a pool of G * 64 particles of one filter and hands a lane
  * the next particle of its pool as soon as the lane's particle reaches the
- * observation time.  Per filter and interval, G = clamp(pool_events / (events
- * per particle in the filter's previous interval), pool_min, pool_max), and
- * pool_first in the first interval; G is at most H / 64 rounded up, and at
+ * observation time.  Per filter and interval, G = clamp(pool_events / e,
+ * pool_min, pool_max), where e is the expected number of events per particle
+ * (the total propensity of the particles' starting states times the
+ * interval's length), and pool_first in the first interval; G is at most H / 64 rounded up, and at
  * most 16 / U (the pool's counts are staged in 4 KiB of LDS).  Idle lanes
  * take new particles once refill_min of them are idle.
  */
@@ -116,10 +117,10 @@ typedef struct lik_tuning {
     int32_t pool_first;    /* >= 1, <= 64 */
     int32_t refill_min;    /* idle lanes of a wavefront that trigger a refill, 1..64 */
     int32_t priority;      /* 1: raise the wavefront priority of the filters whose
-                              particles needed the most events last interval; 0: off */
+                              particles are expected to need the most events; 0: off */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {2, 2, 0, 2, 1, 1}) / reads a network's
+/* Sets (NULL: restores the defaults {2, 4, 1024, 2, 1, 0}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

@@ -176,12 +176,13 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
+        {2, 4, 1024, 2, 1, 0},     // default
         {1, 1, 0, 1, 1, 0},        // one group of 64 particles per wavefront
-        {2, 2, 0, 2, 1, 1},        // default
-        {3, 3, 0, 3, 1, 1},
-        {4, 4, 0, 4, 1, 1},
-        {1, 4, 2048, 1, 1, 1},     // pools of up to four for lighter filters
+        {2, 2, 0, 2, 1, 0},
+        {1, 4, 1024, 1, 1, 0},
+        {2, 4, 2048, 2, 1, 0},
         {2, 4, 512, 2, 1, 1},
+        {4, 4, 0, 4, 1, 0},
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;

@@ -15,7 +15,7 @@
 
 namespace lik {
 // Work partitioning used unless a caller sets another (lik_network_set_tuning).
-constexpr lik_tuning kDefaultTuning = {2, 2, 0, 2, 1, 1};
+constexpr lik_tuning kDefaultTuning = {2, 4, 1024, 2, 1, 0};
 }  // namespace lik
 
 struct lik_network {

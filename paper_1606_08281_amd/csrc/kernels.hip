@@ -3,8 +3,8 @@
 // One engine iteration advances every active filter slot by one observation
 // interval:
 //   k_order: the work list.  Active slots, grouped by (network, precision),
-//     heaviest first by the events their particles needed in the previous
-//     interval; each slot contributes one item per 64 particles.
+//     heaviest first by the events their particles are expected to need;
+//     each slot contributes one item per pool of G * 64 particles.
 //   k_propagate (body in propagate.hpp): one wavefront per item, a pool of
 //     particles of one slot.  Gathers each particle's ancestor state and runs
 //     Gillespie's direct method from the previous observation time to the
@@ -39,6 +39,12 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -83,12 +89,13 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
     d.y = r.y + (size_t)off * r.P;
     d.x0 = r.x0 + (size_t)m * r.U;
     const size_t per = (size_t)r.U * r.Hp;
-    int32_t *st = r.state + (size_t)k * (2 * per + 4 * (size_t)r.Hp);
+    int32_t *st = r.state + (size_t)k * (2 * per + 5 * (size_t)r.Hp);
     d.xa = st;
     d.xb = st + per;
     d.lw = (double *)(st + 2 * per);  // 8-byte aligned: per and Hp are multiples of 64
     d.anc = st + 2 * per + 2 * (size_t)r.Hp;
     d.pev = (uint32_t *)(st + 2 * per + 3 * (size_t)r.Hp);
+    d.pa0 = (float *)(st + 2 * per + 4 * (size_t)r.Hp);
     d.t0 = r.t0[m];
     d.sigma = r.sigma;
     d.seed = r.seed;
@@ -121,9 +128,9 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
 
 // ---------------------------------------------------------------------------
 // order: a counting sort of the active slots over (group, cost key), cost
-// key = 32 - bit length of the previous interval's events (0 = heaviest).
-// Order inside a key is arbitrary: it only changes which wavefront starts
-// first, never a result.
+// key = 32 - bit length of the slot's expected events in the coming interval
+// (0 = heaviest), and the pool size of each slot.  Order inside a key is
+// arbitrary: it only changes which wavefront starts first, never a result.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c) {
     const int nchunk = e.desc[f].Hp >> 6;
@@ -131,19 +138,19 @@ __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c)
     if (e.tcur[f] == 0) {
         g = e.pool_first;
     } else {
-        const uint32_t per = c / (uint32_t)e.desc[f].H;  // events per particle last interval
+        const uint32_t per = c / (uint32_t)e.desc[f].H;  // expected events per particle
         const uint32_t want = e.pool_events / (per > 0 ? per : 1u);
         g = (int)min(want, (uint32_t)e.pool_max);
         g = max(g, e.pool_min);
     }
-    const int lds_cap = kPoolLdsWords / (kPropBlock * (e.desc[f].U + 1));  // pool fits in LDS
+    const int lds_cap = kPoolLdsWords / (kPropBlock * (e.desc[f].U + 2));  // pool fits in LDS
     g = min(g, lds_cap);
     return min(max(g, 1), nchunk);
 }
 
 __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
     __shared__ uint32_t hist[kMaxGroups * kCostKeys];
-    __shared__ uint32_t max_per;  // most events per particle of any slot, last interval
+    __shared__ uint32_t max_per;  // most expected events per particle of any slot
     for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x) hist[k] = 0;
     if (threadIdx.x == 0) max_per = 0;
     __syncthreads();
@@ -177,9 +184,9 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
         const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
         const uint32_t pos = atomicAdd(&hist[e.desc[f].group * kCostKeys + key], n_items);
         for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);
-        // Wavefront priority: the slots whose particles needed the most
-        // events are the ones the iteration waits for; their wavefronts
-        // issue first on a SIMD they share with lighter ones.
+        // Wavefront priority: the slots whose particles are expected to need
+        // the most events are the ones the iteration waits for; their
+        // wavefronts issue first on a SIMD they share with lighter ones.
         const uint32_t per = c / (uint32_t)e.desc[f].H;
         int prio = 0;
         if (e.priority && per > 0)
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     const int T = d.T;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int H = d.H;
-    // events of the interval: the filter's total and its ordering cost
+    // events of the interval into the filter's total
     {
         uint64_t evs = 0;
         for (int j = tid; j < H; j += kWeighBlock) evs += d.pev[j];
@@ -228,7 +235,6 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
             uint64_t tot = 0;
             for (int w = 0; w < kWeighBlock / 64; ++w) tot += redu[w];
             e.fevents[f] += tot;
-            e.cost[f] = (uint32_t)(tot > 0xFFFFFFFFull ? 0xFFFFFFFFull : tot);
         }
     }
     __syncthreads();  // every thread has read tcur and redu before thread 0 moves on
@@ -337,6 +343,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     const uint64_t Q = Cs[H - 1];
     const uint64_t rho = __umul64hi(bcast_u, Q);
     const uint64_t Hu = (uint64_t)H;
+    float pred = 0.0f;  // sum of the ancestors' total propensities
     for (int jj = tid; jj < H; jj += kWeighBlock) {
         const uint64_t point = (uint64_t)jj * Q + rho;
         int lo = 0, hi = H - 1;
@@ -346,6 +353,20 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
             else lo = mid + 1;
         }
         d.anc[jj] = lo;
+        pred += d.pa0[lo];
+    }
+    // Ordering cost of the next interval: the events its particles are
+    // expected to need, total propensity of their starting states times the
+    // interval's length (a scheduling estimate only).
+    pred = wave_sum_f32(pred);
+    __syncthreads();  // red[] reuse
+    if (lane == 0) red[wave] = (double)pred;
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kWeighBlock / 64; ++w) tot += red[w];
+        const double expect = tot * (d.t_obs[t + 1] - d.t_obs[t]);
+        e.cost[f] = expect >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)expect;
     }
 }
 
@@ -396,7 +417,7 @@ __global__ void k_aux_state(EngineArgs e, int32_t base, int32_t F, int32_t *out)
 // launchers
 // ---------------------------------------------------------------------------
 size_t request_state_bytes(int64_t F, int32_t U, int32_t Hp) {
-    return (size_t)F * (2 * (size_t)U * Hp + 4 * (size_t)Hp) * sizeof(int32_t);
+    return (size_t)F * (2 * (size_t)U * Hp + 5 * (size_t)Hp) * sizeof(int32_t);
 }
 
 hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs &r,

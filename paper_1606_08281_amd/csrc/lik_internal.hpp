@@ -22,10 +22,10 @@ constexpr int kMaxGroups = 16;    // (network, precision) groups per iteration
 constexpr int kCostKeys = 33;     // bit length of last-interval events, 0..32
 constexpr uint32_t kFlagStopped = 1u;
 constexpr int32_t kCountLimit = 1 << 30;
-// LDS that holds a pool, per wavefront (5 KiB: 32 wavefronts per CU still
-// fit in its 160 KiB).  A pool takes U + 1 words per particle (counts,
-// events), so G <= kPoolLdsWords / (64 (U + 1)).
-constexpr int kPoolLdsWords = 1280;
+// LDS that holds a pool, per wavefront (6 KiB: 24 wavefronts per CU still
+// fit in its 160 KiB).  A pool takes U + 2 words per particle (counts,
+// events, final propensity), so G <= kPoolLdsWords / (64 (U + 2)).
+constexpr int kPoolLdsWords = 1536;
 
 // Reaction kinds after validation of the reactant orders.
 enum : int32_t { kOrder0 = 0, kOrder1 = 1, kOrder2Homo = 2, kOrder2Hetero = 3 };
@@ -53,6 +53,8 @@ struct FilterDesc {
     double *lw;            // [Hp] particle log-weights (particle-dependent part)
     int32_t *anc;          // [Hp] ancestors for the next interval
     uint32_t *pev;         // [Hp] events of each particle in the last interval
+    float *pa0;            // [Hp] total propensity at each particle's state at the
+                           //      last observation time (cost prediction)
     double t0;             // start time
     double sigma;          // observation noise scale
     uint64_t seed;         // Philox key
@@ -75,7 +77,7 @@ struct EngineArgs {
     int32_t *fstatus;         // [slots]
     uint32_t *fflags;         // [slots]
     uint64_t *fevents;        // [slots] SSA events applied
-    uint32_t *cost;           // [slots] events of the last interval (ordering key)
+    uint32_t *cost;           // [slots] expected events of the next interval (ordering key)
     uint8_t *pool;            // [slots] (wave priority << 6) | (particles per item / 64 - 1)
     uint32_t *items;          // propagation work items (slot << 6 | chunk), grouped
     uint32_t *item_count;     // [kMaxGroups] items written per group

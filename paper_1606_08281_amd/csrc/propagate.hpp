@@ -122,6 +122,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     const uint32_t event_cap = d.event_cap;
     const int32_t *anc_p = d.anc;
     uint32_t *pev_p = d.pev;
+    float *pa0_p = d.pa0;
     const int32_t *x0_p = d.x0;
     const int refill_min = e.refill_min;
 
@@ -131,7 +132,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? (Real)d.theta[r] : (Real)0;
 
     // A pool of more than 64 particles lives in LDS: per particle its counts
-    // ([u][particle - p0]) and its event count.  The ancestors' counts are
+    // ([u][particle - p0]), its event count and its final total propensity.  The ancestors' counts are
     // staged there first, a lane taking a new particle reads it from there,
     // a finished particle's counts and events replace it, and the pool is
     // copied out at the end: the event loop touches no global memory, so it
@@ -142,6 +143,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     const bool staged = npool > kPropBlock;
     int32_t *pool_x = pool_lds;                                // [U][npool]
     uint32_t *pool_n = (uint32_t *)(pool_lds + U * npool);     // [npool]
+    float *pool_a = (float *)(pool_lds + (U + 1) * npool);     // [npool]
     if (staged) {
 #pragma unroll 1
         for (int q = lane; q < npool; q += kPropBlock) {
@@ -186,8 +188,10 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     bool pend = have;            // the lane holds a particle not stored yet
     int st = LIK_STATUS_OK;
     Real S[RMAX];
-    // a finished particle: overflow check, and its counts and events into
-    // the pool's LDS slot (staged) or straight to global memory
+    float a0_end = 0.0f;  // total propensity at the particle's last state
+    // a finished particle: overflow check, and its counts, events and final
+    // total propensity into the pool's LDS slot (staged) or straight to
+    // global memory
     auto retire = [&](bool to_lds) {
 #pragma unroll
         for (int u = 0; u < UMAX; ++u)
@@ -198,11 +202,13 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
             for (int u = 0; u < UMAX; ++u)
                 if (u < U) pool_x[u * npool + (j - p0)] = x[u];
             pool_n[j - p0] = n;
+            pool_a[j - p0] = a0_end;
         } else {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u)
                 if (u < U) dst[(size_t)u * Hp + j] = x[u];
             pev_p[j] = n;
+            pa0_p[j] = a0_end;
         }
     };
 
@@ -214,6 +220,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     for (;;) {
         if (have) {
             const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
+            a0_end = (float)s;
             if (!(s > (Real)0)) {
                 have = false;  // no reaction can fire before the observation
             } else if (n >= event_cap) {
@@ -274,13 +281,14 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     if (staged) {
         if (pend) retire(true);
         __syncthreads();
-        // coalesced copy of the pool's counts and events
+        // coalesced copy of the pool's counts, events and propensities
 #pragma unroll 1
         for (int q = lane; q < npool; q += kPropBlock) {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u)
                 if (u < U) dst[(size_t)u * Hp + p0 + q] = pool_x[u * npool + q];
             pev_p[p0 + q] = pool_n[q];
+            pa0_p[p0 + q] = pool_a[q];
         }
     } else if (pend) {
         retire(false);
