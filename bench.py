@@ -93,7 +93,7 @@ def main():
                          "the fastest (default: the library's default partitioning)")
     ap.add_argument("--tuning", default=None,
                     help="work partitioning pool_min,pool_max,pool_events,pool_first,refill_min,"
-                         "priority "
+                         "priority,items_per_cu "
                          "(default: the library's)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 generic, 2 network-specialised propagation kernel")
@@ -127,7 +127,8 @@ def main():
           file=sys.stderr)
 
     if args.tuning:
-        keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min", "priority")
+        keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min", "priority",
+                "items_per_cu")
         net.set_tuning(**dict(zip(keys, (int(v) for v in args.tuning.split(",")))))
     tuning = net.tuning()
     if args.autotune:
@@ -183,10 +184,26 @@ def main():
                           f64_seed_to_seed=diff(ll64b, ll64))
         del db64
 
+    # HBM bytes per launch from the committed rocprofv3 counter summary of
+    # this kernel and configuration; null once the kernel sources differ.
+    traffic = None
+    if (args.precision == 0 and args.kernel in (0, 2) and not args.tuning and not args.autotune):
+        from paper_1606_08281_amd import profsum
+        rec = profsum.read_traffic(os.path.join(
+            ROOT, "profiles", "lik_propagate_spec_traffic_telegraph_1024x10x1000x50_fp64.txt"))
+        if rec is not None:
+            traffic = float(rec["hbm_bytes_per_launch"])
+
     evals = wl.n_theta * args.steps
     ope = ops_per_event(wl.net.R, wl.net.U, args.precision)
     prop_s = tm["propagate_ms"] / 1e3
-    achieved = events * ope / prop_s / 1e12 if prop_s > 0 else None
+    # A replayed graph records no per-kernel events: its roofline is taken
+    # over the whole step instead (a lower bound for the kernel's).
+    basis = "propagation kernel time (HIP events on its stream)"
+    if prop_s <= 0:
+        prop_s = elapsed
+        basis = "whole step time (graph replay: no per-kernel events)"
+    achieved = events * ope / prop_s / 1e12
     peak = VALU_PEAK_LANE_OPS / 1e12
     out = {
         "metric": "likelihood evals/s",
@@ -218,9 +235,11 @@ def main():
                                "weigh_resample": tm["weigh_ms"] / args.steps},
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
-            "frac": achieved / peak if achieved else None, "traffic": None,
-            "kernel": "k_propagate (direct-method SSA + log-weight)",
+            "frac": achieved / peak, "traffic": traffic,
+            "kernel": "k_propagate (direct-method SSA to the next observation)",
+            "basis": basis,
             "ops_per_event": ope,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": tm["propagate_ms"] / max(tm["propagate_launches"], 1),
             "launches": tm["propagate_launches"],
         },

@@ -118,9 +118,11 @@ typedef struct lik_tuning {
     int32_t refill_min;    /* idle lanes of a wavefront that trigger a refill, 1..64 */
     int32_t priority;      /* 1: raise the wavefront priority of the filters whose
                               particles are expected to need the most events; 0: off */
+    int32_t items_per_cu;  /* pools grow only while an iteration keeps at least this
+                              many work items per compute unit (>= 0; 0: always) */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {2, 4, 1024, 2, 1, 0}) / reads a network's
+/* Sets (NULL: restores the defaults {2, 4, 1024, 2, 1, 0, 160}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

@@ -132,7 +132,7 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
 // (0 = heaviest), and the pool size of each slot.  Order inside a key is
 // arbitrary: it only changes which wavefront starts first, never a result.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c) {
+__device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c, int g_par) {
     const int nchunk = e.desc[f].Hp >> 6;
     int g;
     if (e.tcur[f] == 0) {
@@ -144,22 +144,33 @@ __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c)
         g = max(g, e.pool_min);
     }
     const int lds_cap = kPoolLdsWords / (kPropBlock * (e.desc[f].U + 2));  // pool fits in LDS
-    g = min(g, lds_cap);
+    g = min(min(g, lds_cap), g_par);
     return min(max(g, 1), nchunk);
 }
 
 __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
     __shared__ uint32_t hist[kMaxGroups * kCostKeys];
     __shared__ uint32_t max_per;  // most expected events per particle of any slot
+    __shared__ uint32_t chunks;   // groups of 64 particles over all active slots
     for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x) hist[k] = 0;
-    if (threadIdx.x == 0) max_per = 0;
+    if (threadIdx.x == 0) {
+        max_per = 0;
+        chunks = 0;
+    }
     __syncthreads();
+    for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x)
+        if (slot_active(e, f)) atomicAdd(&chunks, (uint32_t)(e.desc[f].Hp >> 6));
+    __syncthreads();
+    // Pools only when the iteration has work to spare: at most
+    // chunks / pool_min_items groups per pool, so that a small batch still
+    // spreads its particles over as many wavefronts as it can.
+    const int g_par = (int)max(1u, chunks / max(e.pool_min_items, 1u));
     for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x) {
         if (!slot_active(e, f)) continue;
         const uint32_t c = e.cost[f];
         const int key = 32 - (c == 0 ? 0 : 32 - __clz(c));
         const int nchunk = e.desc[f].Hp >> 6;
-        const int g = pool_size(e, f, c);
+        const int g = pool_size(e, f, c, g_par);
         atomicAdd(&hist[e.desc[f].group * kCostKeys + key], (uint32_t)((nchunk + g - 1) / g));
         atomicMax(&max_per, c / (uint32_t)e.desc[f].H);
     }
@@ -180,7 +191,7 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
         const uint32_t c = e.cost[f];
         const int key = 32 - (c == 0 ? 0 : 32 - __clz(c));
         const int nchunk = e.desc[f].Hp >> 6;
-        const int g = pool_size(e, f, c);
+        const int g = pool_size(e, f, c, g_par);
         const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
         const uint32_t pos = atomicAdd(&hist[e.desc[f].group * kCostKeys + key], n_items);
         for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);

@@ -88,6 +88,8 @@ struct EngineArgs {
     int32_t pool_min, pool_max, pool_first;
     int32_t refill_min;       // idle lanes that trigger a refill from the pool
     int32_t priority;         // raise the wave priority of the heaviest slots
+    uint32_t pool_min_items;  // work items an iteration keeps before pools grow
+    int32_t pad0;
     uint32_t group_off[kMaxGroups];  // first item of each group
 };
 

@@ -463,6 +463,7 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->e.pool_first = kDefaultTuning.pool_first;
     S->e.refill_min = kDefaultTuning.refill_min;
     S->e.priority = kDefaultTuning.priority;
+    S->e.pool_min_items = (uint32_t)kDefaultTuning.items_per_cu * compute_units();
     S->pmem.init(o.staging_bytes, 256);
     // every slot starts inactive (stopped), so stale slots are never ordered
     std::vector<uint32_t> stopped(slots, kFlagStopped);

@@ -58,7 +58,8 @@ class Timing(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("pool_min", ctypes.c_int32), ("pool_max", ctypes.c_int32),
                 ("pool_events", ctypes.c_uint32), ("pool_first", ctypes.c_int32),
-                ("refill_min", ctypes.c_int32), ("priority", ctypes.c_int32)]
+                ("refill_min", ctypes.c_int32), ("priority", ctypes.c_int32),
+                ("items_per_cu", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -186,7 +187,7 @@ class Network:
         _check(lib().lik_network_precompile(self.handle, int(precision)))
 
     def set_tuning(self, pool_min=None, pool_max=None, pool_events=None, pool_first=None,
-                   refill_min=None, priority=None, default=False):
+                   refill_min=None, priority=None, items_per_cu=None, default=False):
         """Work partitioning of the propagation kernels (never changes results)."""
         if default:
             _check(lib().lik_network_set_tuning(self.handle, None))
@@ -194,7 +195,8 @@ class Network:
         t = Tuning(**self.tuning())
         for k, v in (("pool_min", pool_min), ("pool_max", pool_max),
                      ("pool_events", pool_events), ("pool_first", pool_first),
-                     ("refill_min", refill_min), ("priority", priority)):
+                     ("refill_min", refill_min), ("priority", priority),
+                     ("items_per_cu", items_per_cu)):
             if v is not None:
                 setattr(t, k, int(v))
         _check(lib().lik_network_set_tuning(self.handle, ctypes.byref(t)))

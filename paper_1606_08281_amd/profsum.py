@@ -1,0 +1,188 @@
+"""Summaries of rocprofv3 output for the profiles/ folder, and the source
+fingerprint that ties a hardware-counter reading to the kernel it was taken on.
+
+  python -m paper_1606_08281_amd.profsum --stats DIR --fetch DIR --write DIR \\
+      [--util DIR] --bench BENCH_JSON --out profiles/NAME.md --traffic profiles/NAME.txt
+
+DIR arguments are rocprofv3 output folders written with --output-format csv
+(--kernel-trace --stats for --stats; --pmc FETCH_SIZE / WRITE_SIZE /
+VALUBusy VALUUtilization for the others, each run with bench.py
+--copy-calibration so that a device-to-device copy of 1 GiB is in the same
+trace).  FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by
+the ratio of the copy's known bytes to what the counter read for it.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+COPY_BYTES = 1 << 30  # bench.py --copy-calibration: 2^28 float32 copied device to device
+
+# Sources that decide what the propagation kernel executes and how work is cut
+# into pools (and so its memory traffic).
+KERNEL_SOURCES = ["paper_1606_08281_amd/csrc/propagate.hpp",
+                  "paper_1606_08281_amd/csrc/devmath.hpp",
+                  "paper_1606_08281_amd/csrc/lik_internal.hpp",
+                  "paper_1606_08281_amd/csrc/kernels.hip",
+                  "paper_1606_08281_amd/csrc/specialize.cpp",
+                  "paper_1606_08281_amd/csrc/host.hpp",
+                  "include/lik.h"]
+
+
+def source_sha256():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _kind(name):
+    if "propagate" in name:
+        return "lik_propagate_spec" if "spec" in name else "lik::k_propagate"
+    for k in ("k_order", "k_weigh", "k_admit", "k_finish", "k_aux_filters", "k_aux_state"):
+        if k in name:
+            return "lik::" + k
+    if "copyBuffer" in name:
+        return "__amd_rocclr_copyBuffer"
+    if "reduce_kernel" in name:
+        return "torch reduce"
+    if "elementwise" in name:
+        return "torch elementwise"
+    return name[:40]
+
+
+def _one(pattern):
+    hits = glob.glob(pattern, recursive=True)
+    if not hits:
+        raise FileNotFoundError(pattern)
+    return hits[0]
+
+
+def kernel_stats(stats_dir):
+    rows = list(csv.DictReader(open(_one(os.path.join(stats_dir, "**", "*kernel_stats.csv")))))
+    out = []
+    for r in rows:
+        out.append({"kernel": _kind(r["Name"]), "calls": int(r["Calls"]),
+                    "total_ms": float(r["TotalDurationNs"]) / 1e6,
+                    "avg_us": float(r["AverageNs"]) / 1e3, "min_us": float(r["MinNs"]) / 1e3,
+                    "max_us": float(r["MaxNs"]) / 1e3, "pct": float(r["Percentage"])})
+    return out
+
+
+def counter_means(pmc_dir):
+    """{(kernel kind, counter): (mean per dispatch, dispatches)}"""
+    rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "**",
+                                                      "*counter_collection.csv")))))
+    acc = {}
+    for r in rows:
+        key = (_kind(r["Kernel_Name"]), r["Counter_Name"])
+        acc.setdefault(key, []).append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def counter_sum(pmc_dir, kind, counter):
+    rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "**",
+                                                      "*counter_collection.csv")))))
+    return sum(float(r["Counter_Value"]) for r in rows
+               if _kind(r["Kernel_Name"]) == kind and r["Counter_Name"] == counter)
+
+
+def traffic(fetch_dir, write_dir, kernel="lik_propagate_spec"):
+    fetch_copy_kib = counter_sum(fetch_dir, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    write_copy_kib = counter_sum(write_dir, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    fs = COPY_BYTES / (fetch_copy_kib * 1024.0)
+    ws = COPY_BYTES / (write_copy_kib * 1024.0)
+    f_kib, n_f = counter_means(fetch_dir)[(kernel, "FETCH_SIZE")]
+    w_kib, n_w = counter_means(write_dir)[(kernel, "WRITE_SIZE")]
+    fb = f_kib * 1024.0 * fs
+    wb = w_kib * 1024.0 * ws
+    return {"fetch_copy_kib": fetch_copy_kib, "write_copy_kib": write_copy_kib,
+            "fetch_scale": fs, "write_scale": ws, "fetch_kib_per_launch": f_kib,
+            "write_kib_per_launch": w_kib, "launches": min(n_f, n_w),
+            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+            "hbm_bytes_per_launch": fb + wb}
+
+
+def read_traffic(path):
+    """Traffic record written by this module, or None if absent or taken on
+    other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("source_sha256") != source_sha256():
+        return None
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--util")
+    ap.add_argument("--bench", required=True, help="bench.py JSON line of the same configuration")
+    ap.add_argument("--title", default="lik_propagate_spec — telegraph 1024 theta x 10 traj x "
+                                       "1000 particles x 50 obs (FP64)")
+    ap.add_argument("--commands", required=True, help="text file with the commands that ran")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic", required=True)
+    a = ap.parse_args()
+
+    stats = kernel_stats(a.stats)
+    tr = traffic(a.fetch, a.write)
+    bench = json.loads(open(a.bench).read().strip().splitlines()[-1])
+    util = counter_means(a.util) if a.util else {}
+    sha = source_sha256()
+    lines = [f"# {a.title}", "",
+             "Engine iteration = k_order + lik_propagate_spec + k_weigh; 50 iterations per "
+             "bench step.", "", "Commands (repository root on one MI355X, `R` = its path):", "",
+             "```"] + open(a.commands).read().strip().splitlines() + ["```", "",
+             "Kernel statistics (rocprofv3 --kernel-trace --stats):", "",
+             "| kernel | calls | total ms | average us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|"]
+    for s in stats:
+        lines.append(f"| {s['kernel']} | {s['calls']} | {s['total_ms']:.2f} | {s['avg_us']:.1f} | "
+                     f"{s['min_us']:.1f} | {s['max_us']:.1f} | {s['pct']:.3f} |")
+    rl = bench["roofline"]
+    lines += ["", f"bench.py, same configuration: {bench['value']:.1f} evals/s, "
+                  f"{bench['ms_per_step']:.1f} ms per step; propagation average per launch "
+                  f"{rl['avg_launch_ms']:.3f} ms (HIP events on the launch stream); VALU "
+                  f"fraction {rl['frac']:.3f} of {rl['peak']:.2f} T lane-op/s at "
+                  f"{rl['ops_per_event']} lane-ops per event.", "",
+              "HBM traffic of lik_propagate_spec (rocprofv3 --pmc, one pass per counter):", "",
+              f"- copy calibration (1 GiB device-to-device): FETCH_SIZE read "
+              f"{tr['fetch_copy_kib']:.0f} KiB -> scale {tr['fetch_scale']:.4f}; WRITE_SIZE read "
+              f"{tr['write_copy_kib']:.0f} KiB -> scale {tr['write_scale']:.4f}",
+              f"- per launch ({tr['launches']} launches): FETCH_SIZE {tr['fetch_kib_per_launch']:.0f}"
+              f" KiB -> {tr['fetch_bytes_per_launch'] / 1e6:.1f} MB; WRITE_SIZE "
+              f"{tr['write_kib_per_launch']:.0f} KiB -> {tr['write_bytes_per_launch'] / 1e6:.1f} MB;"
+              f" total {tr['hbm_bytes_per_launch'] / 1e6:.1f} MB"]
+    if util:
+        lines += ["", "Utilisation counters (mean per dispatch):", ""]
+        for (k, c), (v, n) in sorted(util.items()):
+            if k in ("lik_propagate_spec", "lik::k_weigh", "lik::k_order"):
+                lines.append(f"- {k} {c}: {v:.2f} ({n} dispatches)")
+    lines += ["", f"Kernel sources fingerprint (sha256): {sha}", ""]
+    open(a.out, "w").write("\n".join(lines))
+    with open(a.traffic, "w") as f:
+        f.write("# HBM traffic of lik_propagate_spec per launch, telegraph 1024x10x1000x50 FP64,\n"
+                "# default work partitioning; read by bench.py while the kernel sources match.\n")
+        f.write(f"source_sha256: {sha}\n")
+        for k in ("fetch_scale", "write_scale", "fetch_bytes_per_launch",
+                  "write_bytes_per_launch", "hbm_bytes_per_launch"):
+            f.write(f"{k}: {tr[k]:.6g}\n")
+    print(a.out, a.traffic)
+
+
+if __name__ == "__main__":
+    main()
