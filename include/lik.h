@@ -122,7 +122,7 @@ typedef struct lik_tuning {
                               many work items per compute unit (>= 0; 0: always) */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {2, 4, 1024, 2, 1, 0, 160}) / reads a network's
+/* Sets (NULL: restores the defaults {1, 4, 1024, 1, 1, 0, 160}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */
@@ -265,6 +265,7 @@ typedef struct lik_server_opts {
     int32_t kernel;         /* LIK_KERNEL_GENERIC or LIK_KERNEL_SPECIALIZED (default, 0) */
     int32_t max_inflight;   /* iterations enqueued ahead of the GPU; 0 = 2 */
     int32_t reserved;       /* must be 0 */
+    const lik_tuning *tuning; /* work partitioning for every iteration; NULL = defaults */
 } lik_server_opts;
 
 typedef struct lik_request {

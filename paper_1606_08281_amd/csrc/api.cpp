@@ -28,6 +28,18 @@ int lik::hip_fail(hipError_t e, const char *where) {
     return fail(LIK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+bool lik::tuning_valid(const lik_tuning &v) {
+    return v.pool_min >= 1 && v.pool_max >= v.pool_min && v.pool_max <= 64 &&
+           v.pool_first >= 1 && v.pool_first <= 64 && v.refill_min >= 1 && v.refill_min <= 64 &&
+           (v.priority == 0 || v.priority == 1) && v.items_per_cu >= 0 &&
+           v.items_per_cu <= (1 << 20);
+}
+
+const char *lik::tuning_rule() {
+    return "tuning must satisfy 1 <= pool_min <= pool_max <= 64, 1 <= pool_first <= 64, "
+           "1 <= refill_min <= 64, priority 0 or 1, 0 <= items_per_cu <= 2^20";
+}
+
 uint32_t lik::compute_units() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -163,12 +175,7 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
 int lik_network_set_tuning(lik_network_t net, const lik_tuning *t) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     lik_tuning v = t ? *t : kDefaultTuning;
-    if (v.pool_min < 1 || v.pool_max < v.pool_min || v.pool_max > 64 || v.pool_first < 1 ||
-        v.pool_first > 64 || v.refill_min < 1 || v.refill_min > 64 || v.priority < 0 ||
-        v.priority > 1 || v.items_per_cu < 0 || v.items_per_cu > (1 << 20))
-        return fail(LIK_EINVAL, "tuning must satisfy 1 <= pool_min <= pool_max <= 64, "
-                                "1 <= pool_first <= 64, 1 <= refill_min <= 64, priority 0 or 1, "
-                                "0 <= items_per_cu <= 2^20");
+    if (!tuning_valid(v)) return fail(LIK_EINVAL, tuning_rule());
     net->tuning = v;
     return LIK_OK;
 }
@@ -186,13 +193,13 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
-        {2, 4, 1024, 2, 1, 0, 160},     // default
+        {1, 4, 1024, 1, 1, 0, 160},     // default
+        {2, 4, 1024, 1, 1, 0, 160},
         {1, 1, 0, 1, 1, 0, 0},          // one group of 64 particles per wavefront
         {2, 2, 0, 2, 1, 0, 160},
-        {1, 4, 1024, 1, 1, 0, 160},
-        {2, 4, 2048, 2, 1, 0, 160},
-        {2, 4, 1024, 2, 1, 0, 40},
-        {2, 4, 1024, 2, 1, 0, 640},
+        {1, 4, 2048, 1, 1, 0, 320},
+        {2, 4, 512, 1, 1, 1, 160},
+        {4, 4, 0, 4, 1, 0, 160},
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;
@@ -475,6 +482,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     L.e.refill_min = net->tuning.refill_min;
     L.e.priority = net->tuning.priority;
     L.e.pool_min_items = (uint32_t)net->tuning.items_per_cu * compute_units();
+    L.e.h_max = H;
 
     const int precision = opts ? opts->precision : LIK_FP64;
     const int variant = opts ? opts->kernel : LIK_KERNEL_AUTO;

@@ -15,7 +15,7 @@
 
 namespace lik {
 // Work partitioning used unless a caller sets another (lik_network_set_tuning).
-constexpr lik_tuning kDefaultTuning = {2, 4, 1024, 2, 1, 0, 160};
+constexpr lik_tuning kDefaultTuning = {1, 4, 1024, 1, 1, 0, 160};
 }  // namespace lik
 
 struct lik_network {
@@ -70,6 +70,8 @@ void release_specialized(lik_network &net);
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
 uint32_t compute_units();  // of the current device
+bool tuning_valid(const lik_tuning &t);
+const char *tuning_rule();
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Argument checks shared by the entry points.

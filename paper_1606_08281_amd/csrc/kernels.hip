@@ -222,8 +222,9 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate(EngineArgs e, int grou
 // rho = floor(w64 Q / 2^64) and ancestors a_j = min{i : H C_{i+1} > j Q + rho}.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
-    __shared__ uint64_t Cs[LIK_MAX_PARTICLES];  // Cs[k] = C_{k+1}
+    extern __shared__ uint64_t Cs[];  // [h_max]: Cs[k] = C_{k+1}
     __shared__ double red[kWeighBlock / 64];
+    __shared__ double logy[LIK_MAX_OBSERVED];
     __shared__ uint64_t redu[kWeighBlock / 64];
     __shared__ double bcast;
     __shared__ uint64_t bcast_u;
@@ -263,6 +264,8 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     const int j1 = min(j0 + per, H);
     const int32_t *xs = (t & 1) ? d.xa : d.xb;  // counts at the observation time
     const double *yt = d.y + (size_t)t * d.P;
+    if (tid < d.P) logy[tid] = d.obs_kind == LIK_OBS_LOGNORMAL ? dlog(yt[tid]) : 0.0;
+    __syncthreads();
 
     // particle-dependent part of log p(y_t | x_j) (the "Compute l_t^i" step),
     // kept in lw for this thread's second pass; and the maximum
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
                     l = -__builtin_inf();
                     break;
                 }
-                const double z = (dlog(yt[k]) - dlog((double)cnt)) / d.sigma;
+                const double z = (logy[k] - dlog((double)cnt)) / d.sigma;
                 l = l - 0.5 * (z * z);
             } else {
                 const double z = (yt[k] - (double)cnt) / d.sigma;
@@ -473,7 +476,9 @@ hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, co
 
 hipError_t launch_weigh(const EngineArgs &e, hipStream_t s) {
     if (e.f_hi <= e.f_lo) return hipSuccess;
-    hipLaunchKernelGGL(k_weigh, dim3((unsigned)(e.f_hi - e.f_lo)), dim3(kWeighBlock), 0, s, e);
+    if (e.h_max < 1 || e.h_max > LIK_MAX_PARTICLES) return hipErrorInvalidValue;
+    const size_t lds = (size_t)e.h_max * sizeof(uint64_t);  // the prefix sums C
+    hipLaunchKernelGGL(k_weigh, dim3((unsigned)(e.f_hi - e.f_lo)), dim3(kWeighBlock), lds, s, e);
     return hipGetLastError();
 }
 

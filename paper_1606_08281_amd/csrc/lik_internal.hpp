@@ -89,7 +89,7 @@ struct EngineArgs {
     int32_t refill_min;       // idle lanes that trigger a refill from the pool
     int32_t priority;         // raise the wave priority of the heaviest slots
     uint32_t pool_min_items;  // work items an iteration keeps before pools grow
-    int32_t pad0;
+    int32_t h_max;            // most particles of any active slot (LDS of k_weigh)
     uint32_t group_off[kMaxGroups];  // first item of each group
 };
 

@@ -355,8 +355,13 @@ void worker_main(lik_server *S) {
         // one iteration over every resident filter
         GroupLaunch launches[kMaxGroups];
         unsigned need[kMaxGroups] = {0};
+        int32_t h_max = 1;
         for (auto &r : S->resident)
-            if (r->iterations_left > 0) need[r->group] += (unsigned)(r->F() * (r->Hp / 64));
+            if (r->iterations_left > 0) {
+                need[r->group] += (unsigned)(r->F() * (r->Hp / 64));
+                h_max = std::max(h_max, r->H);
+            }
+        S->e.h_max = h_max;
         unsigned off = 0;
         for (int g = 0; g < kMaxGroups; ++g) {
             launches[g] = S->groups[g].launch;
@@ -407,6 +412,7 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     *out = nullptr;
     lik_server_opts o = opts ? *opts : lik_server_opts{0, 0, 0, 0, 0, 0};
     if (o.reserved != 0) return fail(LIK_EINVAL, "reserved must be 0");
+    if (o.tuning && !tuning_valid(*o.tuning)) return fail(LIK_EINVAL, tuning_rule());
     if (o.kernel != 0 && o.kernel != LIK_KERNEL_GENERIC && o.kernel != LIK_KERNEL_SPECIALIZED)
         return fail(LIK_EINVAL, "unknown kernel variant");
     if (o.arena_bytes == 0) o.arena_bytes = (size_t)1 << 30;
@@ -457,13 +463,14 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->res_status = (int32_t *)((char *)S->res_loglik + align256(slots * 8));
     S->slots.init(slots, 1);
     S->dmem.init(o.arena_bytes, 256);
-    S->e.pool_min = kDefaultTuning.pool_min;
-    S->e.pool_max = kDefaultTuning.pool_max;
-    S->e.pool_events = kDefaultTuning.pool_events;
-    S->e.pool_first = kDefaultTuning.pool_first;
-    S->e.refill_min = kDefaultTuning.refill_min;
-    S->e.priority = kDefaultTuning.priority;
-    S->e.pool_min_items = (uint32_t)kDefaultTuning.items_per_cu * compute_units();
+    const lik_tuning tu = o.tuning ? *o.tuning : kDefaultTuning;
+    S->e.pool_min = tu.pool_min;
+    S->e.pool_max = tu.pool_max;
+    S->e.pool_events = tu.pool_events;
+    S->e.pool_first = tu.pool_first;
+    S->e.refill_min = tu.refill_min;
+    S->e.priority = tu.priority;
+    S->e.pool_min_items = (uint32_t)tu.items_per_cu * compute_units();
     S->pmem.init(o.staging_bytes, 256);
     // every slot starts inactive (stopped), so stale slots are never ordered
     std::vector<uint32_t> stopped(slots, kFlagStopped);

@@ -65,7 +65,8 @@ class Tuning(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_size_t), ("staging_bytes", ctypes.c_size_t),
                 ("max_filters", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_inflight", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tuning", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -346,9 +347,19 @@ class Server:
     """Continuous-batching server (lik_server_*): requests of any network,
     particle count and trajectory length share the GPU as they arrive."""
 
-    def __init__(self, arena_bytes=0, staging_bytes=0, max_filters=0, kernel=0, max_inflight=0):
+    def __init__(self, arena_bytes=0, staging_bytes=0, max_filters=0, kernel=0, max_inflight=0,
+                 tuning=None):
+        """tuning: dict of lik_tuning fields (missing ones take the defaults)."""
+        self._tuning = None
+        tp = None
+        if tuning is not None:
+            t = dict(pool_min=1, pool_max=4, pool_events=1024, pool_first=1, refill_min=1,
+                     priority=0, items_per_cu=160)
+            t.update(tuning)
+            self._tuning = Tuning(**{k: int(v) for k, v in t.items()})
+            tp = ctypes.addressof(self._tuning)
         o = ServerOpts(int(arena_bytes), int(staging_bytes), int(max_filters), int(kernel),
-                       int(max_inflight), 0)
+                       int(max_inflight), 0, tp)
         h = ctypes.c_void_p()
         _check(lib().lik_server_create(ctypes.byref(o), ctypes.byref(h)))
         self.handle = h

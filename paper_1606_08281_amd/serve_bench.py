@@ -85,9 +85,9 @@ def run_plain(reqs, nets, arrivals=None):
     return time.perf_counter() - t0, np.array(lat)
 
 
-def run_server(reqs, nets, arrivals=None):
+def run_server(reqs, nets, arrivals=None, tuning=None):
     lat = np.zeros(len(reqs))
-    with lik.Server(arena_bytes=8 << 30, kernel=lik.KERNEL_SPECIALIZED) as srv:
+    with lik.Server(arena_bytes=8 << 30, kernel=lik.KERNEL_SPECIALIZED, tuning=tuning) as srv:
         t0 = time.perf_counter()
         tickets = [None] * len(reqs)
         sub_t = np.zeros(len(reqs))
@@ -142,7 +142,15 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=512)
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the plain path's saturated rate")
+    ap.add_argument("--tuning", default=None,
+                    help="server work partitioning pool_min,pool_max,pool_events,pool_first,"
+                         "refill_min,priority,items_per_cu (default: the library's)")
     args = ap.parse_args()
+    tuning = None
+    if args.tuning:
+        keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min", "priority",
+                "items_per_cu")
+        tuning = dict(zip(keys, (int(v) for v in args.tuning.split(","))))
     import torch
     torch.cuda.set_device(0)
     reqs = uneven_batch() if args.uneven else request_stream(args.requests)
@@ -154,11 +162,16 @@ def main():
             nets[wl.name].precompile(lik.FP64)
     n_evals = sum(len(r["theta"]) for r in reqs)
     if args.uneven:
-        run_server(reqs[:8], nets)
+        run_server(reqs[:8], nets, tuning=tuning)
         print("[serve] warm", flush=True, file=sys.stderr)
-        t_srv, lat, st = run_server(reqs, nets)
+        t_srv, lat, st = run_server(reqs, nets, tuning=tuning)
         print(f"[serve] uneven batch served in {t_srv:.2f} s", flush=True, file=sys.stderr)
         sample = reqs[:args.plain_sample]
+        if args.plain_sample == 0:
+            out = {"requests": len(reqs), "makespan_s": t_srv, "server_evals_per_s": n_evals / t_srv,
+                   "tuning": tuning}
+            print(json.dumps(out), flush=True)
+            return
         t_plain, _ = run_plain(sample, nets)
         out = {"metric": "uneven batch: likelihood evals/s, makespan, p50/p99 completion",
                "requests": len(reqs), "makespan_s": t_srv, "server_evals_per_s": n_evals / t_srv,
@@ -173,17 +186,17 @@ def main():
         return
     # warm both paths (kernel loads, allocator)
     run_plain(reqs[:4], nets)
-    run_server(reqs[:4], nets)
+    run_server(reqs[:4], nets, tuning=tuning)
     print("[serve] warm", flush=True, file=sys.stderr)
     t_plain, _ = run_plain(reqs, nets)
     print(f"[serve] plain saturated {n_evals / t_plain:.1f} evals/s", flush=True, file=sys.stderr)
-    t_srv, _, st_sat = run_server(reqs, nets)
+    t_srv, _, st_sat = run_server(reqs, nets, tuning=tuning)
     print(f"[serve] server saturated {n_evals / t_srv:.1f} evals/s", flush=True, file=sys.stderr)
     rate = args.load * len(reqs) / t_plain   # requests per second
     arrivals = np.cumsum(np.random.default_rng(6).exponential(1.0 / rate, len(reqs)))
     tp, lat_p = run_plain(reqs, nets, arrivals)
     print("[serve] plain at load done", flush=True, file=sys.stderr)
-    ts, lat_s, st = run_server(reqs, nets, arrivals)
+    ts, lat_s, st = run_server(reqs, nets, arrivals, tuning=tuning)
     print("[serve] server at load done", flush=True, file=sys.stderr)
     equal = check_equal(reqs, nets)
     out = {

@@ -45,13 +45,15 @@ def _alone(lik, req, nets):
                           req["trajs"], req["H"], req["seed"], precision=int(req["precision"]))
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
-def test_served_results_equal_alone(kernel):
+@pytest.mark.parametrize("kernel,tuning", [
+    (1, None), (2, None),
+    (2, dict(pool_min=4, pool_max=4, pool_first=4, items_per_cu=0, refill_min=5, priority=1))])
+def test_served_results_equal_alone(kernel, tuning):
     from paper_1606_08281_amd import lik
     reqs = _mixed_requests()
     nets = {r["wl"].name: lik.Network(r["wl"].net.orders, r["wl"].net.stoich) for r in reqs}
-    _say("server mixed requests, kernel", kernel)
-    with lik.Server(arena_bytes=256 << 20, kernel=kernel) as srv:
+    _say("server mixed requests, kernel", kernel, "tuning", tuning)
+    with lik.Server(arena_bytes=256 << 20, kernel=kernel, tuning=tuning) as srv:
         tickets = []
         for k, r in enumerate(reqs):
             wl = r["wl"]
@@ -114,3 +116,9 @@ def test_concurrent_clients_and_shutdown():
                            64, 11)
     got = np.concatenate([results[c][0] for c in range(8)])
     assert np.array_equal(got, whole["loglik"])
+
+
+def test_server_rejects_invalid_tuning():
+    from paper_1606_08281_amd import lik
+    with pytest.raises(lik.LikError):
+        lik.Server(arena_bytes=64 << 20, tuning=dict(pool_min=0))
