@@ -127,11 +127,21 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
 }
 
 // ---------------------------------------------------------------------------
-// order: a counting sort of the active slots over (group, cost key), cost
-// key = 32 - bit length of the slot's expected events in the coming interval
-// (0 = heaviest), and the pool size of each slot.  Order inside a key is
-// arbitrary: it only changes which wavefront starts first, never a result.
+// order: the pool size of each slot, and a counting sort of the active slots
+// over (group, duration key): the expected events per lane of the slot's
+// work items (expected events per particle times the groups per pool), in
+// quarter octaves, longest first.  Order inside a key is arbitrary: it only
+// changes which wavefront starts first, never a result.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int duration_key(uint64_t c) {
+    if (c == 0) return kCostKeys - 1;
+    if (c > 0xFFFFFFFFull) c = 0xFFFFFFFFull;
+    const uint32_t v = (uint32_t)c;
+    const int b = 32 - __clz(v);  // bit length, 1..32
+    const int frac = b >= 3 ? (int)((v >> (b - 3)) & 3u) : (int)((v << (3 - b)) & 3u);
+    return 4 * (32 - b) + (3 - frac);  // 0 = longest
+}
+
 __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c, int g_par) {
     const int nchunk = e.desc[f].Hp >> 6;
     int g;
@@ -168,9 +178,9 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
     for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x) {
         if (!slot_active(e, f)) continue;
         const uint32_t c = e.cost[f];
-        const int key = 32 - (c == 0 ? 0 : 32 - __clz(c));
         const int nchunk = e.desc[f].Hp >> 6;
         const int g = pool_size(e, f, c, g_par);
+        const int key = duration_key((uint64_t)(c / (uint32_t)e.desc[f].H) * (uint64_t)g);
         atomicAdd(&hist[e.desc[f].group * kCostKeys + key], (uint32_t)((nchunk + g - 1) / g));
         atomicMax(&max_per, c / (uint32_t)e.desc[f].H);
     }
@@ -189,9 +199,9 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
     for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x) {
         if (!slot_active(e, f)) continue;
         const uint32_t c = e.cost[f];
-        const int key = 32 - (c == 0 ? 0 : 32 - __clz(c));
         const int nchunk = e.desc[f].Hp >> 6;
         const int g = pool_size(e, f, c, g_par);
+        const int key = duration_key((uint64_t)(c / (uint32_t)e.desc[f].H) * (uint64_t)g);
         const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
         const uint32_t pos = atomicAdd(&hist[e.desc[f].group * kCostKeys + key], n_items);
         for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);

@@ -19,7 +19,7 @@ namespace lik {
 constexpr int kPropBlock = 64;    // one wavefront per propagation work item
 constexpr int kWeighBlock = 256;  // one workgroup per filter for weights/resampling
 constexpr int kMaxGroups = 16;    // (network, precision) groups per iteration
-constexpr int kCostKeys = 33;     // bit length of last-interval events, 0..32
+constexpr int kCostKeys = 129;    // quarter octaves of expected events per lane, and zero
 constexpr uint32_t kFlagStopped = 1u;
 constexpr int32_t kCountLimit = 1 << 30;
 // LDS that holds a pool, per wavefront (6 KiB: 24 wavefronts per CU still

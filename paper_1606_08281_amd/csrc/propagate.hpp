@@ -67,6 +67,17 @@ __device__ __forceinline__ void apply_change(int U, const uint32_t *sel, int *x)
         if (u < U) x[u] += __builtin_amdgcn_sbfe(sel[u >> 3], 4 * (u & 7), 4);
 }
 
+// A value equal on every lane, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+
 template <bool B, class T, class F>
 struct pick_type {
     using type = T;
@@ -127,9 +138,10 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     const int refill_min = e.refill_min;
 
     using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
+    // Rates are the same for the whole wavefront: kept in scalar registers.
     Real c[RMAX];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? (Real)d.theta[r] : (Real)0;
+    for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? wave_uniform((Real)d.theta[r]) : (Real)0;
 
     // A pool of more than 64 particles lives in LDS: per particle its counts
     // ([u][particle - p0]), its event count and its final total propensity.  The ancestors' counts are
