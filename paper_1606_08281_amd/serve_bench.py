@@ -1,10 +1,13 @@
 """Served likelihood requests: continuous batching against plain per-request
 launches on one MI355X.
 
-The request stream mixes the telegraph and immigration-death networks: each
-request is a batch of 1-32 rate vectors (drawn from the prior, as a level-set
-sampler emits them in a proposal round) against 1-3 trajectories of 10-50
-observations, with 128-1000 filter particles and its own seed.
+The request stream mixes three networks: telegraph (60 %: 1-32 rate vectors
+drawn from the prior, as a level-set sampler emits them in a proposal round,
+against 1-3 trajectories of 10-50 observations, 128-1000 filter particles),
+immigration-death (20 %: 1-32 rate vectors, one trajectory of 10-20
+observations) and the 20-species, 40-reaction random network (20 %: 1-8 rate
+vectors, its trajectory of 100 observations, 512 particles); each request has
+its own seed.
 
   1. saturation: all requests submitted at once, to the server and, one after
      another, to lik_eval_batch (plain launches per request);
@@ -34,18 +37,21 @@ def request_stream(n, seed=13):
     rng = np.random.default_rng(seed)
     tel = W.telegraph_workload(n_theta=2048, n_traj=3, n_obs=50, n_particles=1000)
     imm = W.immigration_death_workload(n_theta=2048, n_particles=256)
+    rnd = W.random_network_workload(n_theta=2048)
     reqs = []
     for k in range(n):
-        use_tel = rng.random() < 0.7
-        wl = tel if use_tel else imm
-        n_theta = int(rng.integers(1, 33))
+        u = rng.random()
+        wl = tel if u < 0.6 else imm if u < 0.8 else rnd
+        n_theta = int(rng.integers(1, 9 if wl is rnd else 33))
         start = int(rng.integers(0, wl.n_theta - n_theta))
-        M = int(rng.integers(1, 4)) if use_tel else 1
-        T = int(rng.integers(10, 51)) if use_tel else int(rng.integers(10, 21))
+        M = int(rng.integers(1, 4)) if wl is tel else 1
+        T = (int(rng.integers(10, 51)) if wl is tel else int(rng.integers(10, 21)) if wl is imm
+             else 100)
+        H = 512 if wl is rnd else int(rng.choice([128, 512, 1000]))
         trajs = [dict(tr, t_obs=tr["t_obs"][:T], y=tr["y"][:T]) for tr in wl.trajectories[:M]]
         reqs.append(dict(wl=wl, theta=wl.theta[start:start + n_theta],
                          ids=np.arange(start, start + n_theta, dtype=np.uint32), trajs=trajs,
-                         H=int(rng.choice([128, 512, 1000])), seed=int(1000 + k)))
+                         H=H, seed=int(1000 + k)))
     return reqs
 
 
@@ -213,8 +219,10 @@ def main():
                               "p99_ms": float(np.percentile(lat_p, 99) * 1e3)}},
         "server_stats": st,
         "served_equals_alone": equal,
-        "workload": "mixed telegraph (70%) and immigration-death requests: 1-32 theta, 1-3 "
-                    "trajectories, 10-50 observations, H in {128, 512, 1000}; FP64",
+        "workload": "telegraph (60%: 1-32 theta, 1-3 trajectories, 10-50 observations, H in "
+                    "{128, 512, 1000}), immigration-death (20%: 1-32 theta, 10-20 observations) "
+                    "and random 20x40 network (20%: 1-8 theta, 100 observations, H 512) "
+                    "requests; FP64",
     }
     print(json.dumps(out), flush=True)
 
