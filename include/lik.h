@@ -120,9 +120,12 @@ typedef struct lik_tuning {
                               particles are expected to need the most events; 0: off */
     int32_t items_per_cu;  /* pools grow only while an iteration keeps at least this
                               many work items per compute unit (>= 0; 0: always) */
+    int32_t persistent;    /* 1: networks of at most 16 reactions run a persistent
+                              kernel whose lanes move on to the next work item when
+                              their pool runs out; 0: one wavefront per work item */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {1, 4, 1024, 1, 1, 0, 160}) / reads a network's
+/* Sets (NULL: restores the defaults {1, 4, 1024, 1, 1, 0, 160, 0}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

@@ -32,13 +32,16 @@ bool lik::tuning_valid(const lik_tuning &v) {
     return v.pool_min >= 1 && v.pool_max >= v.pool_min && v.pool_max <= 64 &&
            v.pool_first >= 1 && v.pool_first <= 64 && v.refill_min >= 1 && v.refill_min <= 64 &&
            (v.priority == 0 || v.priority == 1) && v.items_per_cu >= 0 &&
-           v.items_per_cu <= (1 << 20);
+           v.items_per_cu <= (1 << 20) && (v.persistent == 0 || v.persistent == 1);
 }
 
 const char *lik::tuning_rule() {
     return "tuning must satisfy 1 <= pool_min <= pool_max <= 64, 1 <= pool_first <= 64, "
-           "1 <= refill_min <= 64, priority 0 or 1, 0 <= items_per_cu <= 2^20";
+           "1 <= refill_min <= 64, priority 0 or 1, 0 <= items_per_cu <= 2^20, "
+           "persistent 0 or 1";
 }
+
+unsigned lik::persistent_waves() { return compute_units() * 32u; }
 
 uint32_t lik::compute_units() {
     int dev = 0, cus = 0;
@@ -193,13 +196,13 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
-        {1, 4, 1024, 1, 1, 0, 160},     // default
-        {2, 4, 1024, 1, 1, 0, 160},
-        {1, 1, 0, 1, 1, 0, 0},          // one group of 64 particles per wavefront
-        {2, 2, 0, 2, 1, 0, 160},
-        {1, 4, 2048, 1, 1, 0, 320},
-        {2, 4, 512, 1, 1, 1, 160},
-        {4, 4, 0, 4, 1, 0, 160},
+        {1, 4, 1024, 1, 1, 0, 160, 0},     // default
+        {2, 4, 1024, 1, 1, 0, 160, 0},
+        {1, 1, 0, 1, 1, 0, 0, 0},          // one group of 64 particles per wavefront
+        {1, 4, 2048, 1, 1, 0, 320, 0},
+        {1, 4, 1024, 1, 1, 0, 160, 1},     // persistent wavefronts (R <= 16)
+        {1, 2, 1024, 1, 1, 0, 160, 1},
+        {1, 1, 0, 1, 1, 0, 0, 1},
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;
@@ -350,6 +353,7 @@ size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
     b += align256(F * 8) * 2;                 // fll, fevents
     b += align256(F * (Hp / 64) * 4);         // items
     b += align256(kMaxGroups * 4);            // item_count
+    b += align256(kMaxGroups * 4);            // item_cursor
     b += align256(request_state_bytes((int64_t)F, net->U, Hp));
     return b + 256;
 }
@@ -394,6 +398,7 @@ EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_byte
     L.e.fevents = (uint64_t *)take(slots * 8);
     L.e.items = (uint32_t *)take(items * 4);
     L.e.item_count = (uint32_t *)take(kMaxGroups * 4);
+    L.e.item_cursor = (uint32_t *)take(kMaxGroups * 4);
     L.state = (int32_t *)take(state_bytes);
     return L;
 }
@@ -408,13 +413,15 @@ hipError_t lik::engine_iteration(const EngineArgs &e, const GroupLaunch *groups,
         const GroupLaunch &G = groups[g];
         if (G.max_items == 0) continue;
         hipEvent_t e0 = g_timing.enabled ? timing_mark(s) : nullptr;
+        const bool pers = G.persistent && (G.spec ? G.spec_p != nullptr : G.rmax <= 16);
+        const unsigned grid = pers ? std::min(G.max_items, G.persistent_waves) : G.max_items;
         if (G.spec) {
             int group = g;
             void *params[] = {(void *)&e, (void *)&group};
-            err = hipModuleLaunchKernel(G.spec, G.max_items, 1, 1, kPropBlock, 1, 1, 0, s, params,
-                                        nullptr);
+            err = hipModuleLaunchKernel(pers ? G.spec_p : G.spec, grid, 1, 1, kPropBlock, 1, 1, 0,
+                                        s, params, nullptr);
         } else {
-            err = launch_propagate(e, g, G.max_items, G.netargs, G.umax, G.rmax, G.precision, s);
+            err = launch_propagate(e, g, grid, G.netargs, G.umax, G.rmax, G.precision, pers, s);
         }
         if (err != hipSuccess) return err;
         if (g_timing.enabled) g_timing.prop.push_back({e0, timing_mark(s)});
@@ -495,6 +502,9 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     std::string err;
     if (!choose_specialized(*net, precision, variant, (double)F * H * t_max, &G.spec, &err))
         return fail(LIK_EDEVICE, "specialised kernel unavailable: " + err);
+    G.persistent = net->tuning.persistent != 0 && net->R <= kPersistentMaxR;
+    G.persistent_waves = persistent_waves();
+    if (G.spec && G.persistent) G.spec_p = specialized_kernel(*net, precision, &err, true);
 
     RequestArgs r;
     memset(&r, 0, sizeof(r));

@@ -15,7 +15,7 @@
 
 namespace lik {
 // Work partitioning used unless a caller sets another (lik_network_set_tuning).
-constexpr lik_tuning kDefaultTuning = {1, 4, 1024, 1, 1, 0, 160};
+constexpr lik_tuning kDefaultTuning = {1, 4, 1024, 1, 1, 0, 160, 0};
 }  // namespace lik
 
 struct lik_network {
@@ -31,7 +31,12 @@ struct lik_network {
     lik_tuning tuning = lik::kDefaultTuning;
     // (device, precision) -> loaded specialised kernel
     std::mutex spec_lock;
-    std::map<std::pair<int, int>, std::pair<hipModule_t, hipFunction_t>> spec;
+    struct SpecKernels {
+        hipModule_t mod = nullptr;
+        hipFunction_t item = nullptr;        // lik_propagate_spec
+        hipFunction_t persistent = nullptr;  // lik_propagate_spec_p (R <= 16), or null
+    };
+    std::map<std::pair<int, int>, SpecKernels> spec;
     // captured launch sequences of lik_eval_batch_device (LIK_FLAG_GRAPH)
     struct Graph {
         hipGraph_t graph = nullptr;
@@ -55,7 +60,8 @@ std::string specialized_source(const lik_network &net, int precision);
 // The specialised kernel for the current device, compiled with hipRTC on
 // first use (or read from the on-disk cache).  Returns nullptr and sets *err
 // on failure.
-hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err);
+hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err,
+                                 bool persistent = false);
 
 // Compile (or find in the disk cache) without loading: needs no device.
 bool precompile_specialized(const lik_network &net, int precision, std::string *err);
@@ -70,6 +76,7 @@ void release_specialized(lik_network &net);
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
 uint32_t compute_units();  // of the current device
+unsigned persistent_waves();  // grid of the persistent propagation kernels
 bool tuning_valid(const lik_tuning &t);
 const char *tuning_rule();
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -84,6 +91,9 @@ int check_host_data(const lik_network *net, const lik_obs_model *obs, const lik_
 // One (network, precision) group of an engine iteration.
 struct GroupLaunch {
     hipFunction_t spec = nullptr;    // network-specialised kernel, or null for generic
+    hipFunction_t spec_p = nullptr;  // its persistent variant, or null
+    bool persistent = false;         // take items from the group's counter (R <= 16)
+    unsigned persistent_waves = 0;   // grid of the persistent variant
     const void *netargs = nullptr;   // generic kernel's network tables
     int umax = 0, rmax = 0, precision = 0;
     unsigned max_items = 0;          // upper bound on the group's work items

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
         max_per = 0;
         chunks = 0;
     }
+    if (threadIdx.x < kMaxGroups) e.item_cursor[threadIdx.x] = 0;
     __syncthreads();
     for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x)
         if (slot_active(e, f)) atomicAdd(&chunks, (uint32_t)(e.desc[f].Hp >> 6));
@@ -224,6 +225,12 @@ template <int UMAX, int RMAX, int W, int PREC>
 __global__ __launch_bounds__(kPropBlock) void k_propagate(EngineArgs e, int group,
                                                           NetArgs<RMAX, W> net) {
     propagate_item<NetArgs<RMAX, W>, UMAX, RMAX, W, PREC>(e, net, group);
+}
+
+template <int UMAX, int RMAX, int W, int PREC>
+__global__ __launch_bounds__(kPropBlock) void k_propagate_p(EngineArgs e, int group,
+                                                            NetArgs<RMAX, W> net) {
+    propagate_persistent<NetArgs<RMAX, W>, UMAX, RMAX, W, PREC>(e, net, group);
 }
 
 // ---------------------------------------------------------------------------
@@ -472,9 +479,27 @@ static hipError_t launch_prop_t(const EngineArgs &e, int group, unsigned n_items
     return hipGetLastError();
 }
 
+// persistent variant: n_waves wavefronts take the group's items from its counter
+template <int UMAX, int RMAX, int W>
+static hipError_t launch_prop_p(const EngineArgs &e, int group, unsigned n_waves,
+                                const void *net, int precision, hipStream_t s) {
+    const NetArgs<RMAX, W> &n = *static_cast<const NetArgs<RMAX, W> *>(net);
+    if (precision == LIK_FP32_MIXED)
+        hipLaunchKernelGGL((k_propagate_p<UMAX, RMAX, W, LIK_FP32_MIXED>), dim3(n_waves),
+                           dim3(kPropBlock), 0, s, e, group, n);
+    else
+        hipLaunchKernelGGL((k_propagate_p<UMAX, RMAX, W, LIK_FP64>), dim3(n_waves),
+                           dim3(kPropBlock), 0, s, e, group, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, const void *net,
-                            int umax, int rmax, int precision, hipStream_t s) {
+                            int umax, int rmax, int precision, bool persistent, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
+    if (persistent && umax == 4 && rmax == 8)
+        return launch_prop_p<4, 8, 1>(e, group, n_items, net, precision, s);
+    if (persistent && umax == 8 && rmax == 16)
+        return launch_prop_p<8, 16, 1>(e, group, n_items, net, precision, s);
     if (umax == 4 && rmax == 8)
         return launch_prop_t<4, 8, 1>(e, group, n_items, net, precision, s);
     if (umax == 8 && rmax == 16)

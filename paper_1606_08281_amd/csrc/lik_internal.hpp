@@ -81,6 +81,7 @@ struct EngineArgs {
     uint8_t *pool;            // [slots] (wave priority << 6) | (particles per item / 64 - 1)
     uint32_t *items;          // propagation work items (slot << 6 | chunk), grouped
     uint32_t *item_count;     // [kMaxGroups] items written per group
+    uint32_t *item_cursor;    // [kMaxGroups] next item to take (persistent kernels)
     int32_t f_lo, f_hi;       // slot range that may hold active filters
     // Pool size G per slot: G = clamp(pool_events / (events per particle in
     // the last interval), pool_min, pool_max); pool_first for the first one.
@@ -97,7 +98,8 @@ struct EngineArgs {
 // Host-side launchers (kernels.hip).
 hipError_t launch_order(const EngineArgs &e, hipStream_t s);
 hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, const void *net,
-                            int umax, int rmax, int precision, hipStream_t s);
+                            int umax, int rmax, int precision, bool persistent, hipStream_t s);
+constexpr int kPersistentMaxR = 16;  // rates per lane in registers: small networks only
 hipError_t launch_weigh(const EngineArgs &e, hipStream_t s);
 
 // Per-request setup / results.  A request is n_theta rate vectors against M

@@ -87,6 +87,53 @@ struct pick_type<false, T, F> {
     using type = F;
 };
 
+// One direct-method event of one particle (Supplementary I, the "Simulate"
+// step; the SSA of Gillespie 1977): total propensity, then either the end of
+// the particle's interval (no reaction possible, the event cap, or the next
+// event beyond the observation time -- it is discarded) or one event.
+// a0_end keeps the last total propensity (a scheduling estimate).
+template <class NetT, int UMAX, int RMAX, int W, int PREC, class Real>
+__device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x, Real *S, int j,
+                                          uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                                          double t_end, uint32_t event_cap, double &clock,
+                                          uint32_t &n, int &st, float &a0_end, bool &have) {
+    const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
+    a0_end = (float)s;
+    if (!(s > (Real)0)) {
+        have = false;  // no reaction can fire before the observation
+    } else if (n >= event_cap) {
+        st = st > LIK_STATUS_EVENT_CAP ? st : LIK_STATUS_EVENT_CAP;
+        have = false;
+    } else {
+        const Block4 b = philox4x32_10(n, (uint32_t)j, c2, c3, k0, k1);
+        double tau;
+        Real target;
+        if (PREC == LIK_FP32_MIXED) {
+            // the leading 24 bits of the binary64 uniforms' words
+            const float u1 = (float)((b.w1 >> 8) + 1u) * 0x1p-24f;  // (0, 1]
+            const float u2 = (float)(b.w3 >> 8) * 0x1p-24f;         // [0, 1)
+            tau = (double)(-flog(u1) / (float)s);
+            target = (Real)(u2 * (float)s);
+        } else {
+            const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
+            const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
+            const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
+            const double u2 = (double)z2 * 0x1p-53;        // [0, 1)
+            tau = -dlog(u1) / (double)s;
+            target = (Real)(u2 * (double)s);
+        }
+        if (clock + tau > t_end) {
+            have = false;  // the pending event is discarded
+        } else {
+            uint32_t sel[W];
+            select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
+            apply_change<UMAX, W>(net.U, sel, x);
+            clock = clock + tau;
+            n = n + 1;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // propagate: for every particle of the item's pool, gather its ancestor's
 // counts, run Gillespie's direct method from the previous observation time
@@ -131,9 +178,9 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     // Descriptor fields the event loop uses, read once: the loop's stores
     // could alias the descriptor as far as the compiler knows.
     const uint32_t event_cap = d.event_cap;
-    const int32_t *anc_p = d.anc;
     uint32_t *pev_p = d.pev;
     float *pa0_p = d.pa0;
+    const int32_t *anc_p = d.anc;
     const int32_t *x0_p = d.x0;
     const int refill_min = e.refill_min;
 
@@ -144,12 +191,12 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? wave_uniform((Real)d.theta[r]) : (Real)0;
 
     // A pool of more than 64 particles lives in LDS: per particle its counts
-    // ([u][particle - p0]), its event count and its final total propensity.  The ancestors' counts are
-    // staged there first, a lane taking a new particle reads it from there,
-    // a finished particle's counts and events replace it, and the pool is
-    // copied out at the end: the event loop touches no global memory, so it
-    // never waits on it.  (Only such pools refill: a pool of at most 64 has
-    // one particle per lane.)
+    // ([u][particle - p0]), its event count and its final total propensity.
+    // The ancestors' counts are staged there first, a lane taking a new
+    // particle reads them from there, a finished particle's counts and
+    // events replace them, and the pool is copied out at the end: the event
+    // loop touches no global memory, so it never waits on it.  (Only such
+    // pools refill: a pool of at most 64 has one particle per lane.)
     __shared__ int32_t pool_lds[kPoolLdsWords];
     const int npool = p1 - p0;
     const bool staged = npool > kPropBlock;
@@ -230,43 +277,9 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
         __builtin_amdgcn_s_setprio(1);
     }
     for (;;) {
-        if (have) {
-            const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
-            a0_end = (float)s;
-            if (!(s > (Real)0)) {
-                have = false;  // no reaction can fire before the observation
-            } else if (n >= event_cap) {
-                st = st > LIK_STATUS_EVENT_CAP ? st : LIK_STATUS_EVENT_CAP;
-                have = false;
-            } else {
-                const Block4 b = philox4x32_10(n, (uint32_t)j, c2, c3, k0, k1);
-                double tau;
-                Real target;
-                if (PREC == LIK_FP32_MIXED) {
-                    // the leading 24 bits of the binary64 uniforms' words
-                    const float u1 = (float)((b.w1 >> 8) + 1u) * 0x1p-24f;  // (0, 1]
-                    const float u2 = (float)(b.w3 >> 8) * 0x1p-24f;         // [0, 1)
-                    tau = (double)(-flog(u1) / (float)s);
-                    target = (Real)(u2 * (float)s);
-                } else {
-                    const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
-                    const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
-                    const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
-                    const double u2 = (double)z2 * 0x1p-53;        // [0, 1)
-                    tau = -dlog(u1) / (double)s;
-                    target = (Real)(u2 * (double)s);
-                }
-                if (clock + tau > t_end) {
-                    have = false;  // the pending event is discarded
-                } else {
-                    uint32_t sel[W];
-                    select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
-                    apply_change<UMAX, W>(U, sel, x);
-                    clock = clock + tau;
-                    n = n + 1;
-                }
-            }
-        }
+        if (have)
+            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, j, c2, c3, k0, k1, t_end,
+                                                       event_cap, clock, n, st, a0_end, have);
         // Once at least refill_min lanes are idle (or all are), the idle
         // lanes store what they hold and take the next particles of the
         // pool, in lane order.
@@ -306,6 +319,189 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
         retire(false);
     }
     if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[f], st);
+}
+
+// ---------------------------------------------------------------------------
+// propagate_persistent: the same particles, streams and arithmetic as
+// propagate_item, scheduled across work items.  A grid of wavefronts takes
+// work items of the group from a counter in list order (longest first).  A
+// lane whose particle reaches its observation time stores it and takes the
+// next particle of the wavefront's current pool; once the pool is exhausted
+// the wavefront takes the next item, stages its ancestors' counts in LDS and
+// goes on filling idle lanes, while lanes still running particles of earlier
+// items finish them.  Lanes therefore carry their particle's filter context
+// (rates, observation time, stream ids, output pointers).  The Philox key
+// stays wave-uniform: a pool whose filter has another seed waits until every
+// lane is idle.  Used for networks of at most 16 reactions (the rates live
+// in registers per lane).
+// ---------------------------------------------------------------------------
+template <class NetT, int UMAX, int RMAX, int W, int PREC>
+__device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const NetT &net,
+                                                     int group) {
+    using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
+    const int U = net.U;
+    const int R = net.R;
+    const int lane = (int)threadIdx.x;
+    const uint32_t n_items = e.item_count[group];
+    const uint32_t *items = e.items + e.group_off[group];
+    const int refill_min = e.refill_min;
+    __shared__ int32_t pool_x[kPoolLdsWords];  // [U][npool]: ancestors' counts of the pool
+
+    // the current pool (wave-uniform)
+    int p0 = 0, p1 = 0, next = 0, npool = 0;
+    bool more = true;  // items may remain
+    int pf = 0;        // its filter
+    double p_t0 = 0.0, p_t1 = 0.0;
+    uint32_t p_c2 = 0, p_c3 = 0, p_cap = 0;
+    uint64_t p_seed = 0;
+    int32_t *p_dst = nullptr;
+    uint32_t *p_pev = nullptr;
+    float *p_pa0 = nullptr;
+    int p_hp = 0;
+    Real p_c[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) p_c[r] = (Real)0;
+    // the wavefront's Philox key
+    uint32_t k0 = 0, k1 = 0;
+
+    // the lane's particle and its filter context
+    bool have = false, pend = false;
+    int j = 0, fl = 0, hp = 0;
+    int x[UMAX];
+#pragma unroll
+    for (int u = 0; u < UMAX; ++u) x[u] = 0;
+    Real c[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) c[r] = (Real)0;
+    double clock = 0.0, t_end = 0.0;
+    uint32_t n = 0, c2 = 0, c3 = 0, cap = 0;
+    int32_t *dst = nullptr;
+    uint32_t *pev = nullptr;
+    float *pa0 = nullptr;
+    int st = LIK_STATUS_OK;
+    float a0_end = 0.0f;
+    Real S[RMAX];
+
+    auto retire = [&]() {
+#pragma unroll
+        for (int u = 0; u < UMAX; ++u)
+            if (u < U && x[u] > kCountLimit)
+                st = st > LIK_STATUS_COUNT_OVERFLOW ? st : LIK_STATUS_COUNT_OVERFLOW;
+#pragma unroll
+        for (int u = 0; u < UMAX; ++u)
+            if (u < U) dst[(size_t)u * hp + j] = x[u];
+        pev[j] = n;
+        pa0[j] = a0_end;
+        if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[fl], st);
+        st = LIK_STATUS_OK;
+    };
+
+    for (;;) {
+        if (have)
+            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, j, c2, c3, k0, k1, t_end, cap,
+                                                       clock, n, st, a0_end, have);
+        uint64_t idle = __ballot(!have);
+        const int n_idle = (int)__popcll(idle);
+        if (n_idle > 0 && (next < p1 || more) && (n_idle >= refill_min || idle == ~0ull)) {
+            if (!have && pend) {
+                retire();
+                pend = false;
+            }
+            for (;;) {
+                if (idle == 0ull) break;
+                if (next >= p1) {
+                    if (!more) break;
+                    uint32_t idx = 0;
+                    if (lane == 0) idx = atomicAdd(&e.item_cursor[group], 1u);
+                    idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
+                    if (idx >= n_items) {
+                        more = false;
+                        break;
+                    }
+                    const uint32_t item = __builtin_amdgcn_readfirstlane(items[idx]);
+                    pf = (int)(item >> 6);
+                    const FilterDesc &d = e.desc[pf];
+                    const int t = __builtin_amdgcn_readfirstlane(e.tcur[pf]);
+                    const int H = __builtin_amdgcn_readfirstlane(d.H);
+                    p_hp = __builtin_amdgcn_readfirstlane(d.Hp);
+                    p0 = (int)(item & 63u) * kPropBlock;
+                    const int g = (int)(__builtin_amdgcn_readfirstlane(e.pool[pf]) & 63u) + 1;
+                    p1 = min(p0 + g * kPropBlock, H);
+                    next = p0;
+                    npool = p1 - p0;
+                    p_t0 = wave_uniform((t == 0) ? d.t0 : d.t_obs[t - 1]);
+                    p_t1 = wave_uniform(d.t_obs[t]);
+                    p_c2 = __builtin_amdgcn_readfirstlane((d.traj << 16) | (uint32_t)t);
+                    p_c3 = __builtin_amdgcn_readfirstlane(d.theta_id << 2);
+                    p_cap = __builtin_amdgcn_readfirstlane(d.event_cap);
+                    p_seed = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(d.seed >> 32))
+                              << 32) |
+                             __builtin_amdgcn_readfirstlane((uint32_t)d.seed);
+                    const int32_t *src = (t & 1) ? d.xb : d.xa;
+                    p_dst = (t & 1) ? d.xa : d.xb;
+                    p_pev = d.pev;
+                    p_pa0 = d.pa0;
+#pragma unroll
+                    for (int r = 0; r < RMAX; ++r)
+                        p_c[r] = (r < R) ? wave_uniform((Real)d.theta[r]) : (Real)0;
+                    // stage the pool's ancestors' counts (every lane has read
+                    // the previous pool's entries it needed)
+                    const int32_t *anc = d.anc;
+                    const int32_t *x0 = d.x0;
+#pragma unroll 1
+                    for (int q = lane; q < npool; q += kPropBlock) {
+                        if (t == 0) {
+#pragma unroll
+                            for (int u = 0; u < UMAX; ++u)
+                                if (u < U) pool_x[u * npool + q] = x0[u];
+                        } else {
+                            const int a = anc[p0 + q];
+#pragma unroll
+                            for (int u = 0; u < UMAX; ++u)
+                                if (u < U) pool_x[u * npool + q] = src[(size_t)u * p_hp + a];
+                        }
+                    }
+                    __syncthreads();  // the workgroup is this one wavefront
+                }
+                // a pool with another key waits until every lane is idle
+                const uint32_t pk0 = (uint32_t)p_seed, pk1 = (uint32_t)(p_seed >> 32);
+                if (pk0 != k0 || pk1 != k1) {
+                    if (idle != ~0ull) break;
+                    k0 = pk0;
+                    k1 = pk1;
+                }
+                const int avail = p1 - next;
+                if (!have) {
+                    const int rank = (int)__popcll(idle & ((1ull << lane) - 1ull));
+                    if (rank < avail) {
+                        j = next + rank;
+#pragma unroll
+                        for (int u = 0; u < UMAX; ++u)
+                            x[u] = (u < U) ? pool_x[u * npool + (j - p0)] : 0;
+#pragma unroll
+                        for (int r = 0; r < RMAX; ++r) c[r] = p_c[r];
+                        clock = p_t0;
+                        t_end = p_t1;
+                        n = 0;
+                        c2 = p_c2;
+                        c3 = p_c3;
+                        cap = p_cap;
+                        dst = p_dst;
+                        pev = p_pev;
+                        pa0 = p_pa0;
+                        hp = p_hp;
+                        fl = pf;
+                        have = true;
+                        pend = true;
+                    }
+                }
+                next += min((int)__popcll(idle), avail);
+                idle = __ballot(!have);
+            }
+        }
+        if (__ballot(have) == 0ull && next >= p1 && !more) break;
+    }
+    if (pend) retire();
 }
 
 }  // namespace lik

@@ -131,6 +131,7 @@ struct Group {
 struct lik_server {
     lik_server_opts opts;
     int device = 0;
+    bool persistent = false;  // persistent propagation kernels for small networks
     hipStream_t stream = nullptr;
     char *dev_base = nullptr;       // engine table + arena
     char *arena = nullptr;
@@ -261,8 +262,12 @@ bool try_place(lik_server *S, Request &r, std::string *err) {
         G.launch.umax = r.net->umax;
         G.launch.rmax = r.net->rmax;
         G.launch.precision = r.precision;
+        G.launch.persistent = S->persistent && r.net->R <= kPersistentMaxR;
+        G.launch.persistent_waves = persistent_waves();
         if (S->opts.kernel != LIK_KERNEL_GENERIC) {
             G.launch.spec = specialized_kernel(*r.net, r.precision, err);
+            if (G.launch.spec && G.launch.persistent)
+                G.launch.spec_p = specialized_kernel(*r.net, r.precision, err, true);
             // an unavailable specialisation leaves the group on the generic kernel
         }
     }
@@ -428,7 +433,8 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     const size_t table = align256(slots * sizeof(FilterDesc)) + 4 * align256(slots * 4) +
                          align256(slots) +
                          2 * align256(slots * 8) + align256(slots * 64 * 4) +
-                         align256(kMaxGroups * 4) + align256(slots * 8) + align256(slots * 4);
+                         2 * align256(kMaxGroups * 4) + align256(slots * 8) +
+                         align256(slots * 4);
     hipError_t err = hipMalloc((void **)&S->dev_base, table + o.arena_bytes + 256);
     if (err != hipSuccess) return fail(LIK_ENOMEM, "device arena allocation failed");
     const size_t pinned_bytes = o.staging_bytes + slots * 12 + 512;
@@ -455,6 +461,7 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->e.fevents = (uint64_t *)take(slots * 8);
     S->e.items = (uint32_t *)take(slots * 64 * 4);
     S->e.item_count = (uint32_t *)take(kMaxGroups * 4);
+    S->e.item_cursor = (uint32_t *)take(kMaxGroups * 4);
     S->dev_loglik = (double *)take(slots * 8);
     S->dev_status = (int32_t *)take(slots * 4);
     S->arena = p;
@@ -471,6 +478,7 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->e.refill_min = tu.refill_min;
     S->e.priority = tu.priority;
     S->e.pool_min_items = (uint32_t)tu.items_per_cu * compute_units();
+    S->persistent = tu.persistent != 0;
     S->pmem.init(o.staging_bytes, 256);
     // every slot starts inactive (stopped), so stale slots are never ordered
     std::vector<uint32_t> stopped(slots, kFlagStopped);

@@ -147,6 +147,12 @@ std::string specialized_source(const lik_network &net, int precision) {
          "  const lik::SpecNet net{};\n"
          "  lik::propagate_item<lik::SpecNet, "
       << U << ", " << R << ", " << W << ", " << precision << ">(e, net, group);\n}\n";
+    if (R <= kPersistentMaxR)
+        o << "extern \"C\" __global__ __launch_bounds__(64) void lik_propagate_spec_p("
+             "lik::EngineArgs e, int group) {\n"
+             "  const lik::SpecNet net{};\n"
+             "  lik::propagate_persistent<lik::SpecNet, "
+          << U << ", " << R << ", " << W << ", " << precision << ">(e, net, group);\n}\n";
     return o.str();
 }
 
@@ -188,7 +194,8 @@ bool precompile_specialized(const lik_network &net, int precision, std::string *
     return specialized_code(net, precision, &code, &src, &path, err);
 }
 
-hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err) {
+hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err,
+                                 bool persistent) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         *err = "hipGetDevice failed";
@@ -196,7 +203,7 @@ hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *e
     }
     std::lock_guard<std::mutex> g(net.spec_lock);
     auto it = net.spec.find({dev, precision});
-    if (it != net.spec.end()) return it->second.second;
+    if (it != net.spec.end()) return persistent ? it->second.persistent : it->second.item;
 
     std::vector<char> code;
     std::string src, path;
@@ -215,15 +222,19 @@ hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *e
             return nullptr;
         }
     }
-    hipFunction_t fn = nullptr;
-    e = hipModuleGetFunction(&fn, mod, "lik_propagate_spec");
+    lik_network::SpecKernels k;
+    k.mod = mod;
+    e = hipModuleGetFunction(&k.item, mod, "lik_propagate_spec");
     if (e != hipSuccess) {
         *err = std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
         (void)hipModuleUnload(mod);
         return nullptr;
     }
-    net.spec[{dev, precision}] = {mod, fn};
-    return fn;
+    if (net.R <= kPersistentMaxR && hipModuleGetFunction(&k.persistent, mod,
+                                                         "lik_propagate_spec_p") != hipSuccess)
+        k.persistent = nullptr;
+    net.spec[{dev, precision}] = k;
+    return persistent ? k.persistent : k.item;
 }
 
 void release_specialized(lik_network &net) {
@@ -232,7 +243,7 @@ void release_specialized(lik_network &net) {
     (void)hipGetDevice(&cur);
     for (auto &kv : net.spec) {
         (void)hipSetDevice(kv.first.first);
-        (void)hipModuleUnload(kv.second.first);
+        (void)hipModuleUnload(kv.second.mod);
     }
     if (!net.spec.empty()) (void)hipSetDevice(cur);
     net.spec.clear();

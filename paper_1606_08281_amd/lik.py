@@ -59,7 +59,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("pool_min", ctypes.c_int32), ("pool_max", ctypes.c_int32),
                 ("pool_events", ctypes.c_uint32), ("pool_first", ctypes.c_int32),
                 ("refill_min", ctypes.c_int32), ("priority", ctypes.c_int32),
-                ("items_per_cu", ctypes.c_int32)]
+                ("items_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -188,7 +188,8 @@ class Network:
         _check(lib().lik_network_precompile(self.handle, int(precision)))
 
     def set_tuning(self, pool_min=None, pool_max=None, pool_events=None, pool_first=None,
-                   refill_min=None, priority=None, items_per_cu=None, default=False):
+                   refill_min=None, priority=None, items_per_cu=None, persistent=None,
+                   default=False):
         """Work partitioning of the propagation kernels (never changes results)."""
         if default:
             _check(lib().lik_network_set_tuning(self.handle, None))
@@ -197,7 +198,7 @@ class Network:
         for k, v in (("pool_min", pool_min), ("pool_max", pool_max),
                      ("pool_events", pool_events), ("pool_first", pool_first),
                      ("refill_min", refill_min), ("priority", priority),
-                     ("items_per_cu", items_per_cu)):
+                     ("items_per_cu", items_per_cu), ("persistent", persistent)):
             if v is not None:
                 setattr(t, k, int(v))
         _check(lib().lik_network_set_tuning(self.handle, ctypes.byref(t)))
@@ -354,7 +355,7 @@ class Server:
         tp = None
         if tuning is not None:
             t = dict(pool_min=1, pool_max=4, pool_events=1024, pool_first=1, refill_min=1,
-                     priority=0, items_per_cu=160)
+                     priority=0, items_per_cu=160, persistent=0)
             t.update(tuning)
             self._tuning = Tuning(**{k: int(v) for k, v in t.items()})
             tp = ctypes.addressof(self._tuning)

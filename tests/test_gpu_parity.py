@@ -244,15 +244,21 @@ def test_telegraph_full_batch_sampled(orc, precision):
 
 
 TUNINGS = [dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=1, priority=0,
-                items_per_cu=0),
+                items_per_cu=0, persistent=0),
            dict(pool_min=2, pool_max=4, pool_events=1024, pool_first=2, refill_min=1, priority=1,
-                items_per_cu=0),
+                items_per_cu=0, persistent=0),
            dict(pool_min=2, pool_max=8, pool_events=8192, pool_first=2, refill_min=7, priority=1,
-                items_per_cu=1),
+                items_per_cu=1, persistent=0),
            dict(pool_min=3, pool_max=5, pool_events=1, pool_first=7, refill_min=64, priority=0,
-                items_per_cu=0),
+                items_per_cu=0, persistent=0),
            dict(pool_min=64, pool_max=64, pool_events=0, pool_first=64, refill_min=33,
-                priority=1, items_per_cu=0)]
+                priority=1, items_per_cu=0, persistent=0),
+           dict(pool_min=1, pool_max=4, pool_events=1024, pool_first=1, refill_min=1, priority=0,
+                items_per_cu=160, persistent=1),
+           dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=9, priority=0,
+                items_per_cu=0, persistent=1),
+           dict(pool_min=4, pool_max=4, pool_events=0, pool_first=4, refill_min=64, priority=0,
+                items_per_cu=0, persistent=1)]
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
