@@ -15,7 +15,7 @@
 
 namespace lik {
 // Work partitioning used unless a caller sets another (lik_network_set_tuning).
-constexpr lik_tuning kDefaultTuning = {1, 4, 1024, 1, 1, 0, 160, 0};
+constexpr lik_tuning kDefaultTuning = {1, 6, 1536, 1, 1, 0, 160, 0};
 }  // namespace lik
 
 struct lik_network {

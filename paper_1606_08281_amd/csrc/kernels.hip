@@ -153,7 +153,7 @@ __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c,
         g = (int)min(want, (uint32_t)e.pool_max);
         g = max(g, e.pool_min);
     }
-    const int lds_cap = kPoolLdsWords / (kPropBlock * (e.desc[f].U + 2));  // pool fits in LDS
+    const int lds_cap = kPoolLdsWords / (kPropBlock * e.desc[f].U);  // pool fits in LDS
     g = min(min(g, lds_cap), g_par);
     return min(max(g, 1), nchunk);
 }

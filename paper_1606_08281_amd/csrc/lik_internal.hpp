@@ -22,9 +22,9 @@ constexpr int kMaxGroups = 16;    // (network, precision) groups per iteration
 constexpr int kCostKeys = 129;    // quarter octaves of expected events per lane, and zero
 constexpr uint32_t kFlagStopped = 1u;
 constexpr int32_t kCountLimit = 1 << 30;
-// LDS that holds a pool, per wavefront (6 KiB: 24 wavefronts per CU still
-// fit in its 160 KiB).  A pool takes U + 2 words per particle (counts,
-// events, final propensity), so G <= kPoolLdsWords / (64 (U + 2)).
+// LDS that stages a pool's starting counts, per wavefront (6 KiB: 26
+// wavefronts per CU fit in its 160 KiB).  A pool takes U words per particle,
+// so G <= kPoolLdsWords / (64 U).
 constexpr int kPoolLdsWords = 1536;
 
 // Reaction kinds after validation of the reactant orders.

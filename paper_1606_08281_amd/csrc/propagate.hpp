@@ -190,19 +190,15 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? wave_uniform((Real)d.theta[r]) : (Real)0;
 
-    // A pool of more than 64 particles lives in LDS: per particle its counts
-    // ([u][particle - p0]), its event count and its final total propensity.
-    // The ancestors' counts are staged there first, a lane taking a new
-    // particle reads them from there, a finished particle's counts and
-    // events replace them, and the pool is copied out at the end: the event
-    // loop touches no global memory, so it never waits on it.  (Only such
-    // pools refill: a pool of at most 64 has one particle per lane.)
-    __shared__ int32_t pool_lds[kPoolLdsWords];
+    // A pool of more than 64 particles first stages its ancestors' counts in
+    // LDS ([u][particle - p0]); a lane taking a new particle reads them from
+    // there, so the event loop never waits on a global load (a finished
+    // particle's results are stored straight to global memory: stores do
+    // not stall).  A pool of at most 64 particles has one per lane and
+    // reads its counts directly.
+    __shared__ int32_t pool_x[kPoolLdsWords];  // [U][npool]
     const int npool = p1 - p0;
     const bool staged = npool > kPropBlock;
-    int32_t *pool_x = pool_lds;                                // [U][npool]
-    uint32_t *pool_n = (uint32_t *)(pool_lds + U * npool);     // [npool]
-    float *pool_a = (float *)(pool_lds + (U + 1) * npool);     // [npool]
     if (staged) {
 #pragma unroll 1
         for (int q = lane; q < npool; q += kPropBlock) {
@@ -251,24 +247,16 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     // a finished particle: overflow check, and its counts, events and final
     // total propensity into the pool's LDS slot (staged) or straight to
     // global memory
-    auto retire = [&](bool to_lds) {
+    auto retire = [&]() {
 #pragma unroll
         for (int u = 0; u < UMAX; ++u)
             if (u < U && x[u] > kCountLimit)
                 st = st > LIK_STATUS_COUNT_OVERFLOW ? st : LIK_STATUS_COUNT_OVERFLOW;
-        if (to_lds) {
 #pragma unroll
-            for (int u = 0; u < UMAX; ++u)
-                if (u < U) pool_x[u * npool + (j - p0)] = x[u];
-            pool_n[j - p0] = n;
-            pool_a[j - p0] = a0_end;
-        } else {
-#pragma unroll
-            for (int u = 0; u < UMAX; ++u)
-                if (u < U) dst[(size_t)u * Hp + j] = x[u];
-            pev_p[j] = n;
-            pa0_p[j] = a0_end;
-        }
+        for (int u = 0; u < UMAX; ++u)
+            if (u < U) dst[(size_t)u * Hp + j] = x[u];
+        pev_p[j] = n;
+        pa0_p[j] = a0_end;
     };
 
     if ((pool >> 6) == 3) {
@@ -288,7 +276,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
             const int n_idle = (int)__popcll(idle);
             if (n_idle >= refill_min || idle == ~0ull) {
                 if (!have) {
-                    if (pend) retire(true);
+                    if (pend) retire();
                     pend = false;
                     const int nj = next + (int)__popcll(idle & ((1ull << lane) - 1ull));
                     if (nj < p1) {
@@ -303,21 +291,7 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
         }
         if (__ballot(have) == 0ull) break;
     }
-    if (staged) {
-        if (pend) retire(true);
-        __syncthreads();
-        // coalesced copy of the pool's counts, events and propensities
-#pragma unroll 1
-        for (int q = lane; q < npool; q += kPropBlock) {
-#pragma unroll
-            for (int u = 0; u < UMAX; ++u)
-                if (u < U) dst[(size_t)u * Hp + p0 + q] = pool_x[u * npool + q];
-            pev_p[p0 + q] = pool_n[q];
-            pa0_p[p0 + q] = pool_a[q];
-        }
-    } else if (pend) {
-        retire(false);
-    }
+    if (pend) retire();
     if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[f], st);
 }
 
