@@ -106,9 +106,10 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
  * observation time.  Per filter and interval, G = clamp(pool_events / e,
  * pool_min, pool_max), where e is the expected number of events per particle
  * (the total propensity of the particles' starting states times the
- * interval's length), and pool_first in the first interval; G is at most H / 64 rounded up, and at
- * most 16 / U (the pool's counts are staged in 4 KiB of LDS).  Idle lanes
- * take new particles once refill_min of them are idle.
+ * interval's length), and pool_first in the first interval.  G is at most
+ * H / 64 rounded up, and at most 24 / U (the pool's starting counts are
+ * staged in 6 KiB of LDS).  Idle lanes take new particles once refill_min
+ * of them are idle.
  */
 typedef struct lik_tuning {
     int32_t pool_min;      /* >= 1 */
@@ -125,7 +126,7 @@ typedef struct lik_tuning {
                               their pool runs out; 0: one wavefront per work item */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {1, 4, 1024, 1, 1, 0, 160, 0}) / reads a network's
+/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

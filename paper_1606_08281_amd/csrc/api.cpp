@@ -196,13 +196,13 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
-        {1, 4, 1024, 1, 1, 0, 160, 0},     // default
-        {2, 4, 1024, 1, 1, 0, 160, 0},
+        {1, 6, 1536, 1, 1, 0, 160, 0},     // default
+        {1, 4, 1024, 1, 1, 0, 160, 0},
+        {2, 6, 2048, 1, 1, 0, 160, 0},
         {1, 1, 0, 1, 1, 0, 0, 0},          // one group of 64 particles per wavefront
-        {1, 4, 2048, 1, 1, 0, 320, 0},
-        {1, 4, 1024, 1, 1, 0, 160, 1},     // persistent wavefronts (R <= 16)
+        {1, 6, 2048, 1, 1, 0, 320, 0},
+        {1, 1, 0, 1, 1, 0, 0, 1},          // persistent wavefronts (R <= 16)
         {1, 2, 1024, 1, 1, 0, 160, 1},
-        {1, 1, 0, 1, 1, 0, 0, 1},
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;

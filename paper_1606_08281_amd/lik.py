@@ -354,7 +354,7 @@ class Server:
         self._tuning = None
         tp = None
         if tuning is not None:
-            t = dict(pool_min=1, pool_max=4, pool_events=1024, pool_first=1, refill_min=1,
+            t = dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1,
                      priority=0, items_per_cu=160, persistent=0)
             t.update(tuning)
             self._tuning = Tuning(**{k: int(v) for k, v in t.items()})

@@ -123,7 +123,7 @@ def test_precompile_specialized_kernels_without_gpu(tmp_path, monkeypatch):
 
 def test_tuning_set_get_and_bounds():
     net = lik.Network(*[np.asarray(a) for a in (W.telegraph().orders, W.telegraph().stoich)])
-    default = {"pool_min": 1, "pool_max": 4, "pool_events": 1024, "pool_first": 1,
+    default = {"pool_min": 1, "pool_max": 6, "pool_events": 1536, "pool_first": 1,
                "refill_min": 1, "priority": 0, "items_per_cu": 160, "persistent": 0}
     assert net.tuning() == default
     assert net.set_tuning(pool_min=1, pool_max=16, pool_events=100, pool_first=3,
