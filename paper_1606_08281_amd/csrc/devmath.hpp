@@ -46,6 +46,17 @@ constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
 constexpr double kInvLn2 = 0x1.71547652b82fep+0;
 constexpr double kHalfSqrt2 = 0x1.6a09e667f3bcdp-1;  // (nearest sqrt 2) / 2, exact halving
 
+// a * b + c with one rounding, as one three-operand v_fma_f64.  In a loop the
+// compiler keeps each Horner coefficient in registers and, choosing the
+// two-operand v_fmac_f64, copies it into the accumulator before every step;
+// this form takes the coefficient as a plain source (one instruction per
+// step instead of two).  Same operation as fma(): IEEE fused multiply-add.
+__device__ __forceinline__ double fma_f64(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // Natural logarithm of x > 0 (x = 0 -> -inf).  Reduction x = 2^e m,
 // m in [sqrt(1/2), sqrt(2)]; with f = m - 1 and s = f / (2 + f),
 // log m = 2 atanh s = t + t z Q(z), t = 2s, z = s^2,
@@ -65,15 +76,15 @@ __device__ __forceinline__ double dlog(double x) {
     const double s = f / (2.0 + f);
     const double z = s * s;
     double q = 1.0 / 21.0;
-    q = __builtin_fma(q, z, 1.0 / 19.0);
-    q = __builtin_fma(q, z, 1.0 / 17.0);
-    q = __builtin_fma(q, z, 1.0 / 15.0);
-    q = __builtin_fma(q, z, 1.0 / 13.0);
-    q = __builtin_fma(q, z, 1.0 / 11.0);
-    q = __builtin_fma(q, z, 1.0 / 9.0);
-    q = __builtin_fma(q, z, 1.0 / 7.0);
-    q = __builtin_fma(q, z, 1.0 / 5.0);
-    q = __builtin_fma(q, z, 1.0 / 3.0);
+    q = fma_f64(q, z, 1.0 / 19.0);
+    q = fma_f64(q, z, 1.0 / 17.0);
+    q = fma_f64(q, z, 1.0 / 15.0);
+    q = fma_f64(q, z, 1.0 / 13.0);
+    q = fma_f64(q, z, 1.0 / 11.0);
+    q = fma_f64(q, z, 1.0 / 9.0);
+    q = fma_f64(q, z, 1.0 / 7.0);
+    q = fma_f64(q, z, 1.0 / 5.0);
+    q = fma_f64(q, z, 1.0 / 3.0);
     const double t = 2.0 * s;
     const double w = t * z;
     const double lm = __builtin_fma(w, q, t);
