@@ -106,7 +106,8 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
  * observation time.  Per filter and interval, G = clamp(pool_events / e,
  * pool_min, pool_max), where e is the expected number of events per particle
  * (the total propensity of the particles' starting states times the
- * interval's length), and pool_first in the first interval.  G is at most
+ * interval's length; in the first interval the total propensity at x0), and
+ * pool_first when there is no estimate.  G is at most
  * H / 64 rounded up, and at most 24 / U (the pool's starting counts are
  * staged in 6 KiB of LDS).  Idle lanes take new particles once refill_min
  * of them are idle.

@@ -530,6 +530,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     r.seed = seed;
     r.event_cap = (uint32_t)((opts && opts->event_cap) ? opts->event_cap : LIK_DEFAULT_EVENT_CAP);
     r.base = 0;
+    fill_reactant_tables(r, net->kind, net->s1, net->s2, net->R);
 
     hipStream_t s = (hipStream_t)stream;
     auto enqueue = [&](hipStream_t st) -> int {

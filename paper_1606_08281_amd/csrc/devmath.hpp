@@ -61,8 +61,14 @@ __device__ __forceinline__ double fma_f64(double a, double b, double c) {
 // m in [sqrt(1/2), sqrt(2)]; with f = m - 1 and s = f / (2 + f),
 // log m = 2 atanh s = t + t z Q(z), t = 2s, z = s^2,
 // Q(z) = 1/3 + z/5 + ... + z^9/21; log x = e ln2_hi + (e ln2_lo + log m).
+__device__ __forceinline__ double dlog_pos(double x);
 __device__ __forceinline__ double dlog(double x) {
     if (x == 0.0) return -__builtin_inf();
+    return dlog_pos(x);
+}
+
+// The same for x > 0 (no test for zero: the SSA's uniforms are in (0, 1]).
+__device__ __forceinline__ double dlog_pos(double x) {
     const double mant = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1), exact, subnormals too
     int e = __builtin_amdgcn_frexp_exp(x);
     double m;
@@ -122,8 +128,14 @@ constexpr float kLn2HiF = 0x1.62e4p-1f;
 constexpr float kLn2LoF = 0x1.7f7d1cp-20f;
 constexpr float kHalfSqrt2F = 0x1.6a09e6p-1f;
 
+__device__ __forceinline__ float flog_pos(float x);
 __device__ __forceinline__ float flog(float x) {
     if (x == 0.0f) return -__builtin_inff();
+    return flog_pos(x);
+}
+
+// The same for x > 0.
+__device__ __forceinline__ float flog_pos(float x) {
     const float mant = __builtin_amdgcn_frexp_mantf(x);
     int e = __builtin_amdgcn_frexp_expf(x);
     float m;

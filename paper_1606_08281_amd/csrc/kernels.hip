@@ -123,7 +123,35 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
     e.fstatus[f] = bad ? LIK_STATUS_BAD_THETA : LIK_STATUS_OK;
     e.fflags[f] = bad ? kFlagStopped : 0u;
     e.fevents[f] = 0;
-    e.cost[f] = 0;
+    // expected events of the first interval (a scheduling estimate):
+    // H x total propensity at x0 x the interval's length
+    double a0 = 0.0;
+    if (!bad) {
+        for (int q = 0; q < r.R; ++q) {
+            const int k = r.kind[q];
+            double h = 1.0;
+            if (k == kOrder1) {
+                h = (double)d.x0[r.s1[q]];
+            } else if (k == kOrder2Homo) {
+                const double v = (double)d.x0[r.s1[q]];
+                h = 0.5 * v * (v - 1.0);
+            } else if (k == kOrder2Hetero) {
+                h = (double)d.x0[r.s1[q]] * (double)d.x0[r.s2[q]];
+            }
+            a0 += d.theta[q] * h;
+        }
+    }
+    const double expect = (double)r.H * a0 * (d.t_obs[0] - d.t0);
+    e.cost[f] = !(expect > 0.0) ? 0u : expect >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)expect;
+}
+
+void fill_reactant_tables(RequestArgs &r, const int32_t *kind, const int32_t *s1,
+                          const int32_t *s2, int R) {
+    for (int q = 0; q < LIK_MAX_REACTIONS; ++q) {
+        r.kind[q] = q < R ? (int8_t)kind[q] : (int8_t)0;
+        r.s1[q] = q < R ? (int8_t)s1[q] : (int8_t)0;
+        r.s2[q] = q < R ? (int8_t)s2[q] : (int8_t)0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -145,8 +173,8 @@ __device__ __forceinline__ int duration_key(uint64_t c) {
 __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c, int g_par) {
     const int nchunk = e.desc[f].Hp >> 6;
     int g;
-    if (e.tcur[f] == 0) {
-        g = e.pool_first;
+    if (e.tcur[f] == 0 && c == 0) {
+        g = e.pool_first;  // no estimate
     } else {
         const uint32_t per = c / (uint32_t)e.desc[f].H;  // expected events per particle
         const uint32_t want = e.pool_events / (per > 0 ? per : 1u);

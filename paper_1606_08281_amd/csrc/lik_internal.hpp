@@ -119,7 +119,12 @@ struct RequestArgs {
     uint64_t seed;
     uint32_t event_cap;
     int32_t base;               // first slot
+    // reactant tables (kind, s1, s2 per reaction) for the first interval's
+    // cost estimate: total propensity at x0 times the interval's length
+    int8_t kind[LIK_MAX_REACTIONS], s1[LIK_MAX_REACTIONS], s2[LIK_MAX_REACTIONS];
 };
+void fill_reactant_tables(RequestArgs &r, const int32_t *kind, const int32_t *s1,
+                          const int32_t *s2, int R);
 size_t request_state_bytes(int64_t F, int32_t U, int32_t Hp);
 hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs &r,
                         hipStream_t s);

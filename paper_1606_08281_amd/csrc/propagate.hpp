@@ -112,14 +112,14 @@ __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x
             // the leading 24 bits of the binary64 uniforms' words
             const float u1 = (float)((b.w1 >> 8) + 1u) * 0x1p-24f;  // (0, 1]
             const float u2 = (float)(b.w3 >> 8) * 0x1p-24f;         // [0, 1)
-            tau = (double)(-flog(u1) / (float)s);
+            tau = (double)(-flog_pos(u1) / (float)s);
             target = (Real)(u2 * (float)s);
         } else {
             const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
             const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
             const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
             const double u2 = (double)z2 * 0x1p-53;        // [0, 1)
-            tau = -dlog(u1) / (double)s;
+            tau = -dlog_pos(u1) / (double)s;
             target = (Real)(u2 * (double)s);
         }
         if (clock + tau > t_end) {

@@ -224,6 +224,7 @@ hipError_t admit(lik_server *S, Request &r) {
     a.seed = r.seed;
     a.event_cap = (uint32_t)(r.event_cap ? r.event_cap : LIK_DEFAULT_EVENT_CAP);
     a.base = (int32_t)r.slot;
+    fill_reactant_tables(a, r.net->kind, r.net->s1, r.net->s2, r.net->R);
     return launch_admit(S->desc, S->e, a, S->stream);
 }
 
