@@ -58,6 +58,8 @@ extern "C" {
 #define LIK_STATUS_EVENT_CAP 1      /* a particle needed more events in one interval than the cap */
 #define LIK_STATUS_COUNT_OVERFLOW 2 /* a count exceeded 2^30 at the end of an interval */
 #define LIK_STATUS_BAD_THETA 3      /* a rate was negative, infinite or NaN */
+#define LIK_STATUS_SCHEDULER 4      /* the flow schedule saw no work item finish for a
+                                       minute and gave up (an internal fault) */
 
 /* observation noise models (Sec. "General Task": Y ~ p(. | X, theta)) */
 #define LIK_OBS_GAUSSIAN 0  /* y = x_s + N(0, sigma^2) per observed species s */
@@ -108,9 +110,10 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
  * (the total propensity of the particles' starting states times the
  * interval's length; in the first interval the total propensity at x0), and
  * pool_first when there is no estimate.  G is at most
- * H / 64 rounded up, and at most 24 / U (the pool's starting counts are
- * staged in 6 KiB of LDS).  Idle lanes take new particles once refill_min
- * of them are idle.
+ * H / 64 rounded up, and at most 1536 / (64 U + 32) (the pool's starting
+ * counts and its order are staged in 6 KiB of LDS).  Idle lanes take new
+ * particles once refill_min of them are idle; a pool's particles are taken
+ * heaviest first (by the total propensity of their starting counts).
  */
 typedef struct lik_tuning {
     int32_t pool_min;      /* >= 1 */
@@ -125,9 +128,15 @@ typedef struct lik_tuning {
     int32_t persistent;    /* 1: networks of at most 16 reactions run a persistent
                               kernel whose lanes move on to the next work item when
                               their pool runs out; 0: one wavefront per work item */
+    int32_t schedule;      /* batch evaluation: 0: one launch sequence per observation
+                              interval, every filter advancing together; 1: one
+                              persistent launch for all intervals, each filter going on
+                              to its next interval as soon as its own particles are
+                              weighed (the server always advances its slots together;
+                              persistent is ignored under 1) */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0}) / reads a network's
+/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 0}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

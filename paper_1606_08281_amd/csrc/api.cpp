@@ -32,13 +32,14 @@ bool lik::tuning_valid(const lik_tuning &v) {
     return v.pool_min >= 1 && v.pool_max >= v.pool_min && v.pool_max <= 64 &&
            v.pool_first >= 1 && v.pool_first <= 64 && v.refill_min >= 1 && v.refill_min <= 64 &&
            (v.priority == 0 || v.priority == 1) && v.items_per_cu >= 0 &&
-           v.items_per_cu <= (1 << 20) && (v.persistent == 0 || v.persistent == 1);
+           v.items_per_cu <= (1 << 20) && (v.persistent == 0 || v.persistent == 1) &&
+           (v.schedule == 0 || v.schedule == 1);
 }
 
 const char *lik::tuning_rule() {
     return "tuning must satisfy 1 <= pool_min <= pool_max <= 64, 1 <= pool_first <= 64, "
            "1 <= refill_min <= 64, priority 0 or 1, 0 <= items_per_cu <= 2^20, "
-           "persistent 0 or 1";
+           "persistent 0 or 1, schedule 0 or 1";
 }
 
 unsigned lik::persistent_waves() { return compute_units() * 32u; }
@@ -196,13 +197,15 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
-        {1, 6, 1536, 1, 1, 0, 160, 0},     // default
-        {1, 4, 1024, 1, 1, 0, 160, 0},
-        {2, 6, 2048, 1, 1, 0, 160, 0},
-        {1, 1, 0, 1, 1, 0, 0, 0},          // one group of 64 particles per wavefront
-        {1, 6, 2048, 1, 1, 0, 320, 0},
-        {1, 1, 0, 1, 1, 0, 0, 1},          // persistent wavefronts (R <= 16)
-        {1, 2, 1024, 1, 1, 0, 160, 1},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 0},  // default
+        {1, 4, 1024, 1, 1, 0, 160, 0, 0},
+        {2, 6, 2048, 1, 1, 0, 160, 0, 0},
+        {1, 1, 0, 1, 1, 0, 0, 0, 0},       // one group of 64 particles per wavefront
+        {1, 6, 2048, 1, 1, 0, 320, 0, 0},
+        {1, 1, 0, 1, 1, 0, 0, 1, 0},       // persistent wavefronts (R <= 16)
+        {1, 2, 1024, 1, 1, 0, 160, 1, 0},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1},  // flow schedule
+        {1, 6, 3072, 1, 1, 0, 80, 0, 1},
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;
@@ -354,6 +357,9 @@ size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
     b += align256(F * (Hp / 64) * 4);         // items
     b += align256(kMaxGroups * 4);            // item_count
     b += align256(kMaxGroups * 4);            // item_cursor
+    b += align256((size_t)flow_ring_capacity(F, Hp / 64) * 8);  // flow ring
+    b += align256(F * 4);                     // flow: items left per slot
+    b += align256(kCtlWords * 4);             // flow: control words
     b += align256(request_state_bytes((int64_t)F, net->U, Hp));
     return b + 256;
 }
@@ -376,10 +382,12 @@ namespace {
 struct EngineLayout {
     FilterDesc *desc;
     EngineArgs e;
+    FlowArgs fa;
     int32_t *state;
 };
 
-EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_bytes) {
+EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_bytes,
+                          uint32_t ring_capacity) {
     auto take = [&](size_t bytes) {
         char *q = p;
         p += align256(bytes);
@@ -399,6 +407,12 @@ EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_byte
     L.e.items = (uint32_t *)take(items * 4);
     L.e.item_count = (uint32_t *)take(kMaxGroups * 4);
     L.e.item_cursor = (uint32_t *)take(kMaxGroups * 4);
+    memset(&L.fa, 0, sizeof(L.fa));
+    L.fa.ring = (uint64_t *)take((size_t)ring_capacity * 8);
+    L.fa.remaining = (uint32_t *)take(slots * 4);
+    L.fa.ctl = (uint32_t *)take(kCtlWords * 4);
+    L.fa.mask = ring_capacity - 1;
+    L.fa.n_slots = (int32_t)slots;
     L.state = (int32_t *)take(state_bytes);
     return L;
 }
@@ -479,7 +493,9 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     const int Hp = (H + 63) / 64 * 64;
     const int nchunk = Hp / 64;
     char *p = (char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-    EngineLayout L = carve_engine(p, F, F * nchunk, request_state_bytes((int64_t)F, net->U, Hp));
+    const bool flow = net->tuning.schedule == 1;
+    EngineLayout L = carve_engine(p, F, F * nchunk, request_state_bytes((int64_t)F, net->U, Hp),
+                                  flow_ring_capacity(F, nchunk));
     L.e.f_lo = 0;
     L.e.f_hi = (int32_t)F;
     L.e.pool_min = net->tuning.pool_min;
@@ -504,7 +520,30 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
         return fail(LIK_EDEVICE, "specialised kernel unavailable: " + err);
     G.persistent = net->tuning.persistent != 0 && net->R <= kPersistentMaxR;
     G.persistent_waves = persistent_waves();
-    if (G.spec && G.persistent) G.spec_p = specialized_kernel(*net, precision, &err, true);
+    if (G.spec && G.persistent) G.spec_p = specialized_kernel(*net, precision, &err, kSpecPersistent);
+
+    // flow schedule: its kernel and one wavefront per work item the batch can
+    // have (every interval of every filter in groups of 64)
+    hipFunction_t flow_spec = nullptr;
+    unsigned flow_waves = 0;
+    if (flow) {
+        const size_t items_max = (size_t)n_theta * (size_t)total * (size_t)nchunk;
+        if (items_max >= ((size_t)1 << 26))
+            return fail(LIK_EINVAL, "batch too large for the flow schedule (2^26 work items)");
+        flow_waves = (unsigned)std::max<size_t>(items_max, 1);
+        if (G.spec) {
+            flow_spec = specialized_kernel(*net, precision, &err, kSpecFlow);
+            if (!flow_spec) return fail(LIK_EDEVICE, "specialised flow kernel unavailable: " + err);
+        }
+        L.fa.g_par = (int32_t)std::max<size_t>(
+            1, F * nchunk / std::max<uint32_t>(L.e.pool_min_items, 1u));
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+            khz <= 0)
+            khz = 100000;
+        L.fa.stall_ticks = (uint64_t)khz * 1000ull * 60ull;  // one minute
+    }
 
     RequestArgs r;
     memset(&r, 0, sizeof(r));
@@ -536,9 +575,28 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     auto enqueue = [&](hipStream_t st) -> int {
         hipError_t e = launch_admit(L.desc, L.e, r, st);
         if (e != hipSuccess) return hip_fail(e, "admit launch");
-        for (int t = 0; t < t_max; ++t) {
-            e = engine_iteration(L.e, &G, 1, st);
-            if (e != hipSuccess) return hip_fail(e, "iteration launch");
+        if (flow) {
+            e = launch_flow_setup(L.e, L.fa, st);
+            if (e != hipSuccess) return hip_fail(e, "flow setup launch");
+            hipEvent_t e0 = g_timing.enabled ? timing_mark(st) : nullptr;
+            if (flow_spec) {
+                EngineArgs ea = L.e;
+                FlowArgs fb = L.fa;
+                void *params[] = {(void *)&ea, (void *)&fb};
+                e = hipModuleLaunchKernel(flow_spec, flow_waves, 1, 1, kPropBlock, 1, 1, 0, st,
+                                          params, nullptr);
+            } else {
+                e = launch_flow(L.e, L.fa, flow_waves, G.netargs, G.umax, G.rmax, precision, st);
+            }
+            if (e != hipSuccess) return hip_fail(e, "flow launch");
+            if (g_timing.enabled) g_timing.prop.push_back({e0, timing_mark(st)});
+            e = launch_flow_check(L.e, L.fa, st);
+            if (e != hipSuccess) return hip_fail(e, "flow check launch");
+        } else {
+            for (int t = 0; t < t_max; ++t) {
+                e = engine_iteration(L.e, &G, 1, st);
+                if (e != hipSuccess) return hip_fail(e, "iteration launch");
+            }
         }
         e = launch_finish(L.e, 0, n_theta, M, loglik_out, status_out, aux, st);
         if (e != hipSuccess) return hip_fail(e, "finish launch");

@@ -13,6 +13,32 @@
 
 namespace lik {
 
+// ---------------------------------------------------------------------------
+// Lanes of a wavefront.  lane_id() is the lane index behind an empty asm
+// statement, so the compiler recomputes what it derives from it (LDS and
+// exchange addresses) where it is used instead of keeping those values in
+// registers across a whole persistent loop.  Exchanges go through
+// ds_bpermute with addresses from that index.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() {
+    int l = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    asm volatile("" : "+v"(l));
+    return l;
+}
+__device__ __forceinline__ uint32_t lane_read(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+__device__ __forceinline__ uint64_t lane_read(uint64_t v, int src) {
+    const uint32_t lo = lane_read((uint32_t)v, src), hi = lane_read((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double lane_read(double v, int src) {
+    return __longlong_as_double((long long)lane_read((uint64_t)__double_as_longlong(v), src));
+}
+__device__ __forceinline__ float lane_read(float v, int src) {
+    return __uint_as_float(lane_read(__float_as_uint(v), src));
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round two
 // 32x32->64-bit products, the high halves xor'ed with the other words and
 // the round key; the key advances by the Weyl constants between rounds.

@@ -15,7 +15,7 @@
 
 namespace lik {
 // Work partitioning used unless a caller sets another (lik_network_set_tuning).
-constexpr lik_tuning kDefaultTuning = {1, 6, 1536, 1, 1, 0, 160, 0};
+constexpr lik_tuning kDefaultTuning = {1, 6, 1536, 1, 1, 0, 160, 0, 0};
 }  // namespace lik
 
 struct lik_network {
@@ -35,6 +35,7 @@ struct lik_network {
         hipModule_t mod = nullptr;
         hipFunction_t item = nullptr;        // lik_propagate_spec
         hipFunction_t persistent = nullptr;  // lik_propagate_spec_p (R <= 16), or null
+        hipFunction_t flow = nullptr;        // lik_flow_spec
     };
     std::map<std::pair<int, int>, SpecKernels> spec;
     // captured launch sequences of lik_eval_batch_device (LIK_FLAG_GRAPH)
@@ -60,8 +61,9 @@ std::string specialized_source(const lik_network &net, int precision);
 // The specialised kernel for the current device, compiled with hipRTC on
 // first use (or read from the on-disk cache).  Returns nullptr and sets *err
 // on failure.
+enum SpecKind { kSpecItem = 0, kSpecPersistent = 1, kSpecFlow = 2 };
 hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err,
-                                 bool persistent = false);
+                                 int kind = kSpecItem);
 
 // Compile (or find in the disk cache) without loading: needs no device.
 bool precompile_specialized(const lik_network &net, int precision, std::string *err);

@@ -25,51 +25,11 @@
 
 #include "devmath.hpp"
 #include "lik_internal.hpp"
+#include "flow.hpp"
 #include "propagate.hpp"
+#include "weigh.hpp"
 
 namespace lik {
-
-// ---------------------------------------------------------------------------
-// wavefront reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ float wave_sum_f32(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// inclusive prefix sum over the 64 lanes of a wavefront
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint64_t o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
-    }
-    return v;
-}
-
-__device__ __forceinline__ bool slot_active(const EngineArgs &e, int f) {
-    return !(e.fflags[f] & kFlagStopped) && e.tcur[f] < e.desc[f].T;
-}
 
 // ---------------------------------------------------------------------------
 // admit: fill the slots of one request.  Rates that are negative, infinite or
@@ -170,22 +130,6 @@ __device__ __forceinline__ int duration_key(uint64_t c) {
     return 4 * (32 - b) + (3 - frac);  // 0 = longest
 }
 
-__device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c, int g_par) {
-    const int nchunk = e.desc[f].Hp >> 6;
-    int g;
-    if (e.tcur[f] == 0 && c == 0) {
-        g = e.pool_first;  // no estimate
-    } else {
-        const uint32_t per = c / (uint32_t)e.desc[f].H;  // expected events per particle
-        const uint32_t want = e.pool_events / (per > 0 ? per : 1u);
-        g = (int)min(want, (uint32_t)e.pool_max);
-        g = max(g, e.pool_min);
-    }
-    const int lds_cap = kPoolLdsWords / (kPropBlock * e.desc[f].U);  // pool fits in LDS
-    g = min(min(g, lds_cap), g_par);
-    return min(max(g, 1), nchunk);
-}
-
 __global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
     __shared__ uint32_t hist[kMaxGroups * kCostKeys];
     __shared__ uint32_t max_per;  // most expected events per particle of any slot
@@ -262,6 +206,53 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate_p(EngineArgs e, int gr
 }
 
 // ---------------------------------------------------------------------------
+// flow engine (flow.hpp): ring reset, the first interval's items, the
+// persistent launch, and the check that it did not give up
+// ---------------------------------------------------------------------------
+__global__ void k_flow_init(FlowArgs fa) {
+    const size_t cap = (size_t)fa.mask + 1;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
+         i += (size_t)gridDim.x * blockDim.x)
+        fa.ring[i] = (uint64_t)i << 32;  // free for position i
+    if (blockIdx.x == 0)
+        for (int w = threadIdx.x; w < kCtlWords; w += blockDim.x) fa.ctl[w] = 0u;
+}
+
+__global__ void k_flow_seed(EngineArgs e, FlowArgs fa) {
+    const int f = e.f_lo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (f >= e.f_hi) return;
+    if (!slot_active(e, f)) {
+        atomicAdd(&fa.ctl[kCtlFinished], 1u);
+        return;
+    }
+    const int G = pool_size(e, f, e.cost[f], fa.g_par);
+    const int n_items = ((e.desc[f].Hp >> 6) + G - 1) / G;
+    e.pool[f] = (uint8_t)(G - 1);
+    fa.remaining[f] = (uint32_t)n_items;
+    const uint32_t base = atomicAdd(&fa.ctl[kCtlTail], (uint32_t)n_items);
+    for (int k = 0; k < n_items; ++k) {
+        const uint32_t pos = base + (uint32_t)k;
+        fa.ring[pos & fa.mask] =
+            ((uint64_t)(pos + 1u) << 32) | (((uint32_t)f << 6) | (uint32_t)(k * G));
+    }
+}
+
+template <int UMAX, int RMAX, int W, int PREC>
+__global__ __launch_bounds__(kPropBlock) void k_flow(EngineArgs e, FlowArgs fa,
+                                                     NetArgs<RMAX, W> net) {
+    flow_run<NetArgs<RMAX, W>, UMAX, RMAX, W, PREC>(e, fa, net);
+}
+
+__global__ void k_flow_check(EngineArgs e, FlowArgs fa) {
+    if (fa.ctl[kCtlAbort] == 0u) return;
+    const int f = e.f_lo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (f >= e.f_hi || !slot_active(e, f)) return;
+    e.fstatus[f] = LIK_STATUS_SCHEDULER;
+    e.fll[f] = __builtin_nan("");
+    e.fflags[f] |= kFlagStopped;
+}
+
+// ---------------------------------------------------------------------------
 // weigh: log-sum-exp into the running log-likelihood, then systematic
 // resampling with q_j = floor(e_j 2^32), integer prefix sums C, one offset
 // rho = floor(w64 Q / 2^64) and ancestors a_j = min{i : H C_{i+1} > j Q + rho}.
@@ -285,7 +276,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     {
         uint64_t evs = 0;
         for (int j = tid; j < H; j += kWeighBlock) evs += d.pev[j];
-        evs = wave_sum_u64(evs);
+        evs = wave_sum_u64(evs, lane);
         if (lane == 0) redu[wave] = evs;
         __syncthreads();
         if (tid == 0) {
@@ -316,25 +307,11 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     // kept in lw for this thread's second pass; and the maximum
     double mx = -__builtin_inf();
     for (int j = j0; j < j1; ++j) {
-        double l = 0.0;
-        for (int k = 0; k < d.P; ++k) {
-            const int cnt = xs[(size_t)d.obs_species[k] * d.Hp + j];
-            if (d.obs_kind == LIK_OBS_LOGNORMAL) {
-                if (cnt <= 0) {
-                    l = -__builtin_inf();
-                    break;
-                }
-                const double z = (logy[k] - dlog((double)cnt)) / d.sigma;
-                l = l - 0.5 * (z * z);
-            } else {
-                const double z = (yt[k] - (double)cnt) / d.sigma;
-                l = l - 0.5 * (z * z);
-            }
-        }
+        const double l = obs_logweight(d, xs, j, logy, yt);
         lw[j] = l;
         mx = fmax(mx, l);
     }
-    mx = wave_max(mx);
+    mx = wave_max(mx, lane);
     if (lane == 0) red[wave] = mx;
     __syncthreads();
     if (tid == 0) {
@@ -363,12 +340,12 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
         Cs[j] = q;
         qsum += q;
     }
-    s = wave_sum(s);
+    s = wave_sum(s, lane);
     __syncthreads();  // red[] reuse
     if (lane == 0) red[wave] = s;
 
     // exclusive scan of the per-thread sums (thread order = particle order)
-    const uint64_t incl = wave_incl_scan_u64(qsum);
+    const uint64_t incl = wave_incl_scan_u64(qsum, lane);
     if (lane == 63) redu[wave] = incl;
     __syncthreads();
     uint64_t base = incl - qsum;
@@ -381,21 +358,10 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     if (tid == 0) {
         double S = red[0];
         for (int w = 1; w < kWeighBlock / 64; ++w) S += red[w];
-        // running log-likelihood: log of the mean weight plus the
-        // particle-independent part of the observation density
-        const double per_comp = dlog(d.sigma) + 0.5 * dlog(2.0 * 3.141592653589793);
-        double cst = -((double)d.P * per_comp);
-        if (d.obs_kind == LIK_OBS_LOGNORMAL)
-            for (int k = 0; k < d.P; ++k) cst = cst - dlog(yt[k]);
-        const double inc = ((mx + dlog(S)) - dlog((double)H)) + cst;
-        e.fll[f] = e.fll[f] + inc;
+        // running log-likelihood
+        e.fll[f] = e.fll[f] + loglik_increment(d, mx, S, yt);
         e.tcur[f] = t + 1;
-        if (t + 1 < T) {
-            const Block4 b = philox4x32_10(0u, 0u, (d.traj << 16) | (uint32_t)(t + 1),
-                                           (d.theta_id << 2) | 1u, (uint32_t)d.seed,
-                                           (uint32_t)(d.seed >> 32));
-            bcast_u = ((uint64_t)b.w1 << 32) | b.w0;
-        }
+        if (t + 1 < T) bcast_u = resample_word(d, t);
     }
     if (t + 1 >= T) return;
     __syncthreads();
@@ -417,15 +383,14 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     // Ordering cost of the next interval: the events its particles are
     // expected to need, total propensity of their starting states times the
     // interval's length (a scheduling estimate only).
-    pred = wave_sum_f32(pred);
+    pred = wave_sum_f32(pred, lane);
     __syncthreads();  // red[] reuse
     if (lane == 0) red[wave] = (double)pred;
     __syncthreads();
     if (tid == 0) {
         double tot = 0.0;
         for (int w = 0; w < kWeighBlock / 64; ++w) tot += red[w];
-        const double expect = tot * (d.t_obs[t + 1] - d.t_obs[t]);
-        e.cost[f] = expect >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)expect;
+        e.cost[f] = cost_estimate(d, t, tot);
     }
 }
 
@@ -535,6 +500,42 @@ hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, co
     if (umax == 32 && rmax == 64)
         return launch_prop_t<32, 64, 4>(e, group, n_items, net, precision, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_flow_setup(const EngineArgs &e, const FlowArgs &fa, hipStream_t s) {
+    hipLaunchKernelGGL(k_flow_init, dim3(1024), dim3(256), 0, s, fa);
+    const int F = e.f_hi - e.f_lo;
+    if (F > 0) hipLaunchKernelGGL(k_flow_seed, dim3((F + 255) / 256), dim3(256), 0, s, e, fa);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_check(const EngineArgs &e, const FlowArgs &fa, hipStream_t s) {
+    const int F = e.f_hi - e.f_lo;
+    if (F > 0) hipLaunchKernelGGL(k_flow_check, dim3((F + 255) / 256), dim3(256), 0, s, e, fa);
+    return hipGetLastError();
+}
+
+template <int UMAX, int RMAX, int W>
+static const void *flow_fn(int precision) {
+    return precision == LIK_FP32_MIXED ? (const void *)k_flow<UMAX, RMAX, W, LIK_FP32_MIXED>
+                                       : (const void *)k_flow<UMAX, RMAX, W, LIK_FP64>;
+}
+
+static const void *flow_kernel(int umax, int rmax, int precision) {
+    if (umax == 4 && rmax == 8) return flow_fn<4, 8, 1>(precision);
+    if (umax == 8 && rmax == 16) return flow_fn<8, 16, 1>(precision);
+    if (umax == 32 && rmax == 64) return flow_fn<32, 64, 4>(precision);
+    return nullptr;
+}
+
+hipError_t launch_flow(const EngineArgs &e, const FlowArgs &fa, unsigned n_waves, const void *net,
+                       int umax, int rmax, int precision, hipStream_t s) {
+    const void *fn = flow_kernel(umax, rmax, precision);
+    if (!fn || n_waves == 0) return hipErrorInvalidValue;
+    EngineArgs ea = e;
+    FlowArgs fb = fa;
+    void *args[] = {(void *)&ea, (void *)&fb, const_cast<void *>(net)};
+    return hipLaunchKernel(fn, dim3(n_waves), dim3(kPropBlock), args, 0, s);
 }
 
 hipError_t launch_weigh(const EngineArgs &e, hipStream_t s) {

@@ -23,9 +23,14 @@ constexpr int kCostKeys = 129;    // quarter octaves of expected events per lane
 constexpr uint32_t kFlagStopped = 1u;
 constexpr int32_t kCountLimit = 1 << 30;
 // LDS that stages a pool's starting counts, per wavefront (6 KiB: 26
-// wavefronts per CU fit in its 160 KiB).  A pool takes U words per particle,
-// so G <= kPoolLdsWords / (64 U).
+// wavefronts per CU fit in its 160 KiB).  A pool takes U words per particle
+// for the counts and half a word for its processing order (16-bit indexes),
+// so G <= kPoolLdsWords / (64 U + 32).
 constexpr int kPoolLdsWords = 1536;
+__host__ __device__ constexpr int pool_lds_cap(int U) { return kPoolLdsWords / (64 * U + 32); }
+// Pools of up to 64 * kSortPerLane particles are taken heaviest first.
+constexpr int kSortPerLane = 6;
+constexpr int kSortBuckets = 64;  // half octaves of the expected cost, below the heaviest
 
 // Reaction kinds after validation of the reactant orders.
 enum : int32_t { kOrder0 = 0, kOrder1 = 1, kOrder2Homo = 2, kOrder2Hetero = 3 };
@@ -94,6 +99,31 @@ struct EngineArgs {
     uint32_t group_off[kMaxGroups];  // first item of each group
 };
 
+// Flow engine (one launch runs every interval of a batch; flow.hpp).  Its
+// control words sit 128 bytes apart in ctl.
+enum : int {
+    kCtlHead = 0,        // next ring position a wavefront claims
+    kCtlTail = 32,       // next ring position a work item is written to
+    kCtlFinished = 64,   // slots that need no further interval
+    kCtlAbort = 96,      // nonzero: a wavefront saw no progress for stall_ticks
+    kCtlProgress = 128,  // work items finished
+    kCtlWords = 160
+};
+struct FlowArgs {
+    // ring[pos & mask] = (pos + 1) << 32 | item once the item of position pos
+    // is written, pos << 32 while the slot is free for position pos
+    uint64_t *ring;
+    uint32_t *remaining;   // [slots] work items of the slot's interval not finished
+    uint32_t *ctl;         // [kCtlWords]
+    uint32_t mask;         // ring capacity - 1: a power of two, at least twice the
+                           // slots' groups of 64 (items outstanding at any time)
+    int32_t n_slots;       // the batch is done when this many slots have finished
+    int32_t g_par;         // largest pool (groups of 64) of a work item
+    int32_t pad;
+    uint64_t stall_ticks;  // wall-clock ticks without a finished item before a
+                           // waiting wavefront gives up (a scheduler fault)
+};
+
 #ifndef __HIPCC_RTC__
 // Host-side launchers (kernels.hip).
 hipError_t launch_order(const EngineArgs &e, hipStream_t s);
@@ -101,6 +131,19 @@ hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, co
                             int umax, int rmax, int precision, bool persistent, hipStream_t s);
 constexpr int kPersistentMaxR = 16;  // rates per lane in registers: small networks only
 hipError_t launch_weigh(const EngineArgs &e, hipStream_t s);
+// Flow engine: ring reset and first items; the launch (generic network
+// tables; n_waves wavefronts, one work item each); the scheduler-fault check.
+hipError_t launch_flow_setup(const EngineArgs &e, const FlowArgs &fa, hipStream_t s);
+hipError_t launch_flow(const EngineArgs &e, const FlowArgs &fa, unsigned n_waves, const void *net,
+                       int umax, int rmax, int precision, hipStream_t s);
+hipError_t launch_flow_check(const EngineArgs &e, const FlowArgs &fa, hipStream_t s);
+// Ring capacity for F slots of nchunk groups of 64 particles.
+inline uint32_t flow_ring_capacity(size_t F, int nchunk) {
+    const size_t need = 2 * F * (size_t)nchunk;
+    uint32_t c = 1024;
+    while ((size_t)c < need && c < (1u << 31)) c <<= 1;
+    return c;
+}
 
 // Per-request setup / results.  A request is n_theta rate vectors against M
 // trajectories, occupying slots base .. base + n_theta*M - 1.

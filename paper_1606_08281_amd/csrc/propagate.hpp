@@ -77,6 +77,19 @@ __device__ __forceinline__ double wave_uniform(double v) {
 __device__ __forceinline__ float wave_uniform(float v) {
     return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
 }
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <class T>
+__device__ __forceinline__ T *wave_uniform(T *p) {
+    return reinterpret_cast<T *>(wave_uniform((uint64_t)reinterpret_cast<unsigned long long>(p)));
+}
 
 template <bool B, class T, class F>
 struct pick_type {
@@ -152,36 +165,40 @@ __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x
 // kernels).
 // ---------------------------------------------------------------------------
 template <class NetT, int UMAX, int RMAX, int W, int PREC>
-__device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &net, int group) {
-    if (blockIdx.x >= e.item_count[group]) return;
-    const uint32_t item = e.items[e.group_off[group] + blockIdx.x];
+__device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, uint32_t item) {
+    // Every value of the item's context is the same on all lanes: moved to
+    // scalar registers (a persistent caller loads them with vector loads,
+    // after stores of earlier items, and would otherwise keep them in
+    // vector registers through the event loop).
+    item = wave_uniform(item);
     const int f = (int)(item >> 6);
     const FilterDesc &d = e.desc[f];
-    const int t = e.tcur[f];
+    const int t = wave_uniform(e.tcur[f]);
 
     const int U = net.U;
     const int R = net.R;
-    const int H = d.H;
-    const int Hp = d.Hp;
-    const int lane = (int)threadIdx.x;
+    const int H = wave_uniform(d.H);
+    const int Hp = wave_uniform(d.Hp);
+    const int lane = lane_id();
     const int p0 = (int)(item & 63u) * kPropBlock;
-    const int pool = e.pool[f];  // (priority << 6) | (G - 1)
+    const int pool = wave_uniform((int)e.pool[f]);  // (priority << 6) | (G - 1)
     const int p1 = min(p0 + ((pool & 63) + 1) * kPropBlock, H);
 
-    const double t_start = (t == 0) ? d.t0 : d.t_obs[t - 1];
-    const double t_end = d.t_obs[t];
-    const uint32_t c2 = (d.traj << 16) | (uint32_t)t;
-    const uint32_t c3 = d.theta_id << 2;  // purpose 0: reaction events
-    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
-    const int32_t *src = (t & 1) ? d.xb : d.xa;
-    int32_t *dst = (t & 1) ? d.xa : d.xb;
+    const double t_start = wave_uniform((t == 0) ? d.t0 : d.t_obs[t - 1]);
+    const double t_end = wave_uniform(d.t_obs[t]);
+    const uint32_t c2 = wave_uniform((d.traj << 16) | (uint32_t)t);
+    const uint32_t c3 = wave_uniform(d.theta_id << 2);  // purpose 0: reaction events
+    const uint64_t seed = wave_uniform(d.seed);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const int32_t *src = wave_uniform((t & 1) ? d.xb : d.xa);
+    int32_t *dst = wave_uniform((t & 1) ? d.xa : d.xb);
     // Descriptor fields the event loop uses, read once: the loop's stores
     // could alias the descriptor as far as the compiler knows.
-    const uint32_t event_cap = d.event_cap;
-    uint32_t *pev_p = d.pev;
-    float *pa0_p = d.pa0;
-    const int32_t *anc_p = d.anc;
-    const int32_t *x0_p = d.x0;
+    const uint32_t event_cap = wave_uniform(d.event_cap);
+    uint32_t *pev_p = wave_uniform(d.pev);
+    float *pa0_p = wave_uniform(d.pa0);
+    const int32_t *anc_p = wave_uniform(d.anc);
+    const int32_t *x0_p = wave_uniform(d.x0);
     const int refill_min = e.refill_min;
 
     using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
@@ -196,10 +213,77 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     // particle's results are stored straight to global memory: stores do
     // not stall).  A pool of at most 64 particles has one per lane and
     // reads its counts directly.
-    __shared__ int32_t pool_x[kPoolLdsWords];  // [U][npool]
+    //
+    // Lanes take the pool's particles heaviest first (longest processing
+    // time first): a pool's length is set by the particles taken last, and
+    // heavy particles taken last leave most lanes idle while they finish.
+    // The weight of a particle is the total propensity of its starting
+    // counts (its expected events over the interval, up to the common
+    // interval length), bucketed by half octave below the pool's heaviest;
+    // order[s] is the pool offset of the s-th particle taken.
+    // Which lane runs a particle, and when, never changes its result.
+    __shared__ int32_t pool_x[kPoolLdsWords];  // [U][npool], then order[npool] (uint16)
+    __shared__ uint32_t bucket[kSortBuckets];
     const int npool = p1 - p0;
     const bool staged = npool > kPropBlock;
-    if (staged) {
+    const bool ordered = staged && t > 0 && npool <= kSortPerLane * kPropBlock &&
+                         U * npool + (npool + 1) / 2 <= kPoolLdsWords;
+    uint16_t *order = reinterpret_cast<uint16_t *>(pool_x + U * npool);
+    if (ordered) {
+        bucket[lane] = 0u;
+        int a[kSortPerLane];
+        uint32_t key[kSortPerLane];
+        uint32_t kmax = 0u;
+#pragma unroll
+        for (int k = 0; k < kSortPerLane; ++k) {
+            const int q = lane + k * kPropBlock;
+            a[k] = (q < npool) ? anc_p[p0 + q] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kSortPerLane; ++k) {
+            const int q = lane + k * kPropBlock;
+            int xs[UMAX];
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u)
+                xs[u] = (u < U && q < npool) ? src[(size_t)u * Hp + a[k]] : 0;
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u)
+                if (u < U && q < npool) pool_x[u * npool + q] = xs[u];
+            Real Sk[RMAX];
+            const float w = (float)running_sums<NetT, RMAX, Real>(net, c, xs, Sk);
+            // binary32 bits of a non-negative weight, shifted to sign,
+            // exponent and leading fraction bit: half octaves, in order
+            key[k] = (q < npool) ? (__float_as_uint(w) >> 22) : 0u;
+            kmax = max(kmax, key[k]);
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) kmax = max(kmax, lane_read(kmax, lane ^ m));
+        __syncthreads();  // the workgroup is this one wavefront
+#pragma unroll
+        for (int k = 0; k < kSortPerLane; ++k) {
+            const int q = lane + k * kPropBlock;
+            key[k] = min(kmax - key[k], (uint32_t)(kSortBuckets - 1));
+            if (q < npool) atomicAdd(&bucket[key[k]], 1u);
+        }
+        __syncthreads();
+        {  // exclusive prefix sum over the buckets, heaviest first
+            const uint32_t v = bucket[lane];
+            uint32_t incl = v;
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) {
+                const uint32_t o = lane_read(incl, lane >= m ? lane - m : lane);
+                if (lane >= m) incl += o;
+            }
+            bucket[lane] = incl - v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSortPerLane; ++k) {
+            const int q = lane + k * kPropBlock;
+            if (q < npool) order[atomicAdd(&bucket[key[k]], 1u)] = (uint16_t)q;
+        }
+        __syncthreads();
+    } else if (staged) {
 #pragma unroll 1
         for (int q = lane; q < npool; q += kPropBlock) {
             if (t == 0) {
@@ -221,15 +305,18 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     uint32_t n = 0;
     int j = p0 + lane;  // the lane's particle
     bool have = j < p1;
-    auto load_lds = [&](int jj) {
+    // the s-th particle taken from the pool: its index and starting counts
+    auto load_lds = [&](int s) {
+        const int q = ordered ? (int)order[s] : s;
+        j = p0 + q;
 #pragma unroll
-        for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? pool_x[u * npool + (jj - p0)] : 0;
+        for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? pool_x[u * npool + q] : 0;
         clock = t_start;
         n = 0;
     };
     if (have) {
         if (staged) {
-            load_lds(j);
+            load_lds(lane);
         } else if (t == 0) {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? x0_p[u] : 0;
@@ -280,10 +367,9 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
                     pend = false;
                     const int nj = next + (int)__popcll(idle & ((1ull << lane) - 1ull));
                     if (nj < p1) {
-                        j = nj;
                         have = true;
                         pend = true;
-                        load_lds(j);
+                        load_lds(nj - p0);
                     }
                 }
                 next += n_idle;
@@ -293,6 +379,13 @@ __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &
     }
     if (pend) retire();
     if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[f], st);
+}
+
+// One wavefront per work item of the iteration's list.
+template <class NetT, int UMAX, int RMAX, int W, int PREC>
+__device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &net, int group) {
+    if (blockIdx.x >= e.item_count[group]) return;
+    run_item<NetT, UMAX, RMAX, W, PREC>(e, net, e.items[e.group_off[group] + blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------

@@ -268,7 +268,7 @@ bool try_place(lik_server *S, Request &r, std::string *err) {
         if (S->opts.kernel != LIK_KERNEL_GENERIC) {
             G.launch.spec = specialized_kernel(*r.net, r.precision, err);
             if (G.launch.spec && G.launch.persistent)
-                G.launch.spec_p = specialized_kernel(*r.net, r.precision, err, true);
+                G.launch.spec_p = specialized_kernel(*r.net, r.precision, err, kSpecPersistent);
             // an unavailable specialisation leaves the group on the generic kernel
         }
     }

@@ -120,12 +120,15 @@ std::string specialized_source(const lik_network &net, int precision) {
          "typedef __hip_internal::int32_t int32_t;\n"
          "typedef __hip_internal::int64_t int64_t;\n"
          "typedef __hip_internal::uint8_t uint8_t;\n"
-         "#include \"propagate.hpp\"\n"
+         "typedef __hip_internal::uint16_t uint16_t;\n"
+         "#include \"flow.hpp\"\n"
          "namespace lik {\n"
          "static_assert(sizeof(EngineArgs) == "
       << sizeof(EngineArgs) << ", \"EngineArgs layout\");\n"
          "static_assert(sizeof(FilterDesc) == "
-      << sizeof(FilterDesc) << ", \"FilterDesc layout\");\n";
+      << sizeof(FilterDesc) << ", \"FilterDesc layout\");\n"
+         "static_assert(sizeof(FlowArgs) == "
+      << sizeof(FlowArgs) << ", \"FlowArgs layout\");\n";
     o << "struct SpecNet {\n  static constexpr int U = " << U << ", R = " << R << ";\n";
     auto arr = [&](const char *name, const int32_t *v) {
         o << "  static constexpr int " << name << "[" << R << "] = {";
@@ -147,6 +150,11 @@ std::string specialized_source(const lik_network &net, int precision) {
          "  const lik::SpecNet net{};\n"
          "  lik::propagate_item<lik::SpecNet, "
       << U << ", " << R << ", " << W << ", " << precision << ">(e, net, group);\n}\n";
+    o << "extern \"C\" __global__ __launch_bounds__(64) void lik_flow_spec("
+         "lik::EngineArgs e, lik::FlowArgs fa) {\n"
+         "  const lik::SpecNet net{};\n"
+         "  lik::flow_run<lik::SpecNet, "
+      << U << ", " << R << ", " << W << ", " << precision << ">(e, fa, net);\n}\n";
     if (R <= kPersistentMaxR)
         o << "extern \"C\" __global__ __launch_bounds__(64) void lik_propagate_spec_p("
              "lik::EngineArgs e, int group) {\n"
@@ -195,7 +203,7 @@ bool precompile_specialized(const lik_network &net, int precision, std::string *
 }
 
 hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err,
-                                 bool persistent) {
+                                 int kind) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         *err = "hipGetDevice failed";
@@ -203,7 +211,10 @@ hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *e
     }
     std::lock_guard<std::mutex> g(net.spec_lock);
     auto it = net.spec.find({dev, precision});
-    if (it != net.spec.end()) return persistent ? it->second.persistent : it->second.item;
+    auto pick = [kind](const lik_network::SpecKernels &k) {
+        return kind == kSpecPersistent ? k.persistent : kind == kSpecFlow ? k.flow : k.item;
+    };
+    if (it != net.spec.end()) return pick(it->second);
 
     std::vector<char> code;
     std::string src, path;
@@ -233,8 +244,9 @@ hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *e
     if (net.R <= kPersistentMaxR && hipModuleGetFunction(&k.persistent, mod,
                                                          "lik_propagate_spec_p") != hipSuccess)
         k.persistent = nullptr;
+    if (hipModuleGetFunction(&k.flow, mod, "lik_flow_spec") != hipSuccess) k.flow = nullptr;
     net.spec[{dev, precision}] = k;
-    return persistent ? k.persistent : k.item;
+    return pick(k);
 }
 
 void release_specialized(lik_network &net) {

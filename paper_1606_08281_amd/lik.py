@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "liblik.so")
 
 LIK_OK, LIK_EINVAL, LIK_ENOMEM, LIK_EDEVICE, LIK_EUNSUPPORTED, LIK_ETIMEOUT = 0, -1, -2, -3, -4, -5
 STATUS_OK, STATUS_EVENT_CAP, STATUS_COUNT_OVERFLOW, STATUS_BAD_THETA = 0, 1, 2, 3
+STATUS_SCHEDULER = 4
 OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
 FP64, FP32_MIXED = 0, 1
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
@@ -59,7 +60,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("pool_min", ctypes.c_int32), ("pool_max", ctypes.c_int32),
                 ("pool_events", ctypes.c_uint32), ("pool_first", ctypes.c_int32),
                 ("refill_min", ctypes.c_int32), ("priority", ctypes.c_int32),
-                ("items_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("items_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -189,6 +191,7 @@ class Network:
 
     def set_tuning(self, pool_min=None, pool_max=None, pool_events=None, pool_first=None,
                    refill_min=None, priority=None, items_per_cu=None, persistent=None,
+                   schedule=None,
                    default=False):
         """Work partitioning of the propagation kernels (never changes results)."""
         if default:
@@ -198,7 +201,8 @@ class Network:
         for k, v in (("pool_min", pool_min), ("pool_max", pool_max),
                      ("pool_events", pool_events), ("pool_first", pool_first),
                      ("refill_min", refill_min), ("priority", priority),
-                     ("items_per_cu", items_per_cu), ("persistent", persistent)):
+                     ("items_per_cu", items_per_cu), ("persistent", persistent),
+                     ("schedule", schedule)):
             if v is not None:
                 setattr(t, k, int(v))
         _check(lib().lik_network_set_tuning(self.handle, ctypes.byref(t)))
@@ -355,7 +359,7 @@ class Server:
         tp = None
         if tuning is not None:
             t = dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1,
-                     priority=0, items_per_cu=160, persistent=0)
+                     priority=0, items_per_cu=160, persistent=0, schedule=0)
             t.update(tuning)
             self._tuning = Tuning(**{k: int(v) for k, v in t.items()})
             tp = ctypes.addressof(self._tuning)

@@ -27,6 +27,8 @@ COPY_BYTES = 1 << 30  # bench.py --copy-calibration: 2^28 float32 copied device 
 KERNEL_SOURCES = ["paper_1606_08281_amd/csrc/propagate.hpp",
                   "paper_1606_08281_amd/csrc/devmath.hpp",
                   "paper_1606_08281_amd/csrc/lik_internal.hpp",
+                  "paper_1606_08281_amd/csrc/weigh.hpp",
+                  "paper_1606_08281_amd/csrc/flow.hpp",
                   "paper_1606_08281_amd/csrc/kernels.hip",
                   "paper_1606_08281_amd/csrc/specialize.cpp",
                   "paper_1606_08281_amd/csrc/host.hpp",

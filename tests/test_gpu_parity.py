@@ -29,9 +29,11 @@ def _oracle(orc, wl, theta=None, theta_ids=None, H=None, precision=0, event_cap=
 
 
 def _gpu(wl, theta=None, theta_ids=None, H=None, precision=0, event_cap=0, trajectories=None,
-         seed=None, kernel=1):
+         seed=None, kernel=1, tuning=None):
     from paper_1606_08281_amd import lik
     net = lik.Network(wl.net.orders, wl.net.stoich)
+    if tuning:
+        net.set_tuning(**tuning)
     return lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma,
                           wl.theta if theta is None else theta,
                           wl.trajectories if trajectories is None else trajectories,
@@ -258,7 +260,15 @@ TUNINGS = [dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=
            dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=9, priority=0,
                 items_per_cu=0, persistent=1),
            dict(pool_min=4, pool_max=4, pool_events=0, pool_first=4, refill_min=64, priority=0,
-                items_per_cu=0, persistent=1)]
+                items_per_cu=0, persistent=1),
+           dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1, priority=0,
+                items_per_cu=160, persistent=0, schedule=1),
+           dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=1, priority=0,
+                items_per_cu=0, persistent=1, schedule=1),
+           dict(pool_min=64, pool_max=64, pool_events=0, pool_first=64, refill_min=5,
+                priority=0, items_per_cu=0, persistent=0, schedule=1)]
+
+FLOW = dict(schedule=1)
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -287,6 +297,77 @@ def test_work_partitioning_never_changes_results(orc, kernel):
     assert_parity(lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta[sub], trajs,
                                  wl.n_particles, wl.seed, theta_ids=sub, aux=True, kernel=kernel),
                   ref)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_flow_schedule_equals_per_interval_schedule(orc, kernel):
+    # one persistent launch, filters advancing independently: bit-identical
+    # to one launch sequence per interval, over statuses, stopped filters,
+    # uneven trajectory lengths, ragged particle counts and both precisions
+    wl = W.immigration_death_workload(n_theta=6, n_particles=70)
+    theta = np.array([[10, 0.1], [-1, 0.1], [np.nan, 1], [np.inf, 1], [0, 0], [1e-300, 1e-300]])
+    cases = [("statuses", dict(wl=wl, theta=theta), True),
+             ("event cap 3", dict(wl=wl, theta=wl.theta[:3], event_cap=3), False)]
+    tw = W.telegraph_workload(n_theta=4, n_traj=3, n_obs=20, n_particles=130)
+    trajs = []
+    for m, T in enumerate([1, 20, 7]):
+        tr = dict(tw.trajectories[m])
+        tr["t_obs"] = tr["t_obs"][:T]
+        tr["y"] = tr["y"][:T]
+        trajs.append(tr)
+    th = np.vstack([W.TELEGRAPH_TRUTH * s for s in [1.0, 0.5, 2.0, 1.3]])
+    cases.append(("uneven T", dict(wl=tw, theta=th, trajectories=trajs), True))
+    z = W.telegraph_workload(n_theta=2, n_traj=1, n_obs=4, n_particles=16)
+    zt = dict(z.trajectories[0])
+    zt["x0"] = np.array([1, 0, 0, 0], np.int32)
+    zth = np.vstack([np.zeros(6), [0.1, 0.1, 0.0, 1.0, 0.0, 1.0]])
+    cases.append(("-inf", dict(wl=z, theta=zth, trajectories=[zt]), True))
+    for H in (1, 65, 4096):
+        iw = W.immigration_death_workload(n_theta=5, n_particles=H)
+        cases.append((f"H={H}", dict(wl=iw), True))
+    for prec in (0, 1):
+        sw = W.telegraph_workload(n_theta=8, n_traj=2, n_obs=12, n_particles=1000)
+        cases.append((f"telegraph precision {prec}", dict(wl=sw, precision=prec), True))
+    for name, kw, state in cases:
+        _say("flow vs per-interval:", name, "kernel", kernel)
+        a = _gpu(kernel=kernel, **kw)
+        b = _gpu(kernel=kernel, tuning=FLOW, **kw)
+        for k in ("loglik", "status", "filter_events", "filter_loglik", "final_state"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), (name, k)
+        ref = _oracle(orc, kw["wl"], theta=kw.get("theta"), trajectories=kw.get("trajectories"),
+                      event_cap=kw.get("event_cap") or 100_000_000,
+                      precision=kw.get("precision", 0))
+        assert_parity(b, ref, check_state=state,
+                      abs_tol=FP32_ABS if kw.get("precision") else None)
+
+
+def test_flow_schedule_graph_replays_and_random_network(orc):
+    import torch
+    from paper_1606_08281_amd import lik
+    wl = W.telegraph_workload(n_theta=24, n_traj=2, n_obs=12, n_particles=200)
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    net.set_tuning(**FLOW)
+    eager = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories,
+                            wl.n_theta, wl.n_particles)
+    graph = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories,
+                            wl.n_theta, wl.n_particles, graph=True)
+    theta = torch.from_numpy(wl.theta).cuda()
+    for k in range(3):
+        _say("flow graph replay", k)
+        ll_e = eager.run(theta, wl.seed + k)[0].clone()
+        junk = torch.randn(4096, device="cuda").sum()
+        ll_g = graph.run(theta, wl.seed + k)[0].clone()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert torch.equal(ll_e, ll_g), k
+    rw = W.random_network_workload(n_theta=64, n_particles=96, n_obs=3, events_per_interval=300)
+    idx = np.arange(0, 64, 8)
+    for kernel in KERNELS:
+        _say("flow random 20x40 kernel", kernel)
+        a = _gpu(rw, theta=rw.theta[idx], theta_ids=idx, kernel=kernel)
+        b = _gpu(rw, theta=rw.theta[idx], theta_ids=idx, kernel=kernel, tuning=FLOW)
+        for k in ("loglik", "status", "filter_events", "final_state"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
 def test_autotune_picks_a_candidate_and_keeps_results():
