@@ -93,7 +93,7 @@ def main():
                          "the fastest (default: the library's default partitioning)")
     ap.add_argument("--tuning", default=None,
                     help="work partitioning pool_min,pool_max,pool_events,pool_first,refill_min,"
-                         "priority,items_per_cu,persistent,schedule "
+                         "priority,items_per_cu,persistent,schedule,urgent_events "
                          "(default: the library's)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 generic, 2 network-specialised propagation kernel")
@@ -128,7 +128,7 @@ def main():
 
     if args.tuning:
         keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min", "priority",
-                "items_per_cu", "persistent", "schedule")
+                "items_per_cu", "persistent", "schedule", "urgent_events")
         net.set_tuning(**dict(zip(keys, (int(v) for v in args.tuning.split(",")))))
     tuning = net.tuning()
     if args.autotune:
@@ -186,11 +186,13 @@ def main():
 
     # HBM bytes per launch from the committed rocprofv3 counter summary of
     # this kernel and configuration; null once the kernel sources differ.
+    flow = tuning.get("schedule", 0) == 1
+    kname = "lik_flow_spec" if flow else "lik_propagate_spec"
     traffic = None
     if (args.precision == 0 and args.kernel in (0, 2) and not args.tuning and not args.autotune):
         from paper_1606_08281_amd import profsum
         rec = profsum.read_traffic(os.path.join(
-            ROOT, "profiles", "lik_propagate_spec_traffic_telegraph_1024x10x1000x50_fp64.txt"))
+            ROOT, "profiles", f"{kname}_traffic_telegraph_1024x10x1000x50_fp64.txt"))
         if rec is not None:
             traffic = float(rec["hbm_bytes_per_launch"])
 
@@ -236,7 +238,10 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tlane-op/s",
             "frac": achieved / peak, "traffic": traffic,
-            "kernel": "k_propagate (direct-method SSA to the next observation)",
+            "kernel": (kname + ": every interval in one launch (direct-method SSA work items "
+                       "and each filter's weighing/resampling)") if flow else
+                      (kname + ": direct-method SSA to the next observation, one launch per "
+                       "interval"),
             "basis": basis,
             "ops_per_event": ope,
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

@@ -134,9 +134,14 @@ typedef struct lik_tuning {
                               to its next interval as soon as its own particles are
                               weighed (the server always advances its slots together;
                               persistent is ignored under 1) */
+    uint32_t urgent_events; /* schedule 1: a filter whose intervals left times the expected
+                               events per lane of its items reach this (one on the critical
+                               path) queues its items at once; the others wait while the
+                               queue is long, so urgent items are taken soon;
+                               0: first come, first served */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 0}) / reads a network's
+/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000}) / reads a network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

@@ -197,15 +197,15 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
-        {1, 6, 1536, 1, 1, 0, 160, 0, 0},  // default
-        {1, 4, 1024, 1, 1, 0, 160, 0, 0},
-        {2, 6, 2048, 1, 1, 0, 160, 0, 0},
-        {1, 1, 0, 1, 1, 0, 0, 0, 0},       // one group of 64 particles per wavefront
-        {1, 6, 2048, 1, 1, 0, 320, 0, 0},
-        {1, 1, 0, 1, 1, 0, 0, 1, 0},       // persistent wavefronts (R <= 16)
-        {1, 2, 1024, 1, 1, 0, 160, 1, 0},
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1},  // flow schedule
-        {1, 6, 3072, 1, 1, 0, 80, 0, 1},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000},  // default: flow schedule
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 32000},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 0},      // flow, first come first served
+        {1, 4, 1024, 1, 1, 0, 160, 0, 1, 16000},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 0, 16000},  // one launch sequence per interval
+        {1, 4, 1024, 1, 1, 0, 160, 0, 0, 16000},
+        {2, 6, 2048, 1, 1, 0, 160, 0, 0, 16000},
+        {1, 1, 0, 1, 1, 0, 0, 0, 0, 16000},       // one group of 64 particles per wavefront
+        {1, 1, 0, 1, 1, 0, 0, 1, 0, 16000},       // persistent wavefronts (R <= 16)
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;
@@ -357,7 +357,7 @@ size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
     b += align256(F * (Hp / 64) * 4);         // items
     b += align256(kMaxGroups * 4);            // item_count
     b += align256(kMaxGroups * 4);            // item_cursor
-    b += align256((size_t)flow_ring_capacity(F, Hp / 64) * 8);  // flow ring
+    b += align256((size_t)flow_ring_capacity(F, Hp / 64) * 8 * kFlowRings);  // flow rings
     b += align256(F * 4);                     // flow: items left per slot
     b += align256(kCtlWords * 4);             // flow: control words
     b += align256(request_state_bytes((int64_t)F, net->U, Hp));
@@ -408,7 +408,7 @@ EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_byte
     L.e.item_count = (uint32_t *)take(kMaxGroups * 4);
     L.e.item_cursor = (uint32_t *)take(kMaxGroups * 4);
     memset(&L.fa, 0, sizeof(L.fa));
-    L.fa.ring = (uint64_t *)take((size_t)ring_capacity * 8);
+    L.fa.ring = (uint64_t *)take((size_t)ring_capacity * 8 * kFlowRings);
     L.fa.remaining = (uint32_t *)take(slots * 4);
     L.fa.ctl = (uint32_t *)take(kCtlWords * 4);
     L.fa.mask = ring_capacity - 1;
@@ -543,6 +543,9 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
             khz <= 0)
             khz = 100000;
         L.fa.stall_ticks = (uint64_t)khz * 1000ull * 60ull;  // one minute
+        L.fa.urgent_events = net->tuning.urgent_events;
+        // about five waiting items for every four wavefronts the device holds
+        L.fa.backlog = std::max(compute_units(), 1u) * 30u;
     }
 
     RequestArgs r;

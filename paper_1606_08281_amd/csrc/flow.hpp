@@ -14,15 +14,28 @@
 // items of its next interval to the ring.  Wavefronts left without an item
 // leave once every filter is done.
 //
-// Ring protocol (a bounded multi-producer multi-consumer queue with one
-// sequence word per slot): a consumer claims position p from the head
-// counter and waits until slot p & mask holds sequence p + 1, takes the
-// item and marks the slot free for position p + capacity; a producer
-// claims p from the tail counter, waits until the slot holds sequence p
-// (free for p) and writes (p + 1, item).  At most one interval of items per
-// filter is outstanding, so at most sum(groups of 64) <= capacity / 2 items
-// sit in the ring and a producer never waits for a slot that no wavefront
-// has claimed.  Hand-offs between wavefronts (item results before the
+// Ring protocol (bounded multi-producer multi-consumer queues with one
+// sequence word per slot): a producer reserves position p from a ring's
+// tail counter, waits until slot p & mask holds sequence p (free for p) and
+// writes (p + 1, entry); a consumer takes p from the head counter, waits
+// until the slot holds p + 1, takes the entry and marks the slot free for
+// position p + capacity.  Every wavefront claims its item with one
+// fetch-and-add, so thousands of waiting wavefronts never contend on a
+// compare-and-swap.
+//
+// Priority without a second claim path: first come, first served would let
+// a filter wait at every interval behind a whole generation of other
+// filters' items, and the filters with the longest chains (many intervals
+// left times long items) would set the end of the run.  So the item ring is
+// kept short: a filter that is not urgent and finds `backlog` items already
+// waiting is parked (its id goes to a second ring) instead of appending its
+// items; every wavefront that finishes an item takes one parked filter and
+// appends its items while fewer than `backlog` wait.  Urgent filters always
+// append, and so wait only behind a short ring.  No deadlock: a filter is
+// parked only while items wait, and the last of them to finish un-parks.
+// At most one interval of items per filter is outstanding, so at most
+// sum(groups of 64) <= capacity / 2 entries sit in a ring and a producer
+// never waits for a slot that no wavefront has claimed.  Hand-offs between wavefronts (item results before the
 // weighing, the weighing's state before the next items) are agent-scope
 // release/acquire pairs.
 #pragma once
@@ -40,42 +53,154 @@ __device__ __forceinline__ uint32_t ctl_load(const FlowArgs &fa, int w) {
     return __hip_atomic_load(&fa.ctl[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until ring slot `pos` holds sequence `want` (its entry in *entry).
-// False if the batch is done (when `until_done`) or the flow has given up:
-// a wavefront that sees no work item finish for stall_ticks sets the abort
-// word, which every waiting wavefront then sees.
-__device__ __forceinline__ bool ring_wait(const FlowArgs &fa, uint32_t pos, uint32_t want,
+// Gives up (sets the abort word, which every waiting wavefront then sees)
+// once no work item has finished for stall_ticks.  `seen` and `since` carry
+// the wait's last progress count and its time.
+__device__ __forceinline__ bool flow_stalled(const FlowArgs &fa, uint32_t &seen,
+                                             uint64_t &since) {
+    if (ctl_load(fa, kCtlAbort) != 0u) return true;
+    const uint32_t prog = ctl_load(fa, kCtlProgress);
+    const uint64_t now = wall_clock64();
+    if (prog != seen) {
+        seen = prog;
+        since = now;
+    } else if (now - since > fa.stall_ticks) {
+        __hip_atomic_store(&fa.ctl[kCtlAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ uint64_t *ring_slot(const FlowArgs &fa, int r, uint32_t pos) {
+    return fa.ring + (size_t)r * (fa.mask + 1) + (pos & fa.mask);
+}
+
+// Waits until slot `pos` of ring r holds sequence `want` (its entry in
+// *entry); false if the flow has given up, or (when `until_done`) once
+// every filter is done.
+__device__ __forceinline__ bool ring_wait(const FlowArgs &fa, int r, uint32_t pos, uint32_t want,
                                           uint64_t *entry, bool until_done) {
     uint64_t since = wall_clock64();
     uint32_t seen = ctl_load(fa, kCtlProgress);
     for (;;) {
         const uint64_t v =
-            __hip_atomic_load(&fa.ring[pos & fa.mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_load(ring_slot(fa, r, pos), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((uint32_t)(v >> 32) == want) {
             *entry = v;
             return true;
         }
         if (until_done && (int)ctl_load(fa, kCtlFinished) >= fa.n_slots) return false;
-        if (ctl_load(fa, kCtlAbort) != 0u) return false;
-        const uint32_t prog = ctl_load(fa, kCtlProgress);
-        const uint64_t now = wall_clock64();
-        if (prog != seen) {
-            seen = prog;
-            since = now;
-        } else if (now - since > fa.stall_ticks) {
-            __hip_atomic_store(&fa.ctl[kCtlAbort], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
+        if (flow_stalled(fa, seen, since)) return false;
         __builtin_amdgcn_s_sleep(8);
     }
 }
 
-// Weighing of filter f after its interval tcur[f] (one wavefront; the
-// arithmetic of k_weigh with its 256 threads emulated as 4 x 64 lanes: thread
-// v = 64 w + lane owns particles [v per, (v + 1) per), per = ceil(H / 256)).
-// The log-weights and then the integer prefix sums live in the slot's lw
-// array (8 bytes per particle).  Returns true when the filter goes on to
-// another interval; *cost receives its expected events.
+// Reserves n positions of ring r and writes one entry per lane below n (a
+// lane waits until its slot is free for the position).  The caller has
+// released what the entries' readers need.
+__device__ __forceinline__ void ring_put(const FlowArgs &fa, int r, int n, uint32_t entry_of_lane,
+                                         int lane) {
+    uint32_t base = 0;
+    if (lane == 0)
+        base = __hip_atomic_fetch_add(&fa.ctl[kCtlTail + 64 * r], (uint32_t)n, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    base = __builtin_amdgcn_readfirstlane(base);  // lane 0's: every lane is active
+    if (lane < n) {
+        const uint32_t pos = base + (uint32_t)lane;
+        uint64_t ent;
+        if (ring_wait(fa, r, pos, pos, &ent, false))
+            __hip_atomic_store(ring_slot(fa, r, pos), ((uint64_t)(pos + 1u) << 32) | entry_of_lane,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Takes the slot's entry of position pos and frees the slot for its next lap.
+__device__ __forceinline__ void ring_take(const FlowArgs &fa, int r, uint32_t pos) {
+    __hip_atomic_store(ring_slot(fa, r, pos), (uint64_t)(pos + fa.mask + 1u) << 32,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A filter is urgent (its items never wait in the parked ring) when its
+// intervals left times the expected events per lane of its items (events
+// per particle times the G particles a lane takes) reach urgent_events.
+__device__ __forceinline__ bool flow_urgent(const EngineArgs &e, const FlowArgs &fa, int f,
+                                            uint32_t cost, int G) {
+    if (fa.urgent_events == 0u) return true;  // no parking: first come, first served
+    const FilterDesc &d = e.desc[f];
+    const uint64_t per_lane = (uint64_t)(cost / (uint32_t)d.H) * (uint64_t)G;
+    const uint64_t left = (uint64_t)(d.T - e.tcur[f]);
+    return per_lane * left >= (uint64_t)fa.urgent_events;
+}
+
+// Items waiting in the item ring; negative when wavefronts wait for items
+// (they take positions ahead of the tail).
+__device__ __forceinline__ int32_t item_backlog(const FlowArgs &fa) {
+    return (int32_t)(ctl_load(fa, kCtlTail + 64 * kRingItems) -
+                     ctl_load(fa, kCtlHead + 64 * kRingItems));
+}
+
+// Writes the work items of filter f (pool size G, state already released)
+// to the item ring.
+__device__ __forceinline__ void emit_items(const EngineArgs &e, const FlowArgs &fa, int f, int G,
+                                           int lane) {
+    const int n_items = ((e.desc[f].Hp >> 6) + G - 1) / G;  // <= 64: one lane per item
+    ring_put(fa, kRingItems, n_items, ((uint32_t)f << 6) | (uint32_t)(lane * G), lane);
+}
+
+// While the item ring is short and filters are parked, takes one parked
+// filter and writes its items (called by every wavefront that finishes an
+// item, so that parked filters move as soon as there is room).
+__device__ __forceinline__ void flow_unpark(const EngineArgs &e, const FlowArgs &fa, int lane) {
+    int f = -1;
+    if (lane == 0 && item_backlog(fa) < (int32_t)fa.backlog) {
+        uint32_t h = ctl_load(fa, kCtlHead + 64 * kRingParked);
+        const uint32_t tl = ctl_load(fa, kCtlTail + 64 * kRingParked);
+        if ((int32_t)(tl - h) > 0 &&
+            __hip_atomic_compare_exchange_strong(&fa.ctl[kCtlHead + 64 * kRingParked], &h, h + 1u,
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+            uint64_t ent;
+            if (ring_wait(fa, kRingParked, h, h + 1u, &ent, false)) {
+                ring_take(fa, kRingParked, h);
+                f = (int)(uint32_t)ent;
+            }
+        }
+    }
+    f = __builtin_amdgcn_readfirstlane(f);
+    if (f < 0) return;
+    // acquire the parked filter's state; release it again to the items' takers
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int G = (int)e.pool[f] + 1;
+    __threadfence();
+    __syncthreads();
+    emit_items(e, fa, f, G, lane);
+}
+
+// Number of resampling points j*Q + rho (j = 0, 1, ...) below x:
+// ceil((x - rho) / Q) for x > rho.  The quotient (at most H) is estimated in
+// binary64 and then made exact with integer products (x < 2^57, Q < 2^45).
+__device__ __forceinline__ uint64_t points_below(uint64_t x, uint64_t rho, uint64_t Q) {
+    if (x <= rho) return 0;
+    const uint64_t y = x - rho - 1;  // n = floor(y / Q) + 1
+    uint64_t m = (uint64_t)((double)y / (double)Q);
+    while (m > 0 && m * Q > y) --m;
+    while ((m + 1) * Q <= y) ++m;
+    return m + 1;
+}
+
+// Weighing of filter f after its interval tcur[f], by one wavefront, with
+// k_weigh's results bit for bit.  Per-particle steps (log-weights, e_j, q_j)
+// run over particles lane-strided, so every lane's loads are independent.
+// The one order-dependent sum, S = sum e_j, follows k_weigh's order: its 256
+// threads are emulated as 4 x 64 lanes, thread v = 64 w + lane summing
+// particles [v per, (v + 1) per), per = ceil(H / 256), then each emulated
+// wavefront's butterfly, then the four in order.  The slot's lw array holds
+// l_j, then e_j.  Resampling is taken from the particles' side: with
+// J(x) = #{j >= 0 : j Q + rho < x}, particle i is the ancestor of exactly
+// the j in [J(H C_i), J(H C_{i+1})) -- the same a_j = min{i : H C_{i+1} >
+// j Q + rho} as the search over j, found without dependent loads.
+// Returns true when the filter goes on to another interval; *cost receives
+// its expected events.
 __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *logy,
                                            uint32_t *cost) {
     const FilterDesc &d = e.desc[f];
@@ -100,21 +225,37 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
     const double *yt = d.y + (size_t)t * d.P;
     if (lane < d.P) logy[lane] = d.obs_kind == LIK_OBS_LOGNORMAL ? dlog(yt[lane]) : 0.0;
     __syncthreads();
-    uint64_t *cw = reinterpret_cast<uint64_t *>(d.lw);
-    constexpr int kVirt = kWeighBlock / 64;  // emulated wavefronts
-    const int per = (H + kWeighBlock - 1) / kWeighBlock;
+    double *w = d.lw;
 
+    // Per-particle passes take kB particles per lane at a time, their loads
+    // issued together (a load cannot move above an earlier iteration's store
+    // to another array, so one particle at a time waits on each load).
+    constexpr int kB = 2;
+    // log-weights and their maximum
     double mx = -__builtin_inf();
-#pragma unroll 1
-    for (int w = 0; w < kVirt; ++w) {
-        const int j0 = (w * 64 + lane) * per;
-        const int j1 = min(j0 + per, H);
-#pragma unroll 1
-        for (int j = j0; j < j1; ++j) {
-            const double l = obs_logweight(d, xs, j, logy, yt);
-            cw[j] = (uint64_t)__double_as_longlong(l);
-            mx = fmax(mx, l);
+    for (int base = lane; base < H; base += 64 * kB) {
+        double l[kB];
+        bool on[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            l[k] = 0.0;
+            on[k] = base + 64 * k < H;
         }
+        for (int o = 0; o < d.P; ++o) {
+            const int32_t *xo = xs + (size_t)d.obs_species[o] * d.Hp;
+            int cnt[kB];
+#pragma unroll
+            for (int k = 0; k < kB; ++k) cnt[k] = on[k] ? xo[base + 64 * k] : 0;
+#pragma unroll
+            for (int k = 0; k < kB; ++k)
+                if (on[k]) on[k] = obs_term(d, o, cnt[k], logy, yt, l[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k)
+            if (base + 64 * k < H) {
+                w[base + 64 * k] = l[k];
+                mx = fmax(mx, l[k]);
+            }
     }
     mx = wave_max(mx, lane);
     if (mx == -__builtin_inf()) {
@@ -125,68 +266,71 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
         }
         return false;
     }
+    // e_j = exp(l_j - mx) in place
+    for (int base = lane; base < H; base += 64 * kB) {
+        double v[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) v[k] = base + 64 * k < H ? w[base + 64 * k] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kB; ++k)
+            if (base + 64 * k < H) w[base + 64 * k] = dexp_nonpos(v[k] - mx);
+    }
+    __syncthreads();  // every lane's e_j before the emulated threads read them
 
-    // per emulated wavefront w: e_j and its threads' sums s (S adds the
-    // wavefront sums in wavefront order), q_j = floor(e_j 2^32), then the
-    // inclusive prefix sums C_{j+1} in place (thread order = particle order)
+    // S in k_weigh's order
+    constexpr int kVirt = kWeighBlock / 64;
+    const int per = (H + kWeighBlock - 1) / kWeighBlock;
     double S = 0.0;
-    uint64_t before = 0;  // q of the emulated wavefronts before w
 #pragma unroll 1
-    for (int w = 0; w < kVirt; ++w) {
-        const int j0 = (w * 64 + lane) * per;
+    for (int v = 0; v < kVirt; ++v) {
+        const int j0 = (v * 64 + lane) * per;
         const int j1 = min(j0 + per, H);
         double s = 0.0;
-        uint64_t qsum = 0;
-#pragma unroll 1
-        for (int j = j0; j < j1; ++j) {
-            const double ej = dexp_nonpos(__longlong_as_double((long long)cw[j]) - mx);
-            s += ej;
-            const uint64_t q = (uint64_t)(ej * 4294967296.0);
-            cw[j] = q;
-            qsum += q;
-        }
+        for (int j = j0; j < j1; ++j) s += w[j];
         const double r = wave_sum(s, lane);
-        S = (w == 0) ? r : S + r;
-        const uint64_t incl = wave_incl_scan_u64(qsum, lane);
-        uint64_t run = before + incl - qsum;
-#pragma unroll 1
-        for (int j = j0; j < j1; ++j) {
-            run += cw[j];
-            cw[j] = run;
-        }
-        before += lane_read(incl, 63);
+        S = (v == 0) ? r : S + r;
     }
     if (lane == 0) {
         e.fll[f] = e.fll[f] + loglik_increment(d, mx, S, yt);
         e.tcur[f] = t + 1;
     }
     if (t + 1 >= d.T) return false;
-    __syncthreads();  // every lane's prefix sums before any lane searches them
 
-    // a_j = min{i : H C_{i+1} > j Q + rho}; nondecreasing in j, so each lane
-    // searches the first of its consecutive outputs and walks on from there
-    const uint64_t Q = cw[H - 1];
+    // q_j = floor(e_j 2^32) and their total Q
+    uint64_t Q = 0;
+    for (int j = lane; j < H; j += 64) Q += (uint64_t)(w[j] * 4294967296.0);
+    Q = wave_sum_u64(Q, lane);
     const uint64_t rho = __umul64hi(resample_word(d, t), Q);
     const uint64_t Hu = (uint64_t)H;
-    const int per64 = (H + 63) / 64;
-    const int a0 = lane * per64;
-    const int a1 = min(a0 + per64, H);
+    // each group of 64 particles: prefix sums C_i, C_{i+1} (carried over
+    // groups), then every particle writes the outputs it is the ancestor of
     float pred = 0.0f;  // sum of the ancestors' total propensities
-    if (a0 < a1) {
-        const uint64_t point0 = (uint64_t)a0 * Q + rho;
-        int lo = 0, hi = H - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (Hu * cw[mid] > point0) hi = mid;
-            else lo = mid + 1;
+    uint64_t carry = 0;    // C at the group's first particle
+    uint64_t carry_j = 0;  // J(H C) there
+    for (int b0 = 0; b0 < H; b0 += 64 * kB) {
+        double v[kB];
+        float a0[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int i = b0 + 64 * k + lane;
+            v[k] = i < H ? w[i] : 0.0;
+            a0[k] = i < H ? d.pa0[i] : 0.0f;
         }
-        int a = lo;
-#pragma unroll 1
-        for (int jj = a0; jj < a1; ++jj) {
-            const uint64_t point = (uint64_t)jj * Q + rho;
-            while (!(Hu * cw[a] > point)) ++a;
-            d.anc[jj] = a;
-            pred += d.pa0[a];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            const int i = b0 + 64 * k + lane;
+            const uint64_t q = i < H ? (uint64_t)(v[k] * 4294967296.0) : 0;
+            const uint64_t incl = carry + wave_incl_scan_u64(q, lane);  // C_{i+1}
+            // J(H C_{i+1}); J(H C_i) is the previous particle's
+            const uint64_t j_hi = i < H ? min(points_below(Hu * incl, rho, Q), Hu) : Hu;
+            const uint64_t prev = lane_read(j_hi, lane > 0 ? lane - 1 : 0);
+            const uint64_t j_lo = lane > 0 ? prev : carry_j;
+            if (i < H) {
+                for (uint64_t j = j_lo; j < j_hi; ++j) d.anc[j] = i;
+                pred += (float)(j_hi - j_lo) * a0[k];
+            }
+            carry = lane_read(incl, 63);
+            carry_j = lane_read(j_hi, 63);
         }
     }
     pred = wave_sum_f32(pred, lane);
@@ -194,36 +338,32 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
     return true;
 }
 
-// Writes the items of filter f's next interval to the ring.
+// Sets up filter f's next interval and writes its items to the item ring,
+// or parks the filter when the ring already holds `backlog` items and the
+// filter is not urgent.
 __device__ __forceinline__ void flow_push(const EngineArgs &e, const FlowArgs &fa, int f,
                                           uint32_t cost) {
     const int lane = lane_id();
     __syncthreads();  // the weighing's state (tcur, ancestors) from every lane
-    const int G = pool_size(e, f, cost, fa.g_par);
+    // lane 0 wrote tcur: its reading decides, for every lane
+    const int G = __builtin_amdgcn_readfirstlane(pool_size(e, f, cost, fa.g_par));
     const int nchunk = e.desc[f].Hp >> 6;
     const int n_items = (nchunk + G - 1) / G;
+    const int park = __builtin_amdgcn_readfirstlane(
+        (int)(!flow_urgent(e, fa, f, cost, G) && item_backlog(fa) >= (int32_t)fa.backlog));
     if (lane == 0) {
         e.cost[f] = cost;
         e.pool[f] = (uint8_t)(G - 1);
         __hip_atomic_store(&fa.remaining[f], (uint32_t)n_items, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    // release: everything above before the items become visible
+    // release: everything above before the items (or the parked entry) are visible
     __threadfence();
     __syncthreads();
-    uint32_t base = 0;
-    if (lane == 0)
-        base = __hip_atomic_fetch_add(&fa.ctl[kCtlTail], (uint32_t)n_items, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-    base = __builtin_amdgcn_readfirstlane(base);  // lane 0's: every lane is active
-    if (lane < n_items) {  // n_items <= 64: one lane per item
-        const uint32_t pos = base + (uint32_t)lane;
-        const uint32_t item = ((uint32_t)f << 6) | (uint32_t)(lane * G);
-        uint64_t ent;
-        if (ring_wait(fa, pos, pos, &ent, false))
-            __hip_atomic_store(&fa.ring[pos & fa.mask], ((uint64_t)(pos + 1u) << 32) | item,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (park)
+        ring_put(fa, kRingParked, 1, (uint32_t)f, lane);
+    else
+        emit_items(e, fa, f, G, lane);
 }
 
 // One work item per wavefront (a grid of at least as many wavefronts as the
@@ -239,16 +379,13 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     __shared__ double logy[LIK_MAX_OBSERVED];
     // the wavefronts beyond the batch's last item start after it is done
     if ((int)__builtin_amdgcn_readfirstlane(ctl_load(fa, kCtlFinished)) >= fa.n_slots) return;
-    uint32_t pos = 0;
     uint64_t ent = 0;
     int ok = 0;
     if (lane_id() == 0) {
-        pos = __hip_atomic_fetch_add(&fa.ctl[kCtlHead], 1u, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-        ok = ring_wait(fa, pos, pos + 1u, &ent, true) ? 1 : 0;
-        if (ok)  // the slot is free for its next lap
-            __hip_atomic_store(&fa.ring[pos & fa.mask], (uint64_t)(pos + fa.mask + 1u) << 32,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t pos = __hip_atomic_fetch_add(&fa.ctl[kCtlHead + 64 * kRingItems], 1u,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = ring_wait(fa, kRingItems, pos, pos + 1u, &ent, true) ? 1 : 0;
+        if (ok) ring_take(fa, kRingItems, pos);
     }
     ok = __builtin_amdgcn_readfirstlane(ok);  // lane 0's: every lane is active
     if (!ok) return;  // every filter is done (or the flow gave up)
@@ -269,18 +406,23 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
                                __HIP_MEMORY_SCOPE_AGENT);
     }
     left = __builtin_amdgcn_readfirstlane(left);
-    if (left != 1u) return;
+    if (left != 1u) {
+        flow_unpark(e, fa, lane_id());
+        return;
+    }
     // the last item of the interval: weigh the filter with every item's results
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     uint32_t cost = 0;
     if (flow_weigh(e, f, logy, &cost)) {
         flow_push(e, fa, f, cost);
+        flow_unpark(e, fa, lane_id());
     } else {
         __threadfence();
         __syncthreads();
         if (lane_id() == 0)
             __hip_atomic_fetch_add(&fa.ctl[kCtlFinished], 1u, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
+        flow_unpark(e, fa, lane_id());
     }
 }
 

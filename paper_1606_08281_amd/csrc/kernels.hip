@@ -211,29 +211,38 @@ __global__ __launch_bounds__(kPropBlock) void k_propagate_p(EngineArgs e, int gr
 // ---------------------------------------------------------------------------
 __global__ void k_flow_init(FlowArgs fa) {
     const size_t cap = (size_t)fa.mask + 1;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap * kFlowRings;
          i += (size_t)gridDim.x * blockDim.x)
-        fa.ring[i] = (uint64_t)i << 32;  // free for position i
+        fa.ring[i] = (uint64_t)(i & fa.mask) << 32;  // free for position i
     if (blockIdx.x == 0)
         for (int w = threadIdx.x; w < kCtlWords; w += blockDim.x) fa.ctl[w] = 0u;
 }
 
-__global__ void k_flow_seed(EngineArgs e, FlowArgs fa) {
+// The first interval's items: urgent filters first (pass 0), then the rest
+// (pass 1), appended while the item ring holds fewer than `backlog` items
+// and parked beyond.
+__global__ void k_flow_seed(EngineArgs e, FlowArgs fa, int pass) {
     const int f = e.f_lo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (f >= e.f_hi) return;
     if (!slot_active(e, f)) {
-        atomicAdd(&fa.ctl[kCtlFinished], 1u);
+        if (pass == 0) atomicAdd(&fa.ctl[kCtlFinished], 1u);
         return;
     }
     const int G = pool_size(e, f, e.cost[f], fa.g_par);
+    const bool urgent = flow_urgent(e, fa, f, e.cost[f], G);
+    if (urgent != (pass == 0)) return;
     const int n_items = ((e.desc[f].Hp >> 6) + G - 1) / G;
     e.pool[f] = (uint8_t)(G - 1);
     fa.remaining[f] = (uint32_t)n_items;
-    const uint32_t base = atomicAdd(&fa.ctl[kCtlTail], (uint32_t)n_items);
-    for (int k = 0; k < n_items; ++k) {
+    const bool park = !urgent && atomicAdd(&fa.ctl[kCtlSeedItems], (uint32_t)n_items) >= fa.backlog;
+    const int r = park ? kRingParked : kRingItems;
+    const int n = park ? 1 : n_items;
+    const uint32_t base = atomicAdd(&fa.ctl[kCtlTail + 64 * r], (uint32_t)n);
+    uint64_t *ring = fa.ring + (size_t)r * (fa.mask + 1);
+    for (int k = 0; k < n; ++k) {
         const uint32_t pos = base + (uint32_t)k;
-        fa.ring[pos & fa.mask] =
-            ((uint64_t)(pos + 1u) << 32) | (((uint32_t)f << 6) | (uint32_t)(k * G));
+        const uint32_t entry = park ? (uint32_t)f : (((uint32_t)f << 6) | (uint32_t)(k * G));
+        ring[pos & fa.mask] = ((uint64_t)(pos + 1u) << 32) | entry;
     }
 }
 
@@ -505,7 +514,8 @@ hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, co
 hipError_t launch_flow_setup(const EngineArgs &e, const FlowArgs &fa, hipStream_t s) {
     hipLaunchKernelGGL(k_flow_init, dim3(1024), dim3(256), 0, s, fa);
     const int F = e.f_hi - e.f_lo;
-    if (F > 0) hipLaunchKernelGGL(k_flow_seed, dim3((F + 255) / 256), dim3(256), 0, s, e, fa);
+    for (int pass = 0; pass < 2 && F > 0; ++pass)
+        hipLaunchKernelGGL(k_flow_seed, dim3((F + 255) / 256), dim3(256), 0, s, e, fa, pass);
     return hipGetLastError();
 }
 

@@ -99,19 +99,24 @@ struct EngineArgs {
     uint32_t group_off[kMaxGroups];  // first item of each group
 };
 
-// Flow engine (one launch runs every interval of a batch; flow.hpp).  Its
-// control words sit 128 bytes apart in ctl.
+// Flow engine (one launch runs every interval of a batch; flow.hpp).  Ring
+// kRingItems holds work items, ring kRingParked the ids of filters whose
+// items wait for room.  Control words sit 128 bytes apart in ctl.
+constexpr int kFlowRings = 2;
+enum : int { kRingItems = 0, kRingParked = 1 };
 enum : int {
-    kCtlHead = 0,        // next ring position a wavefront claims
-    kCtlTail = 32,       // next ring position a work item is written to
-    kCtlFinished = 64,   // slots that need no further interval
-    kCtlAbort = 96,      // nonzero: a wavefront saw no progress for stall_ticks
-    kCtlProgress = 128,  // work items finished
-    kCtlWords = 160
+    kCtlHead = 0,         // + 64 r: next position of ring r a wavefront claims
+    kCtlTail = 32,        // + 64 r: next position of ring r an entry is written to
+    kCtlFinished = 128,   // slots that need no further interval
+    kCtlAbort = 160,      // nonzero: a wavefront saw no progress for stall_ticks
+    kCtlProgress = 192,   // work items finished
+    kCtlSeedItems = 224,  // items of the first interval placed in the item ring
+    kCtlWords = 256
 };
 struct FlowArgs {
-    // ring[pos & mask] = (pos + 1) << 32 | item once the item of position pos
-    // is written, pos << 32 while the slot is free for position pos
+    // ring r at ring + r (mask + 1): slot pos & mask holds (pos + 1) << 32 |
+    // item once the item of position pos is written, pos << 32 while it is
+    // free for position pos
     uint64_t *ring;
     uint32_t *remaining;   // [slots] work items of the slot's interval not finished
     uint32_t *ctl;         // [kCtlWords]
@@ -119,7 +124,12 @@ struct FlowArgs {
                            // slots' groups of 64 (items outstanding at any time)
     int32_t n_slots;       // the batch is done when this many slots have finished
     int32_t g_par;         // largest pool (groups of 64) of a work item
-    int32_t pad;
+    uint32_t urgent_events;  // a filter whose intervals left times the expected events
+                             // per lane of its items reach this is never parked (0: no
+                             // parking at all)
+    uint32_t backlog;        // items waiting in the item ring above which a filter that
+                             // is not urgent is parked
+    uint32_t pad;
     uint64_t stall_ticks;  // wall-clock ticks without a finished item before a
                            // waiting wavefront gives up (a scheduler fault)
 };

@@ -78,23 +78,29 @@ __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c,
 // l_t^i" step): a sum over the observed components of -z^2/2, with z the
 // standardised residual of y (Gaussian) or of log y (log-normal, where a
 // count <= 0 has density zero).  logy[k] = log y_k for the log-normal model.
+// obs_term adds component k's term to l; false (l = -inf, later components
+// skipped) for a log-normal observation of a count <= 0.
+__device__ __forceinline__ bool obs_term(const FilterDesc &d, int k, int cnt, const double *logy,
+                                         const double *yt, double &l) {
+    if (d.obs_kind == LIK_OBS_LOGNORMAL) {
+        if (cnt <= 0) {
+            l = -__builtin_inf();
+            return false;
+        }
+        const double z = (logy[k] - dlog((double)cnt)) / d.sigma;
+        l = l - 0.5 * (z * z);
+    } else {
+        const double z = (yt[k] - (double)cnt) / d.sigma;
+        l = l - 0.5 * (z * z);
+    }
+    return true;
+}
+
 __device__ __forceinline__ double obs_logweight(const FilterDesc &d, const int32_t *xs, int j,
                                                 const double *logy, const double *yt) {
     double l = 0.0;
-    for (int k = 0; k < d.P; ++k) {
-        const int cnt = xs[(size_t)d.obs_species[k] * d.Hp + j];
-        if (d.obs_kind == LIK_OBS_LOGNORMAL) {
-            if (cnt <= 0) {
-                l = -__builtin_inf();
-                break;
-            }
-            const double z = (logy[k] - dlog((double)cnt)) / d.sigma;
-            l = l - 0.5 * (z * z);
-        } else {
-            const double z = (yt[k] - (double)cnt) / d.sigma;
-            l = l - 0.5 * (z * z);
-        }
-    }
+    for (int k = 0; k < d.P; ++k)
+        if (!obs_term(d, k, xs[(size_t)d.obs_species[k] * d.Hp + j], logy, yt, l)) break;
     return l;
 }
 

@@ -61,7 +61,7 @@ class Tuning(ctypes.Structure):
                 ("pool_events", ctypes.c_uint32), ("pool_first", ctypes.c_int32),
                 ("refill_min", ctypes.c_int32), ("priority", ctypes.c_int32),
                 ("items_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("urgent_events", ctypes.c_uint32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -191,7 +191,7 @@ class Network:
 
     def set_tuning(self, pool_min=None, pool_max=None, pool_events=None, pool_first=None,
                    refill_min=None, priority=None, items_per_cu=None, persistent=None,
-                   schedule=None,
+                   schedule=None, urgent_events=None,
                    default=False):
         """Work partitioning of the propagation kernels (never changes results)."""
         if default:
@@ -202,7 +202,7 @@ class Network:
                      ("pool_events", pool_events), ("pool_first", pool_first),
                      ("refill_min", refill_min), ("priority", priority),
                      ("items_per_cu", items_per_cu), ("persistent", persistent),
-                     ("schedule", schedule)):
+                     ("schedule", schedule), ("urgent_events", urgent_events)):
             if v is not None:
                 setattr(t, k, int(v))
         _check(lib().lik_network_set_tuning(self.handle, ctypes.byref(t)))
@@ -359,7 +359,8 @@ class Server:
         tp = None
         if tuning is not None:
             t = dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1,
-                     priority=0, items_per_cu=160, persistent=0, schedule=0)
+                     priority=0, items_per_cu=160, persistent=0, schedule=1,
+                     urgent_events=16000)
             t.update(tuning)
             self._tuning = Tuning(**{k: int(v) for k, v in t.items()})
             tp = ctypes.addressof(self._tuning)

@@ -32,6 +32,7 @@ KERNEL_SOURCES = ["paper_1606_08281_amd/csrc/propagate.hpp",
                   "paper_1606_08281_amd/csrc/kernels.hip",
                   "paper_1606_08281_amd/csrc/specialize.cpp",
                   "paper_1606_08281_amd/csrc/host.hpp",
+                  "paper_1606_08281_amd/csrc/api.cpp",
                   "include/lik.h"]
 
 
@@ -47,7 +48,10 @@ def source_sha256():
 def _kind(name):
     if "propagate" in name:
         return "lik_propagate_spec" if "spec" in name else "lik::k_propagate"
-    for k in ("k_order", "k_weigh", "k_admit", "k_finish", "k_aux_filters", "k_aux_state"):
+    if "lik_flow_spec" in name:
+        return "lik_flow_spec"
+    for k in ("k_flow_init", "k_flow_seed", "k_flow_check", "k_flow", "k_order", "k_weigh",
+              "k_admit", "k_finish", "k_aux_filters", "k_aux_state"):
         if k in name:
             return "lik::" + k
     if "copyBuffer" in name:
@@ -95,7 +99,7 @@ def counter_sum(pmc_dir, kind, counter):
                if _kind(r["Kernel_Name"]) == kind and r["Counter_Name"] == counter)
 
 
-def traffic(fetch_dir, write_dir, kernel="lik_propagate_spec"):
+def traffic(fetch_dir, write_dir, kernel="lik_flow_spec"):
     fetch_copy_kib = counter_sum(fetch_dir, "__amd_rocclr_copyBuffer", "FETCH_SIZE")
     write_copy_kib = counter_sum(write_dir, "__amd_rocclr_copyBuffer", "WRITE_SIZE")
     fs = COPY_BYTES / (fetch_copy_kib * 1024.0)
@@ -133,7 +137,8 @@ def main():
     ap.add_argument("--write", required=True)
     ap.add_argument("--util")
     ap.add_argument("--bench", required=True, help="bench.py JSON line of the same configuration")
-    ap.add_argument("--title", default="lik_propagate_spec — telegraph 1024 theta x 10 traj x "
+    ap.add_argument("--kernel", default="lik_flow_spec", help="kernel whose traffic is recorded")
+    ap.add_argument("--title", default="lik_flow_spec — telegraph 1024 theta x 10 traj x "
                                        "1000 particles x 50 obs (FP64)")
     ap.add_argument("--commands", required=True, help="text file with the commands that ran")
     ap.add_argument("--out", required=True)
@@ -141,13 +146,16 @@ def main():
     a = ap.parse_args()
 
     stats = kernel_stats(a.stats)
-    tr = traffic(a.fetch, a.write)
+    tr = traffic(a.fetch, a.write, a.kernel)
     bench = json.loads(open(a.bench).read().strip().splitlines()[-1])
     util = counter_means(a.util) if a.util else {}
     sha = source_sha256()
     lines = [f"# {a.title}", "",
-             "Engine iteration = k_order + lik_propagate_spec + k_weigh; 50 iterations per "
-             "bench step.", "", "Commands (repository root on one MI355X, `R` = its path):", "",
+             ("One bench step = k_admit, the flow set-up kernels, one lik_flow_spec launch (every "
+              "interval: SSA work items and each filter's weighing) and k_finish."
+              if a.kernel == "lik_flow_spec" else
+              "Engine iteration = k_order + lik_propagate_spec + k_weigh; 50 iterations per "
+              "bench step."), "", "Commands (repository root on one MI355X, `R` = its path):", "",
              "```"] + open(a.commands).read().strip().splitlines() + ["```", "",
              "Kernel statistics (rocprofv3 --kernel-trace --stats):", "",
              "| kernel | calls | total ms | average us | min us | max us | % |",
@@ -157,11 +165,11 @@ def main():
                      f"{s['min_us']:.1f} | {s['max_us']:.1f} | {s['pct']:.3f} |")
     rl = bench["roofline"]
     lines += ["", f"bench.py, same configuration: {bench['value']:.1f} evals/s, "
-                  f"{bench['ms_per_step']:.1f} ms per step; propagation average per launch "
+                  f"{bench['ms_per_step']:.1f} ms per step; {a.kernel} average per launch "
                   f"{rl['avg_launch_ms']:.3f} ms (HIP events on the launch stream); VALU "
                   f"fraction {rl['frac']:.3f} of {rl['peak']:.2f} T lane-op/s at "
                   f"{rl['ops_per_event']} lane-ops per event.", "",
-              "HBM traffic of lik_propagate_spec (rocprofv3 --pmc, one pass per counter):", "",
+              f"HBM traffic of {a.kernel} (rocprofv3 --pmc, one pass per counter):", "",
               f"- copy calibration (1 GiB device-to-device): FETCH_SIZE read "
               f"{tr['fetch_copy_kib']:.0f} KiB -> scale {tr['fetch_scale']:.4f}; WRITE_SIZE read "
               f"{tr['write_copy_kib']:.0f} KiB -> scale {tr['write_scale']:.4f}",
@@ -172,12 +180,12 @@ def main():
     if util:
         lines += ["", "Utilisation counters (mean per dispatch):", ""]
         for (k, c), (v, n) in sorted(util.items()):
-            if k in ("lik_propagate_spec", "lik::k_weigh", "lik::k_order"):
+            if k in ("lik_propagate_spec", "lik_flow_spec", "lik::k_weigh", "lik::k_order"):
                 lines.append(f"- {k} {c}: {v:.2f} ({n} dispatches)")
     lines += ["", f"Kernel sources fingerprint (sha256): {sha}", ""]
     open(a.out, "w").write("\n".join(lines))
     with open(a.traffic, "w") as f:
-        f.write("# HBM traffic of lik_propagate_spec per launch, telegraph 1024x10x1000x50 FP64,\n"
+        f.write(f"# HBM traffic of {a.kernel} per launch, telegraph 1024x10x1000x50 FP64,\n"
                 "# default work partitioning; read by bench.py while the kernel sources match.\n")
         f.write(f"source_sha256: {sha}\n")
         for k in ("fetch_scale", "write_scale", "fetch_bytes_per_launch",

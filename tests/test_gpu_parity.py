@@ -246,29 +246,32 @@ def test_telegraph_full_batch_sampled(orc, precision):
 
 
 TUNINGS = [dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=1, priority=0,
-                items_per_cu=0, persistent=0),
+                items_per_cu=0, persistent=0, schedule=0),
            dict(pool_min=2, pool_max=4, pool_events=1024, pool_first=2, refill_min=1, priority=1,
-                items_per_cu=0, persistent=0),
+                items_per_cu=0, persistent=0, schedule=0),
            dict(pool_min=2, pool_max=8, pool_events=8192, pool_first=2, refill_min=7, priority=1,
-                items_per_cu=1, persistent=0),
+                items_per_cu=1, persistent=0, schedule=0),
            dict(pool_min=3, pool_max=5, pool_events=1, pool_first=7, refill_min=64, priority=0,
-                items_per_cu=0, persistent=0),
+                items_per_cu=0, persistent=0, schedule=0),
            dict(pool_min=64, pool_max=64, pool_events=0, pool_first=64, refill_min=33,
-                priority=1, items_per_cu=0, persistent=0),
+                priority=1, items_per_cu=0, persistent=0, schedule=0),
            dict(pool_min=1, pool_max=4, pool_events=1024, pool_first=1, refill_min=1, priority=0,
-                items_per_cu=160, persistent=1),
+                items_per_cu=160, persistent=1, schedule=0),
            dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=9, priority=0,
-                items_per_cu=0, persistent=1),
+                items_per_cu=0, persistent=1, schedule=0),
            dict(pool_min=4, pool_max=4, pool_events=0, pool_first=4, refill_min=64, priority=0,
-                items_per_cu=0, persistent=1),
+                items_per_cu=0, persistent=1, schedule=0),
            dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1, priority=0,
                 items_per_cu=160, persistent=0, schedule=1),
            dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=1, priority=0,
-                items_per_cu=0, persistent=1, schedule=1),
+                items_per_cu=0, persistent=1, schedule=1, urgent_events=0),
            dict(pool_min=64, pool_max=64, pool_events=0, pool_first=64, refill_min=5,
-                priority=0, items_per_cu=0, persistent=0, schedule=1)]
+                priority=0, items_per_cu=0, persistent=0, schedule=1, urgent_events=1),
+           dict(pool_min=1, pool_max=4, pool_events=1024, pool_first=2, refill_min=1, priority=0,
+                items_per_cu=0, persistent=0, schedule=1, urgent_events=3000)]
 
 FLOW = dict(schedule=1)
+PER_INTERVAL = dict(schedule=0)
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -330,7 +333,7 @@ def test_flow_schedule_equals_per_interval_schedule(orc, kernel):
         cases.append((f"telegraph precision {prec}", dict(wl=sw, precision=prec), True))
     for name, kw, state in cases:
         _say("flow vs per-interval:", name, "kernel", kernel)
-        a = _gpu(kernel=kernel, **kw)
+        a = _gpu(kernel=kernel, tuning=PER_INTERVAL, **kw)
         b = _gpu(kernel=kernel, tuning=FLOW, **kw)
         for k in ("loglik", "status", "filter_events", "filter_loglik", "final_state"):
             assert np.array_equal(a[k], b[k], equal_nan=True), (name, k)
@@ -364,7 +367,7 @@ def test_flow_schedule_graph_replays_and_random_network(orc):
     idx = np.arange(0, 64, 8)
     for kernel in KERNELS:
         _say("flow random 20x40 kernel", kernel)
-        a = _gpu(rw, theta=rw.theta[idx], theta_ids=idx, kernel=kernel)
+        a = _gpu(rw, theta=rw.theta[idx], theta_ids=idx, kernel=kernel, tuning=PER_INTERVAL)
         b = _gpu(rw, theta=rw.theta[idx], theta_ids=idx, kernel=kernel, tuning=FLOW)
         for k in ("loglik", "status", "filter_events", "final_state"):
             assert np.array_equal(a[k], b[k], equal_nan=True), k
