@@ -233,23 +233,34 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
     constexpr int kB = 2;
     // log-weights and their maximum
     double mx = -__builtin_inf();
+    // counts of the first observed component: the next pair's are loaded
+    // before this pair's log-weights are stored
+    const int32_t *x0s = xs + (size_t)d.obs_species[0] * d.Hp;
+    int c0[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) c0[k] = lane + 64 * k < H ? x0s[lane + 64 * k] : 0;
     for (int base = lane; base < H; base += 64 * kB) {
         double l[kB];
         bool on[kB];
+        int n0[kB];
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
             l[k] = 0.0;
             on[k] = base + 64 * k < H;
+            const int jn = base + 64 * (kB + k);
+            n0[k] = jn < H ? x0s[jn] : 0;
         }
         for (int o = 0; o < d.P; ++o) {
             const int32_t *xo = xs + (size_t)d.obs_species[o] * d.Hp;
             int cnt[kB];
 #pragma unroll
-            for (int k = 0; k < kB; ++k) cnt[k] = on[k] ? xo[base + 64 * k] : 0;
+            for (int k = 0; k < kB; ++k) cnt[k] = o == 0 ? c0[k] : on[k] ? xo[base + 64 * k] : 0;
 #pragma unroll
             for (int k = 0; k < kB; ++k)
                 if (on[k]) on[k] = obs_term(d, o, cnt[k], logy, yt, l[k]);
         }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) c0[k] = n0[k];
 #pragma unroll
         for (int k = 0; k < kB; ++k)
             if (base + 64 * k < H) {
@@ -266,30 +277,33 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
         }
         return false;
     }
-    // e_j = exp(l_j - mx) in place
-    for (int base = lane; base < H; base += 64 * kB) {
+    // e_j = exp(l_j - mx) in place, and S = sum e_j in k_weigh's order: each
+    // lane's particles in increasing j, then one butterfly; the next pair's
+    // loads are issued before this pair's stores
+    double s = 0.0;
+    {
         double v[kB];
 #pragma unroll
-        for (int k = 0; k < kB; ++k) v[k] = base + 64 * k < H ? w[base + 64 * k] : 0.0;
+        for (int k = 0; k < kB; ++k) v[k] = lane + 64 * k < H ? w[lane + 64 * k] : 0.0;
+        for (int base = lane; base < H; base += 64 * kB) {
+            double nx[kB];
 #pragma unroll
-        for (int k = 0; k < kB; ++k)
-            if (base + 64 * k < H) w[base + 64 * k] = dexp_nonpos(v[k] - mx);
+            for (int k = 0; k < kB; ++k) {
+                const int jn = base + 64 * (kB + k);
+                nx[k] = jn < H ? w[jn] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kB; ++k)
+                if (base + 64 * k < H) {
+                    const double ej = dexp_nonpos(v[k] - mx);
+                    w[base + 64 * k] = ej;
+                    s += ej;
+                }
+#pragma unroll
+            for (int k = 0; k < kB; ++k) v[k] = nx[k];
+        }
     }
-    __syncthreads();  // every lane's e_j before the emulated threads read them
-
-    // S in k_weigh's order
-    constexpr int kVirt = kWeighBlock / 64;
-    const int per = (H + kWeighBlock - 1) / kWeighBlock;
-    double S = 0.0;
-#pragma unroll 1
-    for (int v = 0; v < kVirt; ++v) {
-        const int j0 = (v * 64 + lane) * per;
-        const int j1 = min(j0 + per, H);
-        double s = 0.0;
-        for (int j = j0; j < j1; ++j) s += w[j];
-        const double r = wave_sum(s, lane);
-        S = (v == 0) ? r : S + r;
-    }
+    const double S = wave_sum(s, lane);
     if (lane == 0) {
         e.fll[f] = e.fll[f] + loglik_increment(d, mx, S, yt);
         e.tcur[f] = t + 1;
@@ -307,14 +321,23 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
     float pred = 0.0f;  // sum of the ancestors' total propensities
     uint64_t carry = 0;    // C at the group's first particle
     uint64_t carry_j = 0;  // J(H C) there
+    double v[kB];
+    float a0[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+        const int i = 64 * k + lane;
+        v[k] = i < H ? w[i] : 0.0;
+        a0[k] = i < H ? d.pa0[i] : 0.0f;
+    }
     for (int b0 = 0; b0 < H; b0 += 64 * kB) {
-        double v[kB];
-        float a0[kB];
+        // the next groups' weights, loaded before this group's stores
+        double nv[kB];
+        float na[kB];
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
-            const int i = b0 + 64 * k + lane;
-            v[k] = i < H ? w[i] : 0.0;
-            a0[k] = i < H ? d.pa0[i] : 0.0f;
+            const int i = b0 + 64 * (kB + k) + lane;
+            nv[k] = i < H ? w[i] : 0.0;
+            na[k] = i < H ? d.pa0[i] : 0.0f;
         }
 #pragma unroll
         for (int k = 0; k < kB; ++k) {
@@ -331,6 +354,11 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
             }
             carry = lane_read(incl, 63);
             carry_j = lane_read(j_hi, 63);
+        }
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+            v[k] = nv[k];
+            a0[k] = na[k];
         }
     }
     pred = wave_sum_f32(pred, lane);

@@ -339,19 +339,25 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
         return;
     }
 
-    // e_j, their sum, integer weights q_j (kept in Cs until the scan)
-    double s = 0.0;
+    // e_j (kept in lw) and integer weights q_j (kept in Cs until the scan)
     uint64_t qsum = 0;
     for (int j = j0; j < j1; ++j) {
         const double ej = dexp_nonpos(lw[j] - mx);
-        s += ej;
+        lw[j] = ej;
         const uint64_t q = (uint64_t)(ej * 4294967296.0);
         Cs[j] = q;
         qsum += q;
     }
-    s = wave_sum(s, lane);
-    __syncthreads();  // red[] reuse
-    if (lane == 0) red[wave] = s;
+    __syncthreads();  // every e_j, and red[] reuse
+    // S = sum of e_j in a fixed order: lane-wise sums over j = lane + 64 k in
+    // increasing k, then one butterfly (the order the flow schedule's
+    // one-wavefront weighing takes as well)
+    if (wave == 0) {
+        double s = 0.0;
+        for (int j = lane; j < H; j += 64) s += lw[j];
+        s = wave_sum(s, lane);
+        if (lane == 0) red[0] = s;
+    }
 
     // exclusive scan of the per-thread sums (thread order = particle order)
     const uint64_t incl = wave_incl_scan_u64(qsum, lane);
@@ -365,8 +371,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
         Cs[j] = run;
     }
     if (tid == 0) {
-        double S = red[0];
-        for (int w = 1; w < kWeighBlock / 64; ++w) S += red[w];
+        const double S = red[0];
         // running log-likelihood
         e.fll[f] = e.fll[f] + loglik_increment(d, mx, S, yt);
         e.tcur[f] = t + 1;
