@@ -93,7 +93,7 @@ def main():
                          "the fastest (default: the library's default partitioning)")
     ap.add_argument("--tuning", default=None,
                     help="work partitioning pool_min,pool_max,pool_events,pool_first,refill_min,"
-                         "priority,items_per_cu,persistent,schedule,urgent_events "
+                         "priority,items_per_cu,persistent,schedule,urgent_events,backlog_per_cu "
                          "(default: the library's)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 generic, 2 network-specialised propagation kernel")
@@ -128,7 +128,7 @@ def main():
 
     if args.tuning:
         keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min", "priority",
-                "items_per_cu", "persistent", "schedule", "urgent_events")
+                "items_per_cu", "persistent", "schedule", "urgent_events", "backlog_per_cu")
         net.set_tuning(**dict(zip(keys, (int(v) for v in args.tuning.split(",")))))
     tuning = net.tuning()
     if args.autotune:

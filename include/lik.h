@@ -139,9 +139,12 @@ typedef struct lik_tuning {
                                path) queues its items at once; the others wait while the
                                queue is long, so urgent items are taken soon;
                                0: first come, first served */
+    uint32_t backlog_per_cu; /* schedule 1: the queue counts as long from this many waiting
+                                work items per compute unit (>= 1) */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000}) / reads a network's
+/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30}) / reads a
+ * network's
  * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
  * evaluation on this network is being enqueued on another thread.  The
  * server uses the defaults for every network. */

@@ -33,13 +33,14 @@ bool lik::tuning_valid(const lik_tuning &v) {
            v.pool_first >= 1 && v.pool_first <= 64 && v.refill_min >= 1 && v.refill_min <= 64 &&
            (v.priority == 0 || v.priority == 1) && v.items_per_cu >= 0 &&
            v.items_per_cu <= (1 << 20) && (v.persistent == 0 || v.persistent == 1) &&
-           (v.schedule == 0 || v.schedule == 1);
+           (v.schedule == 0 || v.schedule == 1) && v.backlog_per_cu >= 1 &&
+           v.backlog_per_cu <= (1u << 16);
 }
 
 const char *lik::tuning_rule() {
     return "tuning must satisfy 1 <= pool_min <= pool_max <= 64, 1 <= pool_first <= 64, "
            "1 <= refill_min <= 64, priority 0 or 1, 0 <= items_per_cu <= 2^20, "
-           "persistent 0 or 1, schedule 0 or 1";
+           "persistent 0 or 1, schedule 0 or 1, 1 <= backlog_per_cu <= 65536";
 }
 
 unsigned lik::persistent_waves() { return compute_units() * 32u; }
@@ -197,15 +198,15 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     static const lik_tuning cands[] = {
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000},  // default: flow schedule
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 32000},
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 0},      // flow, first come first served
-        {1, 4, 1024, 1, 1, 0, 160, 0, 1, 16000},
-        {1, 6, 1536, 1, 1, 0, 160, 0, 0, 16000},  // one launch sequence per interval
-        {1, 4, 1024, 1, 1, 0, 160, 0, 0, 16000},
-        {2, 6, 2048, 1, 1, 0, 160, 0, 0, 16000},
-        {1, 1, 0, 1, 1, 0, 0, 0, 0, 16000},       // one group of 64 particles per wavefront
-        {1, 1, 0, 1, 1, 0, 0, 1, 0, 16000},       // persistent wavefronts (R <= 16)
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30},  // default: flow schedule
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 32000, 30},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 0, 30},      // flow, first come first served
+        {1, 4, 1024, 1, 1, 0, 160, 0, 1, 16000, 30},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 0, 16000, 30},  // one launch sequence per interval
+        {1, 4, 1024, 1, 1, 0, 160, 0, 0, 16000, 30},
+        {2, 6, 2048, 1, 1, 0, 160, 0, 0, 16000, 30},
+        {1, 1, 0, 1, 1, 0, 0, 0, 0, 16000, 30},       // one group of 64 particles per wavefront
+        {1, 1, 0, 1, 1, 0, 0, 1, 0, 16000, 30},       // persistent wavefronts (R <= 16)
     };
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;
@@ -544,8 +545,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
             khz = 100000;
         L.fa.stall_ticks = (uint64_t)khz * 1000ull * 60ull;  // one minute
         L.fa.urgent_events = net->tuning.urgent_events;
-        // about five waiting items for every four wavefronts the device holds
-        L.fa.backlog = std::max(compute_units(), 1u) * 30u;
+        L.fa.backlog = std::max(compute_units(), 1u) * net->tuning.backlog_per_cu;
     }
 
     RequestArgs r;

@@ -148,9 +148,11 @@ __device__ __forceinline__ void emit_items(const EngineArgs &e, const FlowArgs &
 }
 
 // While the item ring is short and filters are parked, takes one parked
-// filter and writes its items (called by every wavefront that finishes an
-// item, so that parked filters move as soon as there is room).
-__device__ __forceinline__ void flow_unpark(const EngineArgs &e, const FlowArgs &fa, int lane) {
+// filter and writes its items; false if it took none.  Called by every
+// wavefront that finishes an item, and by the wavefront first in line for
+// the next item while it waits, so that parked filters move as soon as
+// there is room.
+__device__ __forceinline__ bool flow_unpark(const EngineArgs &e, const FlowArgs &fa, int lane) {
     int f = -1;
     if (lane == 0 && item_backlog(fa) < (int32_t)fa.backlog) {
         uint32_t h = ctl_load(fa, kCtlHead + 64 * kRingParked);
@@ -167,13 +169,47 @@ __device__ __forceinline__ void flow_unpark(const EngineArgs &e, const FlowArgs 
         }
     }
     f = __builtin_amdgcn_readfirstlane(f);
-    if (f < 0) return;
+    if (f < 0) return false;
     // acquire the parked filter's state; release it again to the items' takers
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int G = (int)e.pool[f] + 1;
     __threadfence();
     __syncthreads();
     emit_items(e, fa, f, G, lane);
+    return true;
+}
+
+// After an item: takes parked filters (at most kUnparkPerItem) while the
+// item ring is short.
+constexpr int kUnparkPerItem = 4;
+__device__ __forceinline__ void flow_unpark_some(const EngineArgs &e, const FlowArgs &fa,
+                                                 int lane) {
+    for (int k = 0; k < kUnparkPerItem; ++k)
+        if (!flow_unpark(e, fa, lane)) break;
+}
+
+// Waits (lane 0) for the item of position pos of the item ring: 1 with the
+// entry in *entry; 2 when this wavefront is first in line (no producer has
+// reserved pos yet) and filters are parked -- the caller un-parks one and
+// waits again; 0 once every filter is done or the flow has given up.
+__device__ __forceinline__ int item_wait(const FlowArgs &fa, uint32_t pos, uint64_t *entry) {
+    uint64_t since = wall_clock64();
+    uint32_t seen = ctl_load(fa, kCtlProgress);
+    for (;;) {
+        const uint64_t v = __hip_atomic_load(ring_slot(fa, kRingItems, pos), __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == pos + 1u) {
+            *entry = v;
+            return 1;
+        }
+        if (ctl_load(fa, kCtlTail + 64 * kRingItems) == pos &&
+            (int32_t)(ctl_load(fa, kCtlTail + 64 * kRingParked) -
+                      ctl_load(fa, kCtlHead + 64 * kRingParked)) > 0)
+            return 2;
+        if ((int)ctl_load(fa, kCtlFinished) >= fa.n_slots) return 0;
+        if (flow_stalled(fa, seen, since)) return 0;
+        __builtin_amdgcn_s_sleep(8);
+    }
 }
 
 // Number of resampling points j*Q + rho (j = 0, 1, ...) below x:
@@ -408,14 +444,22 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     // the wavefronts beyond the batch's last item start after it is done
     if ((int)__builtin_amdgcn_readfirstlane(ctl_load(fa, kCtlFinished)) >= fa.n_slots) return;
     uint64_t ent = 0;
+    uint32_t pos = 0;
+    if (lane_id() == 0)
+        pos = __hip_atomic_fetch_add(&fa.ctl[kCtlHead + 64 * kRingItems], 1u, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
     int ok = 0;
-    if (lane_id() == 0) {
-        const uint32_t pos = __hip_atomic_fetch_add(&fa.ctl[kCtlHead + 64 * kRingItems], 1u,
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = ring_wait(fa, kRingItems, pos, pos + 1u, &ent, true) ? 1 : 0;
-        if (ok) ring_take(fa, kRingItems, pos);
+    for (;;) {
+        int st = 0;
+        if (lane_id() == 0) st = item_wait(fa, pos, &ent);
+        st = __builtin_amdgcn_readfirstlane(st);  // lane 0's: every lane is active
+        if (st != 2) {
+            ok = st;
+            break;
+        }
+        flow_unpark(e, fa, lane_id());
     }
-    ok = __builtin_amdgcn_readfirstlane(ok);  // lane 0's: every lane is active
+    if (ok && lane_id() == 0) ring_take(fa, kRingItems, pos);
     if (!ok) return;  // every filter is done (or the flow gave up)
     // acquire: the filter's state written before the item was published
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -435,7 +479,7 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     }
     left = __builtin_amdgcn_readfirstlane(left);
     if (left != 1u) {
-        flow_unpark(e, fa, lane_id());
+        flow_unpark_some(e, fa, lane_id());
         return;
     }
     // the last item of the interval: weigh the filter with every item's results
@@ -443,14 +487,14 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     uint32_t cost = 0;
     if (flow_weigh(e, f, logy, &cost)) {
         flow_push(e, fa, f, cost);
-        flow_unpark(e, fa, lane_id());
+        flow_unpark_some(e, fa, lane_id());
     } else {
         __threadfence();
         __syncthreads();
         if (lane_id() == 0)
             __hip_atomic_fetch_add(&fa.ctl[kCtlFinished], 1u, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
-        flow_unpark(e, fa, lane_id());
+        flow_unpark_some(e, fa, lane_id());
     }
 }
 

@@ -61,7 +61,8 @@ class Tuning(ctypes.Structure):
                 ("pool_events", ctypes.c_uint32), ("pool_first", ctypes.c_int32),
                 ("refill_min", ctypes.c_int32), ("priority", ctypes.c_int32),
                 ("items_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("urgent_events", ctypes.c_uint32)]
+                ("schedule", ctypes.c_int32), ("urgent_events", ctypes.c_uint32),
+                ("backlog_per_cu", ctypes.c_uint32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -191,7 +192,7 @@ class Network:
 
     def set_tuning(self, pool_min=None, pool_max=None, pool_events=None, pool_first=None,
                    refill_min=None, priority=None, items_per_cu=None, persistent=None,
-                   schedule=None, urgent_events=None,
+                   schedule=None, urgent_events=None, backlog_per_cu=None,
                    default=False):
         """Work partitioning of the propagation kernels (never changes results)."""
         if default:
@@ -202,7 +203,8 @@ class Network:
                      ("pool_events", pool_events), ("pool_first", pool_first),
                      ("refill_min", refill_min), ("priority", priority),
                      ("items_per_cu", items_per_cu), ("persistent", persistent),
-                     ("schedule", schedule), ("urgent_events", urgent_events)):
+                     ("schedule", schedule), ("urgent_events", urgent_events),
+                     ("backlog_per_cu", backlog_per_cu)):
             if v is not None:
                 setattr(t, k, int(v))
         _check(lib().lik_network_set_tuning(self.handle, ctypes.byref(t)))
@@ -360,7 +362,7 @@ class Server:
         if tuning is not None:
             t = dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1,
                      priority=0, items_per_cu=160, persistent=0, schedule=1,
-                     urgent_events=16000)
+                     urgent_events=16000, backlog_per_cu=30)
             t.update(tuning)
             self._tuning = Tuning(**{k: int(v) for k, v in t.items()})
             tp = ctypes.addressof(self._tuning)

@@ -150,12 +150,13 @@ def main():
                     help="arrival rate as a fraction of the plain path's saturated rate")
     ap.add_argument("--tuning", default=None,
                     help="server work partitioning pool_min,pool_max,pool_events,pool_first,"
-                         "refill_min,priority,items_per_cu,persistent,schedule,urgent_events (default: the library's)")
+                         "refill_min,priority,items_per_cu,persistent,schedule,urgent_events,backlog_per_cu "
+                         "(default: the library's)")
     args = ap.parse_args()
     tuning = None
     if args.tuning:
         keys = ("pool_min", "pool_max", "pool_events", "pool_first", "refill_min", "priority",
-                "items_per_cu", "persistent", "schedule", "urgent_events")
+                "items_per_cu", "persistent", "schedule", "urgent_events", "backlog_per_cu")
         tuning = dict(zip(keys, (int(v) for v in args.tuning.split(","))))
     import torch
     torch.cuda.set_device(0)

@@ -268,7 +268,7 @@ TUNINGS = [dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=
            dict(pool_min=64, pool_max=64, pool_events=0, pool_first=64, refill_min=5,
                 priority=0, items_per_cu=0, persistent=0, schedule=1, urgent_events=1),
            dict(pool_min=1, pool_max=4, pool_events=1024, pool_first=2, refill_min=1, priority=0,
-                items_per_cu=0, persistent=0, schedule=1, urgent_events=3000)]
+                items_per_cu=0, persistent=0, schedule=1, urgent_events=3000, backlog_per_cu=1)]
 
 FLOW = dict(schedule=1)
 PER_INTERVAL = dict(schedule=0)
