@@ -133,7 +133,10 @@ typedef struct lik_tuning {
                               persistent launch for all intervals, each filter going on
                               to its next interval as soon as its own particles are
                               weighed (the server always advances its slots together;
-                              persistent is ignored under 1) */
+                              persistent is ignored under 1; takes 0 where its kernel
+                              keeps fewer than 4 wavefronts per SIMD resident (large
+                              networks) and for batches of 2^26 or more filter-intervals
+                              x groups of 64 particles) */
     uint32_t urgent_events; /* schedule 1: a filter whose intervals left times the expected
                                events per lane of its items reach this (one on the critical
                                path) queues its items at once; the others wait while the

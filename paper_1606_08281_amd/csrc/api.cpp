@@ -494,7 +494,11 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     const int Hp = (H + 63) / 64 * 64;
     const int nchunk = Hp / 64;
     char *p = (char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
-    const bool flow = net->tuning.schedule == 1;
+    // the flow schedule launches one wavefront per possible work item (every
+    // interval of every filter in groups of 64); beyond 2^26 of them the batch
+    // takes the per-interval schedule, with the same results
+    const size_t items_max = (size_t)n_theta * (size_t)total * (size_t)nchunk;
+    bool flow = net->tuning.schedule == 1 && items_max < ((size_t)1 << 26);
     EngineLayout L = carve_engine(p, F, F * nchunk, request_state_bytes((int64_t)F, net->U, Hp),
                                   flow_ring_capacity(F, nchunk));
     L.e.f_lo = 0;
@@ -528,14 +532,21 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     hipFunction_t flow_spec = nullptr;
     unsigned flow_waves = 0;
     if (flow) {
-        const size_t items_max = (size_t)n_theta * (size_t)total * (size_t)nchunk;
-        if (items_max >= ((size_t)1 << 26))
-            return fail(LIK_EINVAL, "batch too large for the flow schedule (2^26 work items)");
-        flow_waves = (unsigned)std::max<size_t>(items_max, 1);
+        // ... and only where its kernel keeps enough wavefronts resident
+        int per_cu = 0;
         if (G.spec) {
             flow_spec = specialized_kernel(*net, precision, &err, kSpecFlow);
             if (!flow_spec) return fail(LIK_EDEVICE, "specialised flow kernel unavailable: " + err);
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, flow_spec, kPropBlock,
+                                                                    0) != hipSuccess)
+                per_cu = 0;
+        } else {
+            per_cu = flow_blocks_per_cu(net->umax, net->rmax, precision);
         }
+        flow = per_cu >= kFlowMinWavesPerCu;
+    }
+    if (flow) {
+        flow_waves = (unsigned)std::max<size_t>(items_max, 1);
         L.fa.g_par = (int32_t)std::max<size_t>(
             1, F * nchunk / std::max<uint32_t>(L.e.pool_min_items, 1u));
         int dev = 0, khz = 0;

@@ -543,6 +543,14 @@ static const void *flow_kernel(int umax, int rmax, int precision) {
     return nullptr;
 }
 
+int flow_blocks_per_cu(int umax, int rmax, int precision) {
+    const void *fn = flow_kernel(umax, rmax, precision);
+    int n = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kPropBlock, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
 hipError_t launch_flow(const EngineArgs &e, const FlowArgs &fa, unsigned n_waves, const void *net,
                        int umax, int rmax, int precision, hipStream_t s) {
     const void *fn = flow_kernel(umax, rmax, precision);

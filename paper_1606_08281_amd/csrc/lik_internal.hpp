@@ -147,6 +147,10 @@ hipError_t launch_flow_setup(const EngineArgs &e, const FlowArgs &fa, hipStream_
 hipError_t launch_flow(const EngineArgs &e, const FlowArgs &fa, unsigned n_waves, const void *net,
                        int umax, int rmax, int precision, hipStream_t s);
 hipError_t launch_flow_check(const EngineArgs &e, const FlowArgs &fa, hipStream_t s);
+int flow_blocks_per_cu(int umax, int rmax, int precision);  // resident flow wavefronts per CU
+// The flow schedule hides each hand-off's latency behind other resident
+// wavefronts: below this many per CU it is slower than the per-interval one.
+constexpr int kFlowMinWavesPerCu = 16;
 // Ring capacity for F slots of nchunk groups of 64 particles.
 inline uint32_t flow_ring_capacity(size_t F, int nchunk) {
     const size_t need = 2 * F * (size_t)nchunk;
