@@ -227,11 +227,9 @@ __device__ __forceinline__ uint64_t points_below(uint64_t x, uint64_t rho, uint6
 // Weighing of filter f after its interval tcur[f], by one wavefront, with
 // k_weigh's results bit for bit.  Per-particle steps (log-weights, e_j, q_j)
 // run over particles lane-strided, so every lane's loads are independent.
-// The one order-dependent sum, S = sum e_j, follows k_weigh's order: its 256
-// threads are emulated as 4 x 64 lanes, thread v = 64 w + lane summing
-// particles [v per, (v + 1) per), per = ceil(H / 256), then each emulated
-// wavefront's butterfly, then the four in order.  The slot's lw array holds
-// l_j, then e_j.  Resampling is taken from the particles' side: with
+// The one order-dependent sum, S = sum e_j, follows k_weigh's order: each
+// lane adds its particles j = lane + 64 k in increasing k, then one
+// butterfly over the lanes.  The slot's lw array holds l_j, then e_j.  Resampling is taken from the particles' side: with
 // J(x) = #{j >= 0 : j Q + rho < x}, particle i is the ancestor of exactly
 // the j in [J(H C_i), J(H C_{i+1})) -- the same a_j = min{i : H C_{i+1} >
 // j Q + rho} as the search over j, found without dependent loads.
