@@ -36,12 +36,36 @@ KERNEL_SOURCES = ["paper_1606_08281_amd/csrc/propagate.hpp",
                   "include/lik.h"]
 
 
+def _code_only(text):
+    """C/C++ source without comments and blank space runs: the fingerprint
+    follows the code the counters were taken on, not edits to its comments."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"' or c == "'":  # string or character literal, copied whole
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_sha256():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         h.update(rel.encode())
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
