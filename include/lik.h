@@ -59,7 +59,9 @@ extern "C" {
 #define LIK_STATUS_COUNT_OVERFLOW 2 /* a count exceeded 2^30 at the end of an interval */
 #define LIK_STATUS_BAD_THETA 3      /* a rate was negative, infinite or NaN */
 #define LIK_STATUS_SCHEDULER 4      /* the flow schedule saw no work item finish for a
-                                       minute and gave up (an internal fault) */
+                                       minute and gave up (an internal fault; the limit,
+                                       in microseconds, can be lowered through the
+                                       environment variable LIK_FLOW_STALL_US for tests) */
 
 /* observation noise models (Sec. "General Task": Y ~ p(. | X, theta)) */
 #define LIK_OBS_GAUSSIAN 0  /* y = x_s + N(0, sigma^2) per observed species s */

@@ -554,7 +554,10 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
             khz <= 0)
             khz = 100000;
-        L.fa.stall_ticks = (uint64_t)khz * 1000ull * 60ull;  // one minute
+        // one minute; LIK_FLOW_STALL_US overrides it (tests of the give-up path)
+        const char *stall_us = getenv("LIK_FLOW_STALL_US");
+        const uint64_t us = (stall_us && *stall_us) ? strtoull(stall_us, nullptr, 10) : 60000000ull;
+        L.fa.stall_ticks = (uint64_t)khz * us / 1000ull;
         L.fa.urgent_events = net->tuning.urgent_events;
         L.fa.backlog = std::max(compute_units(), 1u) * net->tuning.backlog_per_cu;
     }

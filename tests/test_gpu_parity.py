@@ -373,6 +373,25 @@ def test_flow_schedule_graph_replays_and_random_network(orc):
             assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
+def test_flow_scheduler_gives_up_cleanly(monkeypatch):
+    # the flow schedule's bounded waits, forced to their limit from the host
+    # (1 us without a finished work item): the launch ends, unfinished
+    # filters report LIK_STATUS_SCHEDULER with NaN, finished ones are exact
+    wl = W.telegraph_workload(n_theta=8, n_traj=2, n_obs=20, n_particles=256)
+    ref = _gpu(wl, tuning=PER_INTERVAL)
+    monkeypatch.setenv("LIK_FLOW_STALL_US", "1")
+    _say("flow give-up path, stall limit 1 us")
+    got = _gpu(wl, tuning=FLOW)
+    st = got["status"]
+    assert set(np.unique(st).tolist()) <= {0, 4}, st
+    assert (st == 4).any()
+    assert np.all(np.isnan(got["loglik"][st == 4]))
+    assert np.array_equal(got["loglik"][st == 0], ref["loglik"][st == 0])
+    monkeypatch.delenv("LIK_FLOW_STALL_US")
+    again = _gpu(wl, tuning=FLOW)
+    assert np.array_equal(again["loglik"], ref["loglik"])
+
+
 def test_autotune_picks_a_candidate_and_keeps_results():
     import torch
     from paper_1606_08281_amd import lik
