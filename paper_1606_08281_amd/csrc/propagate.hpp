@@ -100,16 +100,49 @@ struct pick_type<false, T, F> {
     using type = F;
 };
 
+// What an event takes from its random numbers (Supplementary I, the
+// "Simulate" step): nl = -log u1 (the waiting time times the total
+// propensity) and u2 (the reaction's share of the total), in the precision of
+// the event arithmetic.  A function of the event's stream counter (n, j)
+// alone, so any lane may compute it for any particle.
+template <int PREC>
+struct EventDraw {
+    using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
+    Real nl, u2;
+};
+
+template <int PREC>
+__device__ __forceinline__ EventDraw<PREC> event_draw(uint32_t n, uint32_t j, uint32_t c2,
+                                                      uint32_t c3, uint32_t k0, uint32_t k1) {
+    using Real = typename EventDraw<PREC>::Real;
+    const Block4 b = philox4x32_10(n, j, c2, c3, k0, k1);
+    EventDraw<PREC> r;
+    if (PREC == LIK_FP32_MIXED) {
+        // the leading 24 bits of the binary64 uniforms' words
+        const float u1 = (float)((b.w1 >> 8) + 1u) * 0x1p-24f;  // (0, 1]
+        r.nl = (Real)(-flog_pos(u1));
+        r.u2 = (Real)((float)(b.w3 >> 8) * 0x1p-24f);  // [0, 1)
+    } else {
+        const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
+        const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
+        const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
+        r.nl = (Real)(-dlog_pos(u1));
+        r.u2 = (Real)((double)z2 * 0x1p-53);  // [0, 1)
+    }
+    return r;
+}
+
 // One direct-method event of one particle (Supplementary I, the "Simulate"
 // step; the SSA of Gillespie 1977): total propensity, then either the end of
 // the particle's interval (no reaction possible, the event cap, or the next
 // event beyond the observation time -- it is discarded) or one event.
+// draw() gives the event's EventDraw (for the particle's current n).
 // a0_end keeps the last total propensity (a scheduling estimate).
-template <class NetT, int UMAX, int RMAX, int W, int PREC, class Real>
-__device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x, Real *S, int j,
-                                          uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+template <class NetT, int UMAX, int RMAX, int W, int PREC, class Real, class DrawFn>
+__device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x, Real *S,
                                           double t_end, uint32_t event_cap, double &clock,
-                                          uint32_t &n, int &st, float &a0_end, bool &have) {
+                                          uint32_t &n, int &st, float &a0_end, bool &have,
+                                          DrawFn &&draw) {
     const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
     a0_end = (float)s;
     if (!(s > (Real)0)) {
@@ -118,22 +151,15 @@ __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x
         st = st > LIK_STATUS_EVENT_CAP ? st : LIK_STATUS_EVENT_CAP;
         have = false;
     } else {
-        const Block4 b = philox4x32_10(n, (uint32_t)j, c2, c3, k0, k1);
+        const EventDraw<PREC> dr = draw();
         double tau;
         Real target;
         if (PREC == LIK_FP32_MIXED) {
-            // the leading 24 bits of the binary64 uniforms' words
-            const float u1 = (float)((b.w1 >> 8) + 1u) * 0x1p-24f;  // (0, 1]
-            const float u2 = (float)(b.w3 >> 8) * 0x1p-24f;         // [0, 1)
-            tau = (double)(-flog_pos(u1) / (float)s);
-            target = (Real)(u2 * (float)s);
+            tau = (double)((float)dr.nl / (float)s);
+            target = (Real)((float)dr.u2 * (float)s);
         } else {
-            const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
-            const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
-            const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
-            const double u2 = (double)z2 * 0x1p-53;        // [0, 1)
-            tau = -dlog_pos(u1) / (double)s;
-            target = (Real)(u2 * (double)s);
+            tau = (double)dr.nl / (double)s;
+            target = (Real)((double)dr.u2 * (double)s);
         }
         if (clock + tau > t_end) {
             have = false;  // the pending event is discarded
@@ -222,7 +248,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     // interval length), bucketed by half octave below the pool's heaviest;
     // order[s] is the pool offset of the s-th particle taken.
     // Which lane runs a particle, and when, never changes its result.
-    __shared__ int32_t pool_x[kPoolLdsWords];  // [U][npool], then order[npool] (uint16)
+    __shared__ __attribute__((aligned(16))) int32_t pool_x[kPoolLdsWords];  // [U][npool], then order[npool] (uint16)
     __shared__ uint32_t bucket[kSortBuckets];
     const int npool = p1 - p0;
     const bool staged = npool > kPropBlock;
@@ -353,8 +379,9 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     }
     for (;;) {
         if (have)
-            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, j, c2, c3, k0, k1, t_end,
-                                                       event_cap, clock, n, st, a0_end, have);
+            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
+                net, c, x, S, t_end, event_cap, clock, n, st, a0_end, have,
+                [&] { return event_draw<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
         // Once at least refill_min lanes are idle (or all are), the idle
         // lanes store what they hold and take the next particles of the
         // pool, in lane order.
@@ -375,7 +402,54 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
                 next += n_idle;
             }
         }
-        if (__ballot(have) == 0ull) break;
+        const uint64_t busy = __ballot(have);
+        if (busy == 0ull) break;
+        if (!(staged && next < p1) && __popcll(busy) <= kPropBlock / 2) break;
+    }
+
+    // The pool's last particles.  Once every particle of the pool has been
+    // taken and at most half of the lanes still run one, the idle lanes draw
+    // the running lanes' coming events ahead of time: with k running lanes
+    // and D = 64 / 2^ceil(log2 k), lane l computes the draw of event
+    // n + (l mod D) of the running lane of rank l / D, into LDS (the pool's
+    // staging area, no longer read); each running lane then takes its next
+    // D draws from there.  A draw depends on (n, j) only, so every event
+    // uses the numbers it would have drawn itself; draws beyond a particle's
+    // end are left unused.
+    using Draw = EventDraw<PREC>;
+    Draw *dbuf = reinterpret_cast<Draw *>(pool_x);                    // [64]
+    uint32_t *xn = reinterpret_cast<uint32_t *>(dbuf + kPropBlock);  // [32]: running lanes' n
+    int32_t *xj = reinterpret_cast<int32_t *>(xn + kPropBlock / 2);  // [32]: and particles
+    static_assert(sizeof(Draw) * kPropBlock + 4 * kPropBlock <= 4 * kPoolLdsWords,
+                  "drain buffers fit the pool's LDS");
+    __syncthreads();  // every read of the staged counts is done
+    for (;;) {
+        const uint64_t busy = __ballot(have);
+        if (busy == 0ull) break;
+        const int k = (int)__popcll(busy);  // <= 32
+        const int lgD = 6 - (k <= 1 ? 0 : 32 - __builtin_clz((uint32_t)(k - 1)));
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(busy >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)busy, 0u));
+        if (have) {
+            xn[rank] = n;
+            xj[rank] = j;
+        }
+        __syncthreads();
+        const int r = lane >> lgD;
+        if (r < k)
+            dbuf[lane] = event_draw<PREC>(xn[r] + (uint32_t)(lane & ((1 << lgD) - 1)),
+                                          (uint32_t)xj[r], c2, c3, k0, k1);
+        __syncthreads();
+        const int slot = rank << lgD;
+#pragma unroll 1
+        for (int i = 0; i < (1 << lgD); ++i) {
+            if (have)
+                ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, t_end, event_cap, clock,
+                                                           n, st, a0_end, have,
+                                                           [&] { return dbuf[slot + i]; });
+            if (__ballot(have) == 0ull) break;
+        }
+        __syncthreads();  // the draws are read before the next round writes
     }
     if (pend) retire();
     if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[f], st);
@@ -465,8 +539,9 @@ __device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const 
 
     for (;;) {
         if (have)
-            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, j, c2, c3, k0, k1, t_end, cap,
-                                                       clock, n, st, a0_end, have);
+            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
+                net, c, x, S, t_end, cap, clock, n, st, a0_end, have,
+                [&] { return event_draw<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
         uint64_t idle = __ballot(!have);
         const int n_idle = (int)__popcll(idle);
         if (n_idle > 0 && (next < p1 || more) && (n_idle >= refill_min || idle == ~0ull)) {
