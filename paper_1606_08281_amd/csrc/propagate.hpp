@@ -410,10 +410,10 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     // The pool's last particles.  Once every particle of the pool has been
     // taken and at most half of the lanes still run one, the idle lanes draw
     // the running lanes' coming events ahead of time: with k running lanes
-    // and D = 64 / 2^ceil(log2 k), lane l computes the draw of event
-    // n + (l mod D) of the running lane of rank l / D, into LDS (the pool's
-    // staging area, no longer read); each running lane then takes its next
-    // D draws from there.  A draw depends on (n, j) only, so every event
+    // and D = floor(64 / k), lane l computes the draw of event n + (l mod D)
+    // of the running lane of rank floor(l / D), into LDS (the pool's staging
+    // area, no longer read); each running lane then takes its next D draws
+    // from there.  A draw depends on (n, j) only, so every event
     // uses the numbers it would have drawn itself; draws beyond a particle's
     // end are left unused.
     using Draw = EventDraw<PREC>;
@@ -427,7 +427,11 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
         const uint64_t busy = __ballot(have);
         if (busy == 0ull) break;
         const int k = (int)__popcll(busy);  // <= 32
-        const int lgD = 6 - (k <= 1 ? 0 : 32 - __builtin_clz((uint32_t)(k - 1)));
+        const int D = kPropBlock / k;       // >= 2
+        // floor(l / D) as (l * ceil(2^16 / D)) >> 16: the product exceeds
+        // l * 2^16 / D by less than l <= 63 < 2^16 / D, too little to reach
+        // the next multiple of 2^16 / D
+        const int m = (0x10000 + D - 1) / D;
         const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(busy >> 32),
                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)busy, 0u));
         if (have) {
@@ -435,14 +439,14 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
             xj[rank] = j;
         }
         __syncthreads();
-        const int r = lane >> lgD;
+        const int r = (lane * m) >> 16;
         if (r < k)
-            dbuf[lane] = event_draw<PREC>(xn[r] + (uint32_t)(lane & ((1 << lgD) - 1)),
-                                          (uint32_t)xj[r], c2, c3, k0, k1);
+            dbuf[lane] = event_draw<PREC>(xn[r] + (uint32_t)(lane - r * D), (uint32_t)xj[r], c2,
+                                          c3, k0, k1);
         __syncthreads();
-        const int slot = rank << lgD;
+        const int slot = rank * D;
 #pragma unroll 1
-        for (int i = 0; i < (1 << lgD); ++i) {
+        for (int i = 0; i < D; ++i) {
             if (have)
                 ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, t_end, event_cap, clock,
                                                            n, st, a0_end, have,
