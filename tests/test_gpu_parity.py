@@ -344,6 +344,34 @@ def test_flow_schedule_equals_per_interval_schedule(orc, kernel):
                       abs_tol=FP32_ABS if kw.get("precision") else None)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pool_drain_draws(orc, precision, kernel):
+    # Once a pool's particles are all taken and at most 32 lanes still run,
+    # the idle lanes compute the running lanes' coming draws.  Particle
+    # counts around 32 and 64 start an item at or just above that point,
+    # staged pools of up to five groups reach it mid-item, and an event cap
+    # that stops the heaviest filters lands among the last particles (two
+    # of the four theta finish, two stop).  Bit-exact against the oracle.
+    tw = W.telegraph_workload(n_theta=4, n_traj=1, n_obs=10, n_particles=97)
+    th = np.vstack([W.TELEGRAPH_TRUTH * s for s in [1.0, 0.7, 1.5, 2.0]])
+    trajs = tw.trajectories[:1]
+    big_pools = dict(pool_min=2, pool_max=5, pool_events=1 << 20, pool_first=5, refill_min=1,
+                     priority=0, items_per_cu=0, persistent=0, schedule=1)
+    for H in (31, 32, 33, 63, 97, 129, 320):
+        for cap in (0, 240):
+            ref = _oracle(orc, tw, theta=th, H=H, trajectories=trajs, precision=precision,
+                          event_cap=cap or 100_000_000)
+            for t in (FLOW, PER_INTERVAL, big_pools):
+                _say("drain draws H", H, "cap", cap, "tuning", t, "precision", precision,
+                     "kernel", kernel)
+                got = _gpu(tw, theta=th, H=H, trajectories=trajs, precision=precision,
+                           event_cap=cap, kernel=kernel, tuning=t)
+                assert_parity(got, ref, abs_tol=FP32_ABS if precision else None)
+            if cap:
+                assert set(ref["status"]) == {0, 1}, ref["status"]
+
+
 def test_flow_schedule_graph_replays_and_random_network(orc):
     import torch
     from paper_1606_08281_amd import lik
