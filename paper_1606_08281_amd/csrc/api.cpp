@@ -598,7 +598,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
             hipEvent_t e0 = g_timing.enabled ? timing_mark(st) : nullptr;
             if (flow_spec) {
                 EngineArgs ea = L.e;
-                FlowArgs fb = L.fa;
+                const FlowArgs *fb = flow_args_copy(L.fa.ctl);  // written by k_flow_init
                 void *params[] = {(void *)&ea, (void *)&fb};
                 e = hipModuleLaunchKernel(flow_spec, flow_waves, 1, 1, kPropBlock, 1, 1, 0, st,
                                           params, nullptr);

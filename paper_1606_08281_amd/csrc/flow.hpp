@@ -435,6 +435,16 @@ __device__ __forceinline__ void flow_push(const EngineArgs &e, const FlowArgs &f
 // position is never filled leaves when every filter is done.  One item per
 // wavefront, rather than a loop over items, keeps the event loop's register
 // allocation that of the per-interval kernel.
+// The kernel's first argument, its EngineArgs, read from the kernel-argument
+// segment (constant memory: scalar loads) behind an empty asm statement, so
+// the compiler issues new loads at the uses instead of keeping the values
+// loaded at the kernel's start.
+__device__ __forceinline__ const EngineArgs &reload_engine_args() {
+    auto p = __builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const EngineArgs *)p;
+}
+
 template <class NetT, int UMAX, int RMAX, int W, int PREC>
 __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa,
                                          const NetT &net) {
@@ -468,6 +478,10 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     // release: this item's results before the filter's count goes down
     __threadfence();
     __syncthreads();
+    // From here on the engine's arguments are read again from the kernel's
+    // argument segment, where used (the fields loaded at the kernel's start
+    // would otherwise stay in scalar registers through the event loop).
+    const EngineArgs &ec = reload_engine_args();
     uint32_t left = 0;
     if (lane_id() == 0) {
         left = __hip_atomic_fetch_sub(&fa.remaining[f], 1u, __ATOMIC_ACQ_REL,
@@ -477,22 +491,22 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     }
     left = __builtin_amdgcn_readfirstlane(left);
     if (left != 1u) {
-        flow_unpark_some(e, fa, lane_id());
+        flow_unpark_some(ec, fa, lane_id());
         return;
     }
     // the last item of the interval: weigh the filter with every item's results
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     uint32_t cost = 0;
-    if (flow_weigh(e, f, logy, &cost)) {
-        flow_push(e, fa, f, cost);
-        flow_unpark_some(e, fa, lane_id());
+    if (flow_weigh(ec, f, logy, &cost)) {
+        flow_push(ec, fa, f, cost);
+        flow_unpark_some(ec, fa, lane_id());
     } else {
         __threadfence();
         __syncthreads();
         if (lane_id() == 0)
             __hip_atomic_fetch_add(&fa.ctl[kCtlFinished], 1u, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
-        flow_unpark_some(e, fa, lane_id());
+        flow_unpark_some(ec, fa, lane_id());
     }
 }
 

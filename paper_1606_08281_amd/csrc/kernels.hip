@@ -214,8 +214,10 @@ __global__ void k_flow_init(FlowArgs fa) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap * kFlowRings;
          i += (size_t)gridDim.x * blockDim.x)
         fa.ring[i] = (uint64_t)(i & fa.mask) << 32;  // free for position i
-    if (blockIdx.x == 0)
-        for (int w = threadIdx.x; w < kCtlWords; w += blockDim.x) fa.ctl[w] = 0u;
+    if (blockIdx.x == 0) {
+        for (int w = threadIdx.x; w < kCtlArgs; w += blockDim.x) fa.ctl[w] = 0u;
+        if (threadIdx.x == 0) *const_cast<FlowArgs *>(flow_args_copy(fa.ctl)) = fa;
+    }
 }
 
 // The first interval's items: urgent filters first (pass 0), then the rest
@@ -247,9 +249,9 @@ __global__ void k_flow_seed(EngineArgs e, FlowArgs fa, int pass) {
 }
 
 template <int UMAX, int RMAX, int W, int PREC>
-__global__ __launch_bounds__(kPropBlock) void k_flow(EngineArgs e, FlowArgs fa,
+__global__ __launch_bounds__(kPropBlock) void k_flow(EngineArgs e, const FlowArgs *fa,
                                                      NetArgs<RMAX, W> net) {
-    flow_run<NetArgs<RMAX, W>, UMAX, RMAX, W, PREC>(e, fa, net);
+    flow_run<NetArgs<RMAX, W>, UMAX, RMAX, W, PREC>(e, *fa, net);
 }
 
 __global__ void k_flow_check(EngineArgs e, FlowArgs fa) {
@@ -556,7 +558,7 @@ hipError_t launch_flow(const EngineArgs &e, const FlowArgs &fa, unsigned n_waves
     const void *fn = flow_kernel(umax, rmax, precision);
     if (!fn || n_waves == 0) return hipErrorInvalidValue;
     EngineArgs ea = e;
-    FlowArgs fb = fa;
+    const FlowArgs *fb = flow_args_copy(fa.ctl);  // written by k_flow_init
     void *args[] = {(void *)&ea, (void *)&fb, const_cast<void *>(net)};
     return hipLaunchKernel(fn, dim3(n_waves), dim3(kPropBlock), args, 0, s);
 }

@@ -111,7 +111,8 @@ enum : int {
     kCtlAbort = 160,      // nonzero: a wavefront saw no progress for stall_ticks
     kCtlProgress = 192,   // work items finished
     kCtlSeedItems = 224,  // items of the first interval placed in the item ring
-    kCtlWords = 256
+    kCtlArgs = 256,       // a copy of the launch's FlowArgs (16 words)
+    kCtlWords = 272
 };
 struct FlowArgs {
     // ring r at ring + r (mask + 1): slot pos & mask holds (pos + 1) << 32 |
@@ -133,6 +134,14 @@ struct FlowArgs {
     uint64_t stall_ticks;  // wall-clock ticks without a finished item before a
                            // waiting wavefront gives up (a scheduler fault)
 };
+static_assert(sizeof(FlowArgs) <= 4 * (kCtlWords - kCtlArgs), "FlowArgs copy fits");
+// The flow kernel reads its FlowArgs from the copy in device memory: its
+// fields are loaded where they are used (the hand-off after the event loop
+// reloads them) instead of being held in scalar registers through the event
+// loop, as kernel arguments are.
+__host__ __device__ inline const FlowArgs *flow_args_copy(uint32_t *ctl) {
+    return reinterpret_cast<const FlowArgs *>(ctl + kCtlArgs);
+}
 
 #ifndef __HIPCC_RTC__
 // Host-side launchers (kernels.hip).

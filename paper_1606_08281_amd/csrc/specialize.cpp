@@ -151,10 +151,10 @@ std::string specialized_source(const lik_network &net, int precision) {
          "  lik::propagate_item<lik::SpecNet, "
       << U << ", " << R << ", " << W << ", " << precision << ">(e, net, group);\n}\n";
     o << "extern \"C\" __global__ __launch_bounds__(64) void lik_flow_spec("
-         "lik::EngineArgs e, lik::FlowArgs fa) {\n"
+         "lik::EngineArgs e, const lik::FlowArgs *fa) {\n"
          "  const lik::SpecNet net{};\n"
          "  lik::flow_run<lik::SpecNet, "
-      << U << ", " << R << ", " << W << ", " << precision << ">(e, fa, net);\n}\n";
+      << U << ", " << R << ", " << W << ", " << precision << ">(e, *fa, net);\n}\n";
     if (R <= kPersistentMaxR)
         o << "extern \"C\" __global__ __launch_bounds__(64) void lik_propagate_spec_p("
              "lik::EngineArgs e, int group) {\n"
