@@ -83,6 +83,14 @@ __device__ __forceinline__ double fma_f64(double a, double b, double c) {
     return r;
 }
 
+// a * k + k with one rounding, k taken once from scalar registers (one
+// v_fma_f64; the two-operand form would first copy k into the accumulator).
+__device__ __forceinline__ double fma_f64_s(double a, double k) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %2" : "=v"(r) : "v"(a), "s"(k));
+    return r;
+}
+
 // Natural logarithm of x > 0 (x = 0 -> -inf).  Reduction x = 2^e m,
 // m in [sqrt(1/2), sqrt(2)]; with f = m - 1 and s = f / (2 + f),
 // log m = 2 atanh s = t + t z Q(z), t = 2s, z = s^2,

@@ -91,6 +91,16 @@ __device__ __forceinline__ T *wave_uniform(T *p) {
     return reinterpret_cast<T *>(wave_uniform((uint64_t)reinterpret_cast<unsigned long long>(p)));
 }
 
+// base[i] = v through the global address space (base: device memory), with
+// the byte offset formed in 32 bits: a wave-uniform base stays in scalar
+// registers and the store takes the offset from one vector register.
+template <class T>
+__device__ __forceinline__ void store_global(T *base, uint32_t i, T v) {
+    typedef __attribute__((address_space(1))) char gchar;
+    typedef __attribute__((address_space(1))) T gT;
+    *(gT *)((gchar *)base + i * (uint32_t)sizeof(T)) = v;
+}
+
 template <bool B, class T, class F>
 struct pick_type {
     using type = T;
@@ -111,23 +121,31 @@ struct EventDraw {
     Real nl, u2;
 };
 
+// A 53-bit integer as binary64, exactly: hi 2^32 + lo < 2^53 is representable,
+// so the one rounding of the fused multiply-add leaves it unchanged.
+__device__ __forceinline__ double u53_to_f64(uint64_t z) {
+    return __builtin_fma((double)(uint32_t)(z >> 32), 0x1p32, (double)(uint32_t)z);
+}
+
 template <int PREC>
 __device__ __forceinline__ EventDraw<PREC> event_draw(uint32_t n, uint32_t j, uint32_t c2,
                                                       uint32_t c3, uint32_t k0, uint32_t k1) {
     using Real = typename EventDraw<PREC>::Real;
     const Block4 b = philox4x32_10(n, j, c2, c3, k0, k1);
     EventDraw<PREC> r;
+    // u1 = (z + 1) 2^-k in (0, 1] and u2 = z' 2^-k in [0, 1), each formed
+    // exactly (every intermediate value is representable)
     if (PREC == LIK_FP32_MIXED) {
         // the leading 24 bits of the binary64 uniforms' words
-        const float u1 = (float)((b.w1 >> 8) + 1u) * 0x1p-24f;  // (0, 1]
+        const float u1 = __builtin_fmaf((float)(b.w1 >> 8), 0x1p-24f, 0x1p-24f);
         r.nl = (Real)(-flog_pos(u1));
-        r.u2 = (Real)((float)(b.w3 >> 8) * 0x1p-24f);  // [0, 1)
+        r.u2 = (Real)((float)(b.w3 >> 8) * 0x1p-24f);
     } else {
         const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
         const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
-        const double u1 = (double)(z1 + 1) * 0x1p-53;  // (0, 1]
+        const double u1 = fma_f64_s(u53_to_f64(z1), 0x1p-53);
         r.nl = (Real)(-dlog_pos(u1));
-        r.u2 = (Real)((double)z2 * 0x1p-53);  // [0, 1)
+        r.u2 = (Real)(u53_to_f64(z2) * 0x1p-53);
     }
     return r;
 }
@@ -360,16 +378,19 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     // a finished particle: overflow check, and its counts, events and final
     // total propensity into the pool's LDS slot (staged) or straight to
     // global memory
+    // (global-memory stores at a wave-uniform base plus the particle's 32-bit
+    // offset: one address operation per particle instead of one per array)
     auto retire = [&]() {
 #pragma unroll
         for (int u = 0; u < UMAX; ++u)
             if (u < U && x[u] > kCountLimit)
                 st = st > LIK_STATUS_COUNT_OVERFLOW ? st : LIK_STATUS_COUNT_OVERFLOW;
+        const uint32_t jo = (uint32_t)j;
 #pragma unroll
         for (int u = 0; u < UMAX; ++u)
-            if (u < U) dst[(size_t)u * Hp + j] = x[u];
-        pev_p[j] = n;
-        pa0_p[j] = a0_end;
+            if (u < U) store_global(dst + (size_t)u * Hp, jo, x[u]);
+        store_global(pev_p, jo, n);
+        store_global(pa0_p, jo, a0_end);
     };
 
     if ((pool >> 6) == 3) {
