@@ -413,7 +413,10 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
                 if (!have) {
                     if (pend) retire();
                     pend = false;
-                    const int nj = next + (int)__popcll(idle & ((1ull << lane) - 1ull));
+                    // rank among the idle lanes: idle lanes below this one
+                    const int nj = next + (int)__builtin_amdgcn_mbcnt_hi(
+                                              (uint32_t)(idle >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                     if (nj < p1) {
                         have = true;
                         pend = true;
@@ -639,7 +642,8 @@ __device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const 
                 }
                 const int avail = p1 - next;
                 if (!have) {
-                    const int rank = (int)__popcll(idle & ((1ull << lane) - 1ull));
+                    const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                     if (rank < avail) {
                         j = next + rank;
 #pragma unroll
