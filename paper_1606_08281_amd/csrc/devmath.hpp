@@ -65,6 +65,54 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return Block4{c0, c1, c2, c3};
 }
 
+// The same generator for an event's counter (n, j, c2, c3) whose last two
+// words and key are wave-uniform: the exclusive-or of two uniform words in
+// rounds 1 and 2 is formed once, on the scalar unit (a vector instruction
+// reads one scalar operand, so the general form copies the other into a
+// vector register for every event).  Same block as philox4x32_10.
+__device__ __forceinline__ Block4 philox4x32_10_event(uint32_t n, uint32_t j, uint32_t c2,
+                                                      uint32_t c3, uint32_t k0, uint32_t k1) {
+    const uint64_t q1 = (uint64_t)c2 * 0xCD9E8D57u;  // uniform
+    uint32_t a1 = (uint32_t)(q1 >> 32) ^ k0;         // round 1: hi(c2 M1) ^ key
+    uint32_t b1 = c3 ^ k1;
+    uint32_t a2 = (uint32_t)q1 ^ (k0 + 0x9E3779B9u);  // round 2: c1 ^ key
+    asm("" : "+s"(a1), "+s"(b1), "+s"(a2));
+    // round 1
+    const uint64_t p0 = (uint64_t)n * 0xD2511F53u;
+    uint32_t c0 = j ^ a1;
+    uint32_t w2 = (uint32_t)(p0 >> 32) ^ b1;
+    uint32_t w3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    // round 2 (its c1 is lo(c2 M1), folded into a2)
+    {
+        const uint64_t r0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t r1 = (uint64_t)w2 * 0xCD9E8D57u;
+        c0 = (uint32_t)(r1 >> 32) ^ a2;
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(r0 >> 32), w3, k1, 0x96);
+        w3 = (uint32_t)r0;
+        const uint32_t c1 = (uint32_t)r1;
+        w2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+        uint32_t c1r = c1;
+#pragma unroll
+        for (int round = 2; round < 10; ++round) {
+            const uint64_t s0 = (uint64_t)c0 * 0xD2511F53u;
+            const uint64_t s1 = (uint64_t)w2 * 0xCD9E8D57u;
+            const uint32_t m0 = __builtin_amdgcn_bitop3_b32((uint32_t)(s1 >> 32), c1r, k0, 0x96);
+            const uint32_t m2 = __builtin_amdgcn_bitop3_b32((uint32_t)(s0 >> 32), w3, k1, 0x96);
+            c1r = (uint32_t)s1;
+            w3 = (uint32_t)s0;
+            c0 = m0;
+            w2 = m2;
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        return Block4{c0, c1r, w2, w3};
+    }
+}
+
 // ln 2 split: 32 leading significant bits (so e * LN2_HI is exact for any
 // binary64 exponent) and the binary64 nearest to the remainder.
 constexpr double kLn2Hi = 0x1.62e42feep-1;

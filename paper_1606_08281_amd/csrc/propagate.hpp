@@ -128,10 +128,8 @@ __device__ __forceinline__ double u53_to_f64(uint64_t z) {
 }
 
 template <int PREC>
-__device__ __forceinline__ EventDraw<PREC> event_draw(uint32_t n, uint32_t j, uint32_t c2,
-                                                      uint32_t c3, uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ EventDraw<PREC> draw_from_block(const Block4 &b) {
     using Real = typename EventDraw<PREC>::Real;
-    const Block4 b = philox4x32_10(n, j, c2, c3, k0, k1);
     EventDraw<PREC> r;
     // u1 = (z + 1) 2^-k in (0, 1] and u2 = z' 2^-k in [0, 1), each formed
     // exactly (every intermediate value is representable)
@@ -148,6 +146,22 @@ __device__ __forceinline__ EventDraw<PREC> event_draw(uint32_t n, uint32_t j, ui
         r.u2 = (Real)(u53_to_f64(z2) * 0x1p-53);
     }
     return r;
+}
+
+// The draw of event n of particle j (any counter words).
+template <int PREC>
+__device__ __forceinline__ EventDraw<PREC> event_draw(uint32_t n, uint32_t j, uint32_t c2,
+                                                      uint32_t c3, uint32_t k0, uint32_t k1) {
+    return draw_from_block<PREC>(philox4x32_10(n, j, c2, c3, k0, k1));
+}
+
+// The same where c2, c3 and the key are wave-uniform (one work item's
+// particles): the generator's uniform parts go to scalar registers.
+template <int PREC>
+__device__ __forceinline__ EventDraw<PREC> event_draw_uniform(uint32_t n, uint32_t j,
+                                                              uint32_t c2, uint32_t c3,
+                                                              uint32_t k0, uint32_t k1) {
+    return draw_from_block<PREC>(philox4x32_10_event(n, j, c2, c3, k0, k1));
 }
 
 // One direct-method event of one particle (Supplementary I, the "Simulate"
@@ -402,7 +416,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
         if (have)
             ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
                 net, c, x, S, t_end, event_cap, clock, n, st, a0_end, have,
-                [&] { return event_draw<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
+                [&] { return event_draw_uniform<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
         // Once at least refill_min lanes are idle (or all are), the idle
         // lanes store what they hold and take the next particles of the
         // pool, in lane order.
@@ -465,8 +479,8 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
         __syncthreads();
         const int r = (lane * m) >> 16;
         if (r < k)
-            dbuf[lane] = event_draw<PREC>(xn[r] + (uint32_t)(lane - r * D), (uint32_t)xj[r], c2,
-                                          c3, k0, k1);
+            dbuf[lane] = event_draw_uniform<PREC>(xn[r] + (uint32_t)(lane - r * D),
+                                                  (uint32_t)xj[r], c2, c3, k0, k1);
         __syncthreads();
         const int slot = rank * D;
 #pragma unroll 1
