@@ -160,7 +160,10 @@ int lik_create_network(int32_t n_species, int32_t n_reactions, const int32_t *re
             if (p == 1) (first < 0 ? first : second) = u;
             if (v < -p) { delete n; return fail(LIK_EINVAL, "net change consumes an unused reactant"); }
             if (v < -7 || v > 7) { delete n; return fail(LIK_EUNSUPPORTED, "|net change| above 7"); }
-            n->nu[r][u >> 3] |= ((uint32_t)v & 0xFu) << (4 * (u & 7));
+            if (nu_bytes(U))
+                n->nu[r][0] |= ((uint32_t)v & 0xFFu) << (8 * u);
+            else
+                n->nu[r][u >> 3] |= ((uint32_t)v & 0xFu) << (4 * (u & 7));
         }
         if (homo >= 0) { n->kind[r] = kOrder2Homo; n->s1[r] = homo; n->s2[r] = homo; }
         else if (second >= 0) { n->kind[r] = kOrder2Hetero; n->s1[r] = first; n->s2[r] = second; }

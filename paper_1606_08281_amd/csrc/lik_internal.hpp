@@ -36,8 +36,10 @@ constexpr int kSortBuckets = 64;  // half octaves of the expected cost, below th
 enum : int32_t { kOrder0 = 0, kOrder1 = 1, kOrder2Homo = 2, kOrder2Hetero = 3 };
 
 // Network tables in kernel-argument (scalar) memory.  Net change of reaction
-// r for species u sits in bits [4(u%8), 4(u%8)+4) of nu[r][u/8], two's
-// complement.
+// r for species u, two's complement: for at most four species a byte, bits
+// [8u, 8u+8) of nu[r][0] (a byte field is added with its sign extension in
+// one instruction); otherwise bits [4(u%8), 4(u%8)+4) of nu[r][u/8].
+__host__ __device__ constexpr bool nu_bytes(int U) { return U <= 4; }
 template <int RMAX, int W>
 struct NetArgs {
     int32_t U, R;

@@ -62,9 +62,15 @@ __device__ __forceinline__ void select_reaction(const NetT &net, const Real *S, 
 
 template <int UMAX, int W>
 __device__ __forceinline__ void apply_change(int U, const uint32_t *sel, int *x) {
+    if (nu_bytes(U)) {
 #pragma unroll
-    for (int u = 0; u < UMAX; ++u)
-        if (u < U) x[u] += __builtin_amdgcn_sbfe(sel[u >> 3], 4 * (u & 7), 4);
+        for (int u = 0; u < (UMAX < 4 ? UMAX : 4); ++u)
+            if (u < U) x[u] += (int)(signed char)(sel[0] >> (8 * u));
+    } else {
+#pragma unroll
+        for (int u = 0; u < UMAX; ++u)
+            if (u < U) x[u] += __builtin_amdgcn_sbfe(sel[u >> 3], 4 * (u & 7), 4);
+    }
 }
 
 // A value equal on every lane, moved to scalar registers.
