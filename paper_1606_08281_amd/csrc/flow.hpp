@@ -438,7 +438,8 @@ __device__ __forceinline__ void flow_push(const EngineArgs &e, const FlowArgs &f
 // The kernel's first argument, its EngineArgs, read from the kernel-argument
 // segment (constant memory: scalar loads) behind an empty asm statement, so
 // the compiler issues new loads at the uses instead of keeping the values
-// loaded at the kernel's start.
+// loaded at the kernel's start.  Every kernel that calls flow_run takes its
+// EngineArgs by value as its first argument (offset 0 of the segment).
 __device__ __forceinline__ const EngineArgs &reload_engine_args() {
     auto p = __builtin_amdgcn_kernarg_segment_ptr();
     asm volatile("" : "+s"(p));

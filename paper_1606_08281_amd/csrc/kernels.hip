@@ -248,6 +248,8 @@ __global__ void k_flow_seed(EngineArgs e, FlowArgs fa, int pass) {
     }
 }
 
+// e must stay the first argument: flow_run reads it again from offset 0 of
+// the kernel-argument segment.
 template <int UMAX, int RMAX, int W, int PREC>
 __global__ __launch_bounds__(kPropBlock) void k_flow(EngineArgs e, const FlowArgs *fa,
                                                      NetArgs<RMAX, W> net) {

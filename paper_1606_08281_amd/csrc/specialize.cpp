@@ -150,6 +150,8 @@ std::string specialized_source(const lik_network &net, int precision) {
          "  const lik::SpecNet net{};\n"
          "  lik::propagate_item<lik::SpecNet, "
       << U << ", " << R << ", " << W << ", " << precision << ">(e, net, group);\n}\n";
+    // e must stay the first argument: flow_run reads it again from offset 0
+    // of the kernel-argument segment
     o << "extern \"C\" __global__ __launch_bounds__(64) void lik_flow_spec("
          "lik::EngineArgs e, const lik::FlowArgs *fa) {\n"
          "  const lik::SpecNet net{};\n"
