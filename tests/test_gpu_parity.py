@@ -186,6 +186,39 @@ def test_random_network_20x40_small(orc, precision):
         assert_parity(got, ref, abs_tol=FP32_ABS if precision else None)
 
 
+def _small_random_workload(U, R, n_theta=6, n_particles=128, n_obs=4, events=200.0):
+    # seeded random network of U species and R reactions, x0 ~ Poisson(50),
+    # rates log-uniform on [1e-2, 1], observation interval set for about
+    # `events` events per particle, synthetic Gaussian data on species 0, 1
+    net = W.random_network(n_species=U, n_reactions=R, seed=W.SEED_NET + 1000 * U + R)
+    rng = np.random.Generator(np.random.PCG64(W.SEED_DATA + 1000 * U + R))
+    x0 = rng.poisson(50, U).astype(np.int32)
+    theta = W.log_uniform(rng, np.full(R, 1e-2), np.full(R, 1.0), n_theta)
+    a0 = np.median([(th * net.propensity_factor(x0)).sum() for th in theta])
+    t_obs = (events / a0) * np.arange(1, n_obs + 1, dtype=np.float64)
+    y = rng.normal(50.0, 10.0, (n_obs, 2))
+    traj = {"t_obs": t_obs, "y": y, "t0": 0.0, "x0": x0}
+    return W.Workload(f"random-{U}x{R}", net, W.OBS_GAUSSIAN, [0, 1], 10.0, theta, [traj],
+                      n_particles)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape", [(3, 12), (4, 9), (6, 10), (8, 16)])
+def test_net_change_packing(orc, shape, precision):
+    # net changes are packed as bytes for at most four species and as 4-bit
+    # fields beyond; the generic kernel runs a network of at most four
+    # species but more than eight reactions in a wider instance, which must
+    # still read bytes.  Both kernel variants against the oracle.
+    U, R = shape
+    wl = _small_random_workload(U, R)
+    ref = _oracle(orc, wl, precision=precision)
+    assert np.all(ref["status"] == 0), ref["status"]
+    for kernel in KERNELS:
+        _say("net-change packing U", U, "R", R, "precision", precision, "kernel", kernel)
+        got = _gpu(wl, precision=precision, kernel=kernel)
+        assert_parity(got, ref, abs_tol=FP32_ABS if precision else None)
+
+
 def test_graph_replays_match_eager():
     # the captured launch sequence, replayed with a new seed each time and
     # with eager work in between, equals eager launches every time
