@@ -14,7 +14,9 @@ namespace lik {
 // Propensities a_r = c_r h_r(x) and their running sums S_r in reaction
 // order (h_r = prod_u C(x_u, p_ru)); returns S_{R-1}.  Real is double for the
 // binary64 step; for the binary32 step the factor h_r (exact in binary64) is
-// rounded to binary32 and multiplied by the binary32 rate.
+// rounded to binary32 and multiplied by the binary32 rate.  S_0 = a_0: a sum
+// started from zero would differ only in the sign of an all-zero sum, which
+// no comparison, division or result depends on.
 template <class NetT, int RMAX, class Real>
 __device__ __forceinline__ Real running_sums(const NetT &net, const Real *c, const int *x,
                                              Real *S) {
@@ -34,7 +36,8 @@ __device__ __forceinline__ Real running_sums(const NetT &net, const Real *c, con
             } else {
                 h = (double)x[net.s1[r]] * (double)x[net.s2[r]];
             }
-            s = s + c[r] * (Real)h;
+            const Real a = c[r] * (Real)h;
+            s = (r == 0) ? a : s + a;
             S[r] = s;
         }
     }
@@ -175,14 +178,15 @@ __device__ __forceinline__ EventDraw<PREC> event_draw_uniform(uint32_t n, uint32
 // the particle's interval (no reaction possible, the event cap, or the next
 // event beyond the observation time -- it is discarded) or one event.
 // draw() gives the event's EventDraw (for the particle's current n).
-// a0_end keeps the last total propensity (a scheduling estimate).
+// a0_end keeps the last total propensity (a scheduling estimate, stored as
+// binary32 when the particle is).
 template <class NetT, int UMAX, int RMAX, int W, int PREC, class Real, class DrawFn>
 __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x, Real *S,
                                           double t_end, uint32_t event_cap, double &clock,
-                                          uint32_t &n, int &st, float &a0_end, bool &have,
+                                          uint32_t &n, int &st, Real &a0_end, bool &have,
                                           DrawFn &&draw) {
     const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
-    a0_end = (float)s;
+    a0_end = s;
     if (!(s > (Real)0)) {
         have = false;  // no reaction can fire before the observation
     } else if (n >= event_cap) {
@@ -394,7 +398,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     bool pend = have;            // the lane holds a particle not stored yet
     int st = LIK_STATUS_OK;
     Real S[RMAX];
-    float a0_end = 0.0f;  // total propensity at the particle's last state
+    Real a0_end = (Real)0;  // total propensity at the particle's last state
     // a finished particle: overflow check, and its counts, events and final
     // total propensity into the pool's LDS slot (staged) or straight to
     // global memory
@@ -410,7 +414,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
         for (int u = 0; u < UMAX; ++u)
             if (u < U) store_global(dst + (size_t)u * Hp, jo, x[u]);
         store_global(pev_p, jo, n);
-        store_global(pa0_p, jo, a0_end);
+        store_global(pa0_p, jo, (float)a0_end);
     };
 
     if ((pool >> 6) == 3) {
@@ -568,7 +572,7 @@ __device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const 
     uint32_t *pev = nullptr;
     float *pa0 = nullptr;
     int st = LIK_STATUS_OK;
-    float a0_end = 0.0f;
+    Real a0_end = (Real)0;
     Real S[RMAX];
 
     auto retire = [&]() {
@@ -580,7 +584,7 @@ __device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const 
         for (int u = 0; u < UMAX; ++u)
             if (u < U) dst[(size_t)u * hp + j] = x[u];
         pev[j] = n;
-        pa0[j] = a0_end;
+        pa0[j] = (float)a0_end;
         if (st != LIK_STATUS_OK) atomicMax(&e.fstatus[fl], st);
         st = LIK_STATUS_OK;
     };
