@@ -178,22 +178,21 @@ __device__ __forceinline__ EventDraw<PREC> event_draw_uniform(uint32_t n, uint32
 // the particle's interval (no reaction possible, the event cap, or the next
 // event beyond the observation time -- it is discarded) or one event.
 // draw() gives the event's EventDraw (for the particle's current n).
-// Returns whether the particle goes on (false: it has reached its end).
 // a0_end keeps the last total propensity (a scheduling estimate, stored as
 // binary32 when the particle is).
 template <class NetT, int UMAX, int RMAX, int W, int PREC, class Real, class DrawFn>
-__device__ __forceinline__ bool ssa_event(const NetT &net, const Real *c, int *x, Real *S,
+__device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x, Real *S,
                                           double t_end, uint32_t event_cap, double &clock,
-                                          uint32_t &n, int &st, Real &a0_end,
+                                          uint32_t &n, int &st, Real &a0_end, bool &have,
                                           DrawFn &&draw) {
     const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
     a0_end = s;
-    if (!(s > (Real)0)) return false;  // no reaction can fire before the observation
-    if (n >= event_cap) {
+    if (!(s > (Real)0)) {
+        have = false;  // no reaction can fire before the observation
+    } else if (n >= event_cap) {
         st = st > LIK_STATUS_EVENT_CAP ? st : LIK_STATUS_EVENT_CAP;
-        return false;
-    }
-    {
+        have = false;
+    } else {
         const EventDraw<PREC> dr = draw();
         double tau;
         Real target;
@@ -204,13 +203,15 @@ __device__ __forceinline__ bool ssa_event(const NetT &net, const Real *c, int *x
             tau = (double)dr.nl / (double)s;
             target = (Real)((double)dr.u2 * (double)s);
         }
-        if (clock + tau > t_end) return false;  // the pending event is discarded
-        uint32_t sel[W];
-        select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
-        apply_change<UMAX, W>(net.U, sel, x);
-        clock = clock + tau;
-        n = n + 1;
-        return true;
+        if (clock + tau > t_end) {
+            have = false;  // the pending event is discarded
+        } else {
+            uint32_t sel[W];
+            select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
+            apply_change<UMAX, W>(net.U, sel, x);
+            clock = clock + tau;
+            n = n + 1;
+        }
     }
 }
 
@@ -423,8 +424,8 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     }
     for (;;) {
         if (have)
-            have = ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
-                net, c, x, S, t_end, event_cap, clock, n, st, a0_end,
+            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
+                net, c, x, S, t_end, event_cap, clock, n, st, a0_end, have,
                 [&] { return event_draw_uniform<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
         // Once at least refill_min lanes are idle (or all are), the idle
         // lanes store what they hold and take the next particles of the
@@ -495,9 +496,9 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
 #pragma unroll 1
         for (int i = 0; i < D; ++i) {
             if (have)
-                have = ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
-                    net, c, x, S, t_end, event_cap, clock, n, st, a0_end,
-                    [&] { return dbuf[slot + i]; });
+                ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, t_end, event_cap, clock,
+                                                           n, st, a0_end, have,
+                                                           [&] { return dbuf[slot + i]; });
             if (__ballot(have) == 0ull) break;
         }
         __syncthreads();  // the draws are read before the next round writes
@@ -590,8 +591,8 @@ __device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const 
 
     for (;;) {
         if (have)
-            have = ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
-                net, c, x, S, t_end, cap, clock, n, st, a0_end,
+            ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
+                net, c, x, S, t_end, cap, clock, n, st, a0_end, have,
                 [&] { return event_draw<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
         uint64_t idle = __ballot(!have);
         const int n_idle = (int)__popcll(idle);
