@@ -57,11 +57,14 @@ extern "C" {
 #define LIK_STATUS_OK 0
 #define LIK_STATUS_EVENT_CAP 1      /* a particle needed more events in one interval than the cap */
 #define LIK_STATUS_COUNT_OVERFLOW 2 /* a count exceeded 2^30 at the end of an interval */
-#define LIK_STATUS_BAD_THETA 3      /* a rate was negative, infinite or NaN */
+#define LIK_STATUS_BAD_THETA 3      /* a rate was negative, infinite or NaN, or (with
+                                       LIK_FP32_MIXED) beyond the binary32 range */
 #define LIK_STATUS_SCHEDULER 4      /* the flow schedule saw no work item finish for a
                                        minute and gave up (an internal fault; the limit,
                                        in microseconds, can be lowered through the
                                        environment variable LIK_FLOW_STALL_US for tests) */
+#define LIK_STATUS_CANCELLED 5      /* server: the request was cancelled (lik_server_cancel) */
+#define LIK_STATUS_TIMED_OUT 6      /* server: the request's own time limit passed first */
 
 /* observation noise models (Sec. "General Task": Y ~ p(. | X, theta)) */
 #define LIK_OBS_GAUSSIAN 0  /* y = x_s + N(0, sigma^2) per observed species s */
@@ -149,10 +152,11 @@ typedef struct lik_tuning {
 } lik_tuning;
 
 /* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30}) / reads a
- * network's
- * tuning; LIK_EINVAL outside the bounds above.  Not to be called while an
- * evaluation on this network is being enqueued on another thread.  The
- * server uses the defaults for every network. */
+ * network's tuning for lik_eval_batch, lik_eval_batch_device and
+ * lik_eval_requests; LIK_EINVAL outside the bounds above.  Not to be called
+ * while an evaluation on this network is being enqueued on another thread.
+ * A server ignores the networks' tunings: it partitions every iteration by
+ * lik_server_opts.tuning (NULL: the defaults). */
 int lik_network_set_tuning(lik_network_t net, const lik_tuning *tuning);
 int lik_network_get_tuning(lik_network_t net, lik_tuning *out);
 
@@ -307,6 +311,9 @@ typedef struct lik_request {
     int32_t reserved;           /* must be 0 */
     uint64_t seed;
     uint64_t event_cap;         /* 0 = default */
+    int64_t timeout_us;         /* > 0: a request not finished this long after its submit is
+                                   withdrawn like a cancelled one, with LIK_STATUS_TIMED_OUT;
+                                   0: no limit */
 } lik_request;
 
 typedef struct lik_server_stats {
@@ -314,6 +321,7 @@ typedef struct lik_server_stats {
     uint64_t iterations;                    /* engine iterations run */
     double p50_latency_us, p99_latency_us;  /* submit -> result available, completed requests */
     double busy_s;                          /* wall time with resident work */
+    uint64_t cancelled;                     /* requests withdrawn (cancelled or timed out) */
 } lik_server_stats;
 
 /* Creates a server on the current device.  LIK_ENOMEM if the arena cannot be allocated. */
@@ -333,6 +341,18 @@ int lik_server_submit(lik_server_t srv, const lik_request *req, uint64_t *ticket
  */
 int lik_server_wait(lik_server_t srv, uint64_t ticket, double *loglik_out, int32_t *status_out,
                     int64_t timeout_us);
+
+/*
+ * Withdraws a request.  Still queued: it is removed at once.  Resident: its
+ * filter slots stop at the next iteration boundary and its slots and memory
+ * are released once the work already enqueued for it has passed; the other
+ * requests' results are unaffected.  Either way the ticket then completes:
+ * lik_server_wait returns LIK_OK with LIK_STATUS_CANCELLED for every theta
+ * and NaN log-likelihoods.  A request whose results are already being
+ * copied back is left to finish (LIK_OK; its results stay valid).
+ * LIK_EINVAL for an unknown ticket.  Thread-safe.
+ */
+int lik_server_cancel(lik_server_t srv, uint64_t ticket);
 
 int lik_server_stats_get(lik_server_t srv, lik_server_stats *out);
 

@@ -415,10 +415,15 @@ typedef struct {
     double *ll_inc;
 } orc_trace;
 
+/* A rate vector the filter cannot run: a negative, infinite or NaN rate; in
+ * FP32-mixed mode also a rate beyond the binary32 range (it would round to
+ * infinity, and infinity times a zero mass-action factor is NaN). */
 static int bad_theta(const orc_problem *P, const double *c)
 {
-    for (int r = 0; r < P->n_reactions; ++r)
+    for (int r = 0; r < P->n_reactions; ++r) {
         if (!(c[r] >= 0.0) || isinf(c[r])) return 1;
+        if (P->precision == ORC_FP32_MIXED && isinf((float)c[r])) return 1;
+    }
     return 0;
 }
 

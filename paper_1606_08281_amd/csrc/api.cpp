@@ -584,6 +584,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     r.P = obs->n_observed;
     r.obs_kind = obs->kind;
     r.group = 0;
+    r.precision = precision;
     for (int k = 0; k < LIK_MAX_OBSERVED; ++k) r.obs_species[k] = k < r.P ? obs->species[k] : 0;
     r.sigma = obs->sigma;
     r.seed = seed;

@@ -33,7 +33,9 @@ namespace lik {
 
 // ---------------------------------------------------------------------------
 // admit: fill the slots of one request.  Rates that are negative, infinite or
-// NaN mark every slot of that theta BAD_THETA before any simulation.
+// NaN -- and, for the binary32 step, beyond the binary32 range (they would
+// round to infinity, and infinity times a zero mass-action factor is NaN) --
+// mark every slot of that theta BAD_THETA before any simulation.
 // ---------------------------------------------------------------------------
 __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
     const int F = r.n_theta * r.M;
@@ -77,6 +79,7 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
     for (int q = 0; q < r.R; ++q) {
         const double c = d.theta[q];
         if (!(c >= 0.0) || isinf(c)) bad = true;
+        if (r.precision == LIK_FP32_MIXED && isinf((float)c)) bad = true;
     }
     e.tcur[f] = 0;
     e.fll[f] = bad ? __builtin_nan("") : 0.0;
@@ -412,6 +415,12 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     }
 }
 
+// stop: the slots of a withdrawn request take no further interval
+__global__ void k_stop(EngineArgs e, int32_t base, int32_t F) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < F) e.fflags[base + k] |= kFlagStopped;
+}
+
 // ---------------------------------------------------------------------------
 // finish: per-theta sum over trajectories in trajectory order, status, aux.
 // ---------------------------------------------------------------------------
@@ -471,6 +480,12 @@ hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs
 }
 
 const void *admit_kernel() { return (const void *)k_admit; }
+
+hipError_t launch_stop(const EngineArgs &e, int32_t base, int32_t F, hipStream_t s) {
+    if (F <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stop, dim3((F + 255) / 256), dim3(256), 0, s, e, base, F);
+    return hipGetLastError();
+}
 
 hipError_t launch_order(const EngineArgs &e, hipStream_t s) {
     hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, e);

@@ -182,6 +182,7 @@ struct RequestArgs {
     const int32_t *x0;          // [M * U]
     int32_t *state;             // particle state arena of the request
     int32_t n_theta, M, H, Hp, U, R, P, obs_kind, group;
+    int32_t precision;          // LIK_FP64 or LIK_FP32_MIXED (rates checked for its range)
     int32_t obs_species[LIK_MAX_OBSERVED];
     double sigma;
     uint64_t seed;
@@ -197,6 +198,8 @@ size_t request_state_bytes(int64_t F, int32_t U, int32_t Hp);
 hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs &r,
                         hipStream_t s);
 const void *admit_kernel();  // k_admit, for updating captured graph nodes
+// Stops slots base .. base + F - 1 (a withdrawn request): later iterations skip them.
+hipError_t launch_stop(const EngineArgs &e, int32_t base, int32_t F, hipStream_t s);
 hipError_t launch_finish(const EngineArgs &e, int32_t base, int32_t n_theta, int32_t M,
                          double *loglik, int32_t *status, const lik_aux *aux, hipStream_t s);
 #endif  // __HIPCC_RTC__

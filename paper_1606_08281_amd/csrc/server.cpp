@@ -13,6 +13,11 @@
 // event.  Requests are complete when their event has passed; their slots and
 // memory are then released.  At most `max_inflight` iterations are enqueued
 // ahead of the GPU, which bounds how long a new request waits to join.
+// A request withdrawn while queued (lik_server_cancel, or its own time limit)
+// leaves the queue at once; one withdrawn while resident has its slots
+// stopped by a kernel enqueued behind the iterations already in flight, and
+// its slots and memory are released once that kernel has passed, so no
+// later request can be placed in memory an earlier iteration still uses.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -97,6 +102,11 @@ struct Request {
     std::vector<uint32_t> ids;
     std::vector<int32_t> offsets, x0;
     Clock::time_point submitted;
+    bool has_deadline = false;  // its own time limit (lik_request.timeout_us)
+    Clock::time_point deadline;
+    // withdrawal (cancel or time limit): the status every theta reports
+    bool withdraw = false;
+    int32_t withdraw_status = LIK_STATUS_OK;
     // placement, once admitted
     int group = -1;
     size_t slot = 0, dev_off = 0, pin_off = 0;
@@ -157,7 +167,7 @@ struct lik_server {
     std::thread worker;
 
     // statistics
-    uint64_t n_submitted = 0, n_completed = 0, n_evals = 0, n_iterations = 0;
+    uint64_t n_submitted = 0, n_completed = 0, n_evals = 0, n_iterations = 0, n_cancelled = 0;
     std::vector<double> latencies_us;
     double busy_s = 0.0;
     bool busy = false;
@@ -170,6 +180,7 @@ namespace {
 int validate_request(const lik_server *srv, const lik_request *q) {
     if (!q) return fail(LIK_EINVAL, "request is NULL");
     if (q->reserved != 0) return fail(LIK_EINVAL, "reserved must be 0");
+    if (q->timeout_us < 0) return fail(LIK_EINVAL, "timeout_us must be >= 0");
     lik_eval_opts o = {q->precision, LIK_KERNEL_AUTO, q->event_cap, q->theta_ids, 0, 0};
     int rc = check_common(q->net, &q->obs, &o, q->n_theta, q->data.n_traj, q->n_particles);
     if (rc) return rc;
@@ -219,6 +230,7 @@ hipError_t admit(lik_server *S, Request &r) {
     a.P = r.obs.n_observed;
     a.obs_kind = r.obs.kind;
     a.group = r.group;
+    a.precision = r.precision;
     for (int k = 0; k < LIK_MAX_OBSERVED; ++k) a.obs_species[k] = r.obs.species[k];
     a.sigma = r.obs.sigma;
     a.seed = r.seed;
@@ -288,6 +300,29 @@ void release(lik_server *S, Request &r) {
     S->groups[r.group].residents -= 1;
 }
 
+// Results of a withdrawn request: NaN log-likelihoods and its status.
+void complete_withdrawn(lik_server *S, Request &r) {
+    r.loglik.assign((size_t)r.n_theta, __builtin_nan(""));
+    r.status.assign((size_t)r.n_theta, r.withdraw_status);
+    r.done = true;
+    S->n_cancelled += 1;
+    S->cv_done.notify_all();
+}
+
+// Withdraws a request (caller holds the lock): a queued one leaves the queue
+// and completes now; a resident one is stopped by the worker.  A request
+// already finishing (results on their way) is left alone.
+void withdraw(lik_server *S, const std::shared_ptr<Request> &r, int32_t status) {
+    if (r->done || r->finishing || r->withdraw) return;
+    r->withdraw = true;
+    r->withdraw_status = status;
+    if (r->group < 0) {
+        auto it = std::find(S->queue.begin(), S->queue.end(), r);
+        if (it != S->queue.end()) S->queue.erase(it);
+        complete_withdrawn(S, *r);
+    }
+}
+
 double percentile(std::vector<double> v, double q) {
     if (v.empty()) return 0.0;
     std::sort(v.begin(), v.end());
@@ -299,20 +334,44 @@ void worker_main(lik_server *S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
+        // requests past their own time limit are withdrawn
+        const Clock::time_point now = Clock::now();
+        std::vector<std::shared_ptr<Request>> expired;
+        for (auto &q : S->queue)
+            if (q->has_deadline && now >= q->deadline) expired.push_back(q);
+        for (auto &q : expired) withdraw(S, q, LIK_STATUS_TIMED_OUT);  // leaves the queue
+        for (auto &r : S->resident)
+            if (r->has_deadline && now >= r->deadline) withdraw(S, r, LIK_STATUS_TIMED_OUT);
+        // withdrawn resident requests: their slots stop behind the iterations
+        // already enqueued; slots and memory are released when that has passed
+        for (auto &r : S->resident) {
+            if (!r->withdraw || r->finishing) continue;
+            if (launch_stop(S->e, (int32_t)r->slot, (int32_t)r->F(), S->stream) != hipSuccess)
+                S->worker_error = "stop launch failed";
+            (void)hipEventCreateWithFlags(&r->done_event, hipEventDisableTiming);
+            (void)hipEventRecord(r->done_event, S->stream);
+            r->finishing = true;
+            r->iterations_left = 0;
+        }
         // completions whose results have reached pinned memory
         for (auto it = S->resident.begin(); it != S->resident.end();) {
             Request &r = **it;
             if (r.finishing && hipEventQuery(r.done_event) == hipSuccess) {
-                r.loglik.assign(S->res_loglik + r.slot, S->res_loglik + r.slot + r.n_theta);
-                r.status.assign(S->res_status + r.slot, S->res_status + r.slot + r.n_theta);
                 (void)hipEventDestroy(r.done_event);
                 r.done_event = nullptr;
                 release(S, r);
-                r.done = true;
-                S->n_completed += 1;
-                S->n_evals += (uint64_t)r.n_theta;
-                S->latencies_us.push_back(
-                    std::chrono::duration<double, std::micro>(Clock::now() - r.submitted).count());
+                if (r.withdraw) {
+                    complete_withdrawn(S, r);
+                } else {
+                    r.loglik.assign(S->res_loglik + r.slot, S->res_loglik + r.slot + r.n_theta);
+                    r.status.assign(S->res_status + r.slot, S->res_status + r.slot + r.n_theta);
+                    r.done = true;
+                    S->n_completed += 1;
+                    S->n_evals += (uint64_t)r.n_theta;
+                    S->latencies_us.push_back(
+                        std::chrono::duration<double, std::micro>(Clock::now() - r.submitted)
+                            .count());
+                }
                 it = S->resident.erase(it);
                 S->cv_done.notify_all();
                 if (S->resident.empty() && S->busy) {
@@ -523,6 +582,10 @@ int lik_server_submit(lik_server_t S, const lik_request *q, uint64_t *ticket) {
     if (r->device_bytes() > S->arena_bytes || r->input_bytes() > S->opts.staging_bytes)
         return fail(LIK_EINVAL, "request larger than the server's arena or staging memory");
     r->submitted = Clock::now();
+    if (q->timeout_us > 0) {
+        r->has_deadline = true;
+        r->deadline = r->submitted + std::chrono::microseconds(q->timeout_us);
+    }
     std::lock_guard<std::mutex> g(S->mu);
     if (S->stopping) return fail(LIK_EINVAL, "server is shutting down");
     r->ticket = S->next_ticket++;
@@ -554,6 +617,16 @@ int lik_server_wait(lik_server_t S, uint64_t ticket, double *loglik_out, int32_t
     return LIK_OK;
 }
 
+int lik_server_cancel(lik_server_t S, uint64_t ticket) {
+    if (!S) return fail(LIK_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->tickets.find(ticket);
+    if (it == S->tickets.end()) return fail(LIK_EINVAL, "unknown ticket");
+    withdraw(S, it->second, LIK_STATUS_CANCELLED);
+    S->cv_work.notify_one();
+    return LIK_OK;
+}
+
 int lik_server_stats_get(lik_server_t S, lik_server_stats *out) {
     if (!S || !out) return fail(LIK_EINVAL, "server or out is NULL");
     std::lock_guard<std::mutex> g(S->mu);
@@ -561,6 +634,7 @@ int lik_server_stats_get(lik_server_t S, lik_server_stats *out) {
     out->completed = S->n_completed;
     out->evals = S->n_evals;
     out->iterations = S->n_iterations;
+    out->cancelled = S->n_cancelled;
     out->p50_latency_us = percentile(S->latencies_us, 0.50);
     out->p99_latency_us = percentile(S->latencies_us, 0.99);
     out->busy_s = S->busy_s + (S->busy ? std::chrono::duration<double>(Clock::now() -

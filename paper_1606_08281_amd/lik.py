@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "liblik.so")
 
 LIK_OK, LIK_EINVAL, LIK_ENOMEM, LIK_EDEVICE, LIK_EUNSUPPORTED, LIK_ETIMEOUT = 0, -1, -2, -3, -4, -5
 STATUS_OK, STATUS_EVENT_CAP, STATUS_COUNT_OVERFLOW, STATUS_BAD_THETA = 0, 1, 2, 3
-STATUS_SCHEDULER = 4
+STATUS_SCHEDULER, STATUS_CANCELLED, STATUS_TIMED_OUT = 4, 5, 6
 OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
 FP64, FP32_MIXED = 0, 1
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
@@ -23,7 +23,8 @@ MAX_OBSERVED = 8
 
 EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile", "lik_eval_batch",
             "lik_workspace_size", "lik_eval_batch_device", "lik_server_create",
-            "lik_server_submit", "lik_server_wait", "lik_server_stats_get", "lik_server_destroy",
+            "lik_server_submit", "lik_server_wait", "lik_server_cancel", "lik_server_stats_get",
+            "lik_server_destroy",
             "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version",
             "lik_network_set_tuning", "lik_network_get_tuning", "lik_autotune_device"]
 
@@ -77,14 +78,14 @@ class Request(ctypes.Structure):
                 ("n_theta", ctypes.c_int32), ("theta", ctypes.c_void_p),
                 ("theta_ids", ctypes.c_void_p), ("data", Data), ("n_particles", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("event_cap", ctypes.c_uint64)]
+                ("event_cap", ctypes.c_uint64), ("timeout_us", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("evals", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
                 ("p50_latency_us", ctypes.c_double), ("p99_latency_us", ctypes.c_double),
-                ("busy_s", ctypes.c_double)]
+                ("busy_s", ctypes.c_double), ("cancelled", ctypes.c_uint64)]
 
 
 class Aux(ctypes.Structure):
@@ -135,6 +136,8 @@ def lib():
         L.lik_server_submit.restype = ctypes.c_int
         L.lik_server_wait.argtypes = [vp, ctypes.c_uint64, vp, vp, ctypes.c_int64]
         L.lik_server_wait.restype = ctypes.c_int
+        L.lik_server_cancel.argtypes = [vp, ctypes.c_uint64]
+        L.lik_server_cancel.restype = ctypes.c_int
         L.lik_server_stats_get.argtypes = [vp, vp]
         L.lik_server_stats_get.restype = ctypes.c_int
         L.lik_server_destroy.argtypes = [vp]
@@ -374,8 +377,9 @@ class Server:
         self._n_theta = {}
 
     def submit(self, net, obs_kind, observed, sigma, theta, trajectories, n_particles, seed,
-               precision=FP64, event_cap=0, theta_ids=None):
-        """Copies the request's inputs; returns a ticket."""
+               precision=FP64, event_cap=0, theta_ids=None, timeout_s=None):
+        """Copies the request's inputs; returns a ticket.  timeout_s: the
+        request's own time limit (withdrawn with STATUS_TIMED_OUT)."""
         theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, net.R))
         P = len(observed)
         d = pack_trajectories(trajectories, P)
@@ -393,6 +397,7 @@ class Server:
         q.reserved = 0
         q.seed = int(seed) & (2**64 - 1)
         q.event_cap = int(event_cap)
+        q.timeout_us = 0 if timeout_s is None else max(1, int(timeout_s * 1e6))
         t = ctypes.c_uint64()
         _check(lib().lik_server_submit(self.handle, ctypes.byref(q), ctypes.byref(t)))
         self._n_theta[t.value] = theta.shape[0]
@@ -410,6 +415,10 @@ class Server:
         _check(rc)
         del self._n_theta[ticket]
         return ll, st
+
+    def cancel(self, ticket):
+        """Withdraws a request (its wait then reports STATUS_CANCELLED)."""
+        _check(lib().lik_server_cancel(self.handle, ticket))
 
     def stats(self):
         s = ServerStats()

@@ -248,34 +248,121 @@ def test_graph_replays_match_eager():
         assert np.array_equal(ll_g.cpu().numpy(), host["loglik"])
 
 
+_HEAVY = {}
+
+
+def heaviest_telegraph_theta(orc, k):
+    """The k rate vectors of the benchmark's telegraph batch that need the
+    most SSA events, ranked by an oracle run of every theta at 16 particles
+    against two trajectories (a cheap, deterministic ranking; a few
+    seconds)."""
+    if k not in _HEAVY:
+        wl = W.telegraph_workload()
+        P = orc.Problem(wl.net.orders, wl.net.stoich, wl.obs_kind, wl.observed, wl.sigma,
+                        wl.theta, wl.trajectories[:2], 16, wl.seed)
+        ev = orc.evaluate(P)["events"].reshape(wl.n_theta, 2).sum(axis=1)
+        _HEAVY[k] = np.argsort(ev, kind="stable")[::-1][:k].copy()
+    return _HEAVY[k]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_telegraph_full_batch_sampled(orc, precision):
     # the benchmark's batch and launch configuration (device entry point,
-    # automatic kernel choice): 1024 theta x 10 trajectories x 1000 particles
-    # x 50 observations; a sample of theta is recomputed by the oracle
+    # automatic kernel choice, default schedule): 1024 theta x 10 trajectories
+    # x 1000 particles x 50 observations.  The oracle recomputes a sample that
+    # spans the cost range -- the three cheapest rate vectors, three from the
+    # middle, and the six heaviest, which alone hold most of the batch's SSA
+    # events (up to 1.2e5 events per particle, long pools, drain draws and
+    # protein counts in the thousands) -- with all ten trajectories each:
+    # per-filter event counts, final particle counts and log-likelihoods.
     import torch
     from paper_1606_08281_amd import lik
     wl = W.telegraph_workload()
     net = lik.Network(wl.net.orders, wl.net.stoich)
     db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
                          wl.n_particles, precision=precision)
+    final = torch.empty((wl.n_theta * wl.n_traj, wl.net.U, wl.n_particles), dtype=torch.int32,
+                        device="cuda")
     _say("telegraph full batch 1024x10x1000x50 precision", precision)
-    ll, st = db.run(torch.from_numpy(wl.theta).cuda(), wl.seed)
+    ll, st = db.run(torch.from_numpy(wl.theta).cuda(), wl.seed, final_state=final)
     torch.cuda.synchronize()
     ll, st = ll.cpu().numpy(), st.cpu().numpy()
-    events = db.events.cpu().numpy().astype(np.uint64).reshape(wl.n_theta, wl.n_traj)
+    M = wl.n_traj
+    events = db.events.cpu().numpy().astype(np.uint64).reshape(wl.n_theta, M)
+    fll = db.filter_loglik.cpu().numpy().reshape(wl.n_theta, M)
     th = wl.theta
     cost = th[:, 2] / th[:, 3] * th[:, 4] + th[:, 2]
     order = np.argsort(cost)
-    idx = np.sort(np.concatenate([order[:3], order[[200, 450, 700]]]))
-    _say("oracle sample", idx.tolist())
+    heavy = heaviest_telegraph_theta(orc, 6)
+    idx = np.unique(np.concatenate([order[:3], order[[200, 450, 700]], heavy]))
+    _say("oracle sample", idx.tolist(), "heaviest", heavy.tolist())
     ref = _oracle(orc, wl, theta=th[idx], theta_ids=idx, precision=precision)
+    fs = final.view(wl.n_theta, M, wl.net.U, wl.n_particles)[torch.from_numpy(idx).cuda()]
+    fs = fs.cpu().numpy().reshape(len(idx) * M, wl.net.U, wl.n_particles)
     assert np.array_equal(st[idx], ref["status"])
     assert np.array_equal(events[idx].ravel(), ref["events"])
+    assert np.array_equal(fs, ref["final_state"])
+    assert np.all(np.abs(fll[idx].ravel() - ref["filter_ll"]) <= REL * np.abs(ref["filter_ll"]))
     assert np.all(np.abs(ll[idx] - ref["loglik"]) <= REL * np.abs(ref["loglik"]))
     if precision:
         assert np.all(np.abs(ll[idx] - ref["loglik"]) <= FP32_ABS)
+    # the heavy sample is heavy: it holds a large share of the batch's events
+    assert events[heavy].sum() > 0.25 * events.sum()
     assert np.all(st == 0) and np.all(np.isfinite(ll))
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_heaviest_theta_at_4096_particles(orc, precision, kernel):
+    # the four heaviest telegraph rate vectors at the largest particle count
+    # (pools of several groups of 64, drain draws at thousands of events per
+    # particle), one trajectory, five observations: bit-exact
+    wl = W.telegraph_workload()
+    heavy = np.sort(heaviest_telegraph_theta(orc, 4))
+    trajs = [dict(wl.trajectories[3], t_obs=wl.trajectories[3]["t_obs"][:5],
+                  y=wl.trajectories[3]["y"][:5])]
+    _say("heaviest theta", heavy.tolist(), "H=4096 T=5 precision", precision, "kernel", kernel)
+    got = _gpu(wl, theta=wl.theta[heavy], theta_ids=heavy, H=4096, trajectories=trajs,
+               precision=precision, kernel=kernel)
+    ref = _oracle(orc, wl, theta=wl.theta[heavy], theta_ids=heavy, H=4096, trajectories=trajs,
+                  precision=precision)
+    assert_parity(got, ref, abs_tol=FP32_ABS if precision else None)
+    assert ref["events"].min() > 4096 * 5 * 100
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_count_overflow(orc, precision, kernel):
+    # counts started just below 2^30 under immigration: a filter stops with
+    # COUNT_OVERFLOW at the first interval whose end count exceeds 2^30, on
+    # both sides, after the same events; the others run to the end
+    wl = W.immigration_death_workload(n_theta=4, n_particles=130)
+    limit = 1 << 30
+    tr = dict(wl.trajectories[0])
+    tr["x0"] = np.array([limit - 300], np.int32)
+    tr["y"] = tr["y"] + float(limit - 300)
+    theta = np.array([[10.0, 0.0], [10.0, 1e-9], [0.5, 0.0], [1e-3, 1e-9]])
+    _say("count overflow precision", precision, "kernel", kernel)
+    got = _gpu(wl, theta=theta, trajectories=[tr], precision=precision, kernel=kernel)
+    ref = _oracle(orc, wl, theta=theta, trajectories=[tr], precision=precision)
+    assert list(ref["status"]) == [2, 2, 0, 0], ref["status"]
+    assert_parity(got, ref)
+    assert np.array_equal(got["filter_events"], ref["events"])   # the stopped ones too
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fp32_rates_beyond_binary32(orc, kernel):
+    # a rate beyond the binary32 range is a bad rate vector for the
+    # FP32-mixed step only; both sides agree in both modes
+    wl = W.immigration_death_workload(n_theta=3, n_particles=64)
+    theta = np.array([[10, 0.1], [1e39, 0.1], [0.1, 5e38]])
+    for precision in (0, 1):
+        _say("rates beyond binary32, precision", precision, "kernel", kernel)
+        got = _gpu(wl, theta=theta, precision=precision, event_cap=10_000, kernel=kernel)
+        ref = _oracle(orc, wl, theta=theta, precision=precision, event_cap=10_000)
+        want = [0, 1, 0] if precision == 0 else [0, 3, 3]
+        assert list(ref["status"]) == want, ref["status"]
+        assert_parity(got, ref, abs_tol=FP32_ABS if precision else None)
 
 
 TUNINGS = [dict(pool_min=1, pool_max=1, pool_events=0, pool_first=1, refill_min=1, priority=0,

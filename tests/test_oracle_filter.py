@@ -147,6 +147,52 @@ def test_statuses(orc):
     assert out["status"][0] == 0 and out["loglik"][0] == -np.inf
 
 
+def test_fp32_rates_beyond_binary32_are_bad_theta(orc):
+    # FP32-mixed rounds every rate to binary32; one beyond its range would be
+    # infinite there (and infinity times a zero reactant count is NaN), so the
+    # rate vector is rejected in that mode only
+    wl = W.immigration_death_workload(n_theta=3, n_particles=16)
+    theta = np.array([[10, 0.1], [1e39, 0.1], [3.0e38, 0.1]])   # 3e38 < FLT_MAX
+    # (a cap of 10^4 events per interval stops the enormous rates quickly)
+    f32 = orc.evaluate(problem_from(orc, wl, theta=theta, precision=1, event_cap=10_000))
+    assert list(f32["status"]) == [0, 3, 1]
+    assert np.isfinite(f32["loglik"][0]) and np.all(np.isnan(f32["loglik"][1:]))
+    f64 = orc.evaluate(problem_from(orc, wl, theta=theta, precision=0, event_cap=10_000))
+    assert list(f64["status"]) == [0, 1, 1]   # binary64 takes both rates (the cap stops them)
+
+
+def test_count_overflow_at_the_exact_limit(orc):
+    # Pure immigration (0 -> X at rate k1, no death) fires at times that do
+    # not depend on the count, so with one particle (no resampling) the path
+    # from x0 is the path from 0 shifted by x0.  Starting at x0 = 2^30 - X(t_k)
+    # the count ends interval k at exactly 2^30 -- allowed -- and the next
+    # interval above it: COUNT_OVERFLOW there, after the same events.
+    wl = W.immigration_death_workload(n_theta=1, n_particles=1)
+    theta = np.array([[10.0, 0.0]])
+    base = orc.trace_filter(problem_from(orc, wl, theta=theta), 0, 0)
+    cum = base["states"][:, 0, 0].astype(np.int64)   # events up to the end of each interval
+    assert base["status"] == 0 and np.all(np.diff(cum) > 0)
+    limit = 1 << 30
+    for k in (0, 6, 18):
+        tr = dict(wl.trajectories[0])
+        tr["x0"] = np.array([limit - cum[k]], np.int32)
+        tr["y"] = tr["y"] + float(limit - cum[k])
+        w2 = W.Workload(wl.name, wl.net, wl.obs_kind, wl.observed, wl.sigma, theta, [tr], 1)
+        out = orc.evaluate(problem_from(orc, w2), want_final_state=True)
+        if k + 1 < len(cum):
+            assert out["status"][0] == 2, (k, out["status"])
+            assert out["events"][0] == cum[k + 1]
+            assert math.isnan(out["loglik"][0])
+            assert out["final_state"][0, 0, 0] == limit - cum[k] + cum[k + 1]
+    # started at exactly the limit minus the whole path's events, every
+    # interval ends at or below 2^30: no overflow
+    tr = dict(wl.trajectories[0])
+    tr["x0"] = np.array([limit - cum[-1]], np.int32)
+    w3 = W.Workload(wl.name, wl.net, wl.obs_kind, wl.observed, wl.sigma, theta, [tr], 1)
+    out = orc.evaluate(problem_from(orc, w3), want_final_state=True)
+    assert out["status"][0] == 0 and out["final_state"][0, 0, 0] == limit
+
+
 def _unbiased(lhat, lstar, k=4.0):
     z = np.exp(lhat - lstar)
     se = z.std(ddof=1) / math.sqrt(len(z))

@@ -10,7 +10,10 @@
   is Poisson, pure death is Binomial, a two-state switch has an explicit
   occupation probability, pure immigration counts events as a Poisson
   process) and against the truncated CME for second-order reactions;
-  conservation laws along paths.
+  conservation laws along paths.  Every one of these runs in both
+  arithmetic modes: the binary64 step and the FP32-mixed step (binary32
+  propensities, uniforms and waiting times, binary64 clock), whose event
+  loop is a separate branch of the oracle.
 """
 import math
 from fractions import Fraction
@@ -109,9 +112,13 @@ def test_resampling_degenerate_cases(orc):
 IMM_DEATH = ([[0], [1]], [[1], [-1]])
 
 
+PRECISIONS = [0, 1]   # binary64 step, FP32-mixed step
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
 @pytest.mark.parametrize("k1,k2,t", [(10.0, 0.1, 5.0), (3.0, 1.0, 2.5), (50.0, 2.0, 10.0)])
-def test_ssa_immigration_death_poisson(orc, k1, k2, t):
-    P = _problem(orc, *IMM_DEATH)
+def test_ssa_immigration_death_poisson(orc, k1, k2, t, precision):
+    P = _problem(orc, *IMM_DEATH, precision=precision)
     n = 20000
     states, ev, st = orc.ssa_paths(P, [k1, k2], [0], 0.0, t, n, theta_id=int(k1))
     assert st == 0
@@ -130,8 +137,33 @@ def test_ssa_immigration_death_poisson(orc, k1, k2, t):
     assert p > 1e-4, (chi2, p)
 
 
-def test_ssa_pure_death_binomial(orc):
-    P = _problem(orc, *IMM_DEATH)
+@pytest.mark.parametrize("net_case", ["immigration-death", "telegraph"])
+def test_fp32_mixed_follows_the_fp64_path(orc, net_case):
+    # Both modes draw event n from the same Philox block, the binary32 mode
+    # taking the leading 24 bits of the very words behind the binary64
+    # uniforms; so a path differs from its binary64 twin only where binary32
+    # rounding flips a decision (which reaction fires, or whether the event
+    # falls before the end), which is rare over a few hundred events.
+    if net_case == "immigration-death":
+        orders, stoich, c, x0, t = [[0], [1]], [[1], [-1]], [10.0, 0.1], [0], 20.0
+    else:
+        from paper_1606_08281_amd.workloads import telegraph
+        net = telegraph()
+        orders, stoich = net.orders, net.stoich
+        c, x0, t = [0.5, 0.5, 10.0, 1.0, 2.0, 0.1], [1, 0, 10, 100], 4.0
+    n = 4000
+    p64 = _problem(orc, orders, stoich, precision=0)
+    p32 = _problem(orc, orders, stoich, precision=1)
+    s64, e64, _ = orc.ssa_paths(p64, c, x0, 0.0, t, n, theta_id=3)
+    s32, e32, _ = orc.ssa_paths(p32, c, x0, 0.0, t, n, theta_id=3)
+    same = np.all(s64 == s32, axis=1) & (e64 == e32)
+    assert e64.mean() > 100
+    assert same.mean() > 0.97, same.mean()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ssa_pure_death_binomial(orc, precision):
+    P = _problem(orc, *IMM_DEATH, precision=precision)
     n, x0, k2, t = 20000, 40, 0.3, 2.0
     states, ev, st = orc.ssa_paths(P, [0.0, k2], [x0], 0.0, t, n)
     x = states[:, 0]
@@ -147,8 +179,9 @@ def test_ssa_pure_death_binomial(orc):
     assert np.array_equal(ev.astype(np.int64), x0 - x.astype(np.int64))
 
 
-def test_ssa_pure_immigration_event_count(orc):
-    P = _problem(orc, *IMM_DEATH)
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ssa_pure_immigration_event_count(orc, precision):
+    P = _problem(orc, *IMM_DEATH, precision=precision)
     n, k1, t = 20000, 7.0, 3.0
     states, ev, st = orc.ssa_paths(P, [k1, 0.0], [0], 0.0, t, n)
     assert np.array_equal(states[:, 0].astype(np.uint64), ev)
@@ -158,10 +191,11 @@ def test_ssa_pure_immigration_event_count(orc):
     assert abs(v / (k1 * t) - 1) < 0.05
 
 
-def test_ssa_telegraph_switch_and_conservation(orc):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ssa_telegraph_switch_and_conservation(orc, precision):
     from paper_1606_08281_amd.workloads import telegraph
     net = telegraph()
-    P = _problem(orc, net.orders, net.stoich)
+    P = _problem(orc, net.orders, net.stoich, precision=precision)
     kon, koff, t = 0.7, 0.3, 1.5
     c = [kon, koff, 5.0, 1.0, 2.0, 0.5]
     n = 20000
@@ -173,15 +207,16 @@ def test_ssa_telegraph_switch_and_conservation(orc):
     assert abs(frac - p_on) < 5 * math.sqrt(p_on * (1 - p_on) / n)
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
 @pytest.mark.parametrize("case", ["dimer", "hetero"])
-def test_ssa_second_order_against_cme(orc, case):
+def test_ssa_second_order_against_cme(orc, case, precision):
     if case == "dimer":   # 2A -> B, B -> 2A
         orders, stoich, c, x0, bounds = [[2, 0], [0, 1]], [[-2, 1], [2, -1]], [0.05, 0.4], [20, 0], [20, 10]
     else:                 # A + B -> C, C -> A + B
         orders = [[1, 1, 0], [0, 0, 1]]
         stoich = [[-1, -1, 1], [1, 1, -1]]
         c, x0, bounds = [0.08, 0.5], [12, 9, 0], [12, 9, 9]
-    P = _problem(orc, orders, stoich)
+    P = _problem(orc, orders, stoich, precision=precision)
     t, n = 1.3, 20000
     states, ev, st = orc.ssa_paths(P, c, x0, 0.0, t, n)
     fsp = FSP(orders, stoich, c, bounds)
