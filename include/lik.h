@@ -270,6 +270,31 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs,
                           int32_t *status_out, const lik_aux *aux, void *workspace,
                           size_t workspace_bytes, void *stream);
 
+/*
+ * lik_eval_batch_device_noalloc -- lik_eval_batch_device for callers that
+ * cannot allocate device memory: code under HIP graph capture (the caller's
+ * own), tight serving loops, harnesses that forbid hipMalloc.  Same arguments
+ * and results as lik_eval_batch_device, without the workspace: the library
+ * uses a static device array of LIK_NOALLOC_SCRATCH_BYTES instead (one per
+ * GPU it runs on, held until the process ends).  This entry point calls no
+ * hipMalloc, hipFree or other allocating routine: it records no timing
+ * events, LIK_FLAG_GRAPH is rejected (LIK_EINVAL), and it never compiles or
+ * loads a specialised kernel -- it runs the one an earlier call of another
+ * entry point loaded on this device, else the generic kernels
+ * (LIK_KERNEL_SPECIALIZED with none loaded: LIK_EINVAL).  A batch whose
+ * lik_workspace_size exceeds LIK_NOALLOC_SCRATCH_BYTES is rejected with
+ * LIK_EINVAL before anything is enqueued.  Every call on a GPU uses that
+ * GPU's one array, which keeps the last call's contents (every kernel
+ * initialises what it reads): calls that overlap on one GPU -- on two
+ * streams, or from two threads -- race and give undefined results.
+ */
+#define LIK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lik_eval_batch_device_noalloc(lik_network_t net, const lik_obs_model *obs,
+                                  const lik_eval_opts *opts, int32_t n_theta, const double *theta,
+                                  const lik_data *data, const int32_t *obs_offsets_host,
+                                  int32_t n_particles, uint64_t seed, double *loglik_out,
+                                  int32_t *status_out, const lik_aux *aux, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Continuous-batching server                                               */
 /* ------------------------------------------------------------------------ */

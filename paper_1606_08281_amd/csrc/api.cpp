@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -424,13 +425,14 @@ EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_byte
 }  // namespace
 
 hipError_t lik::engine_iteration(const EngineArgs &e, const GroupLaunch *groups, int n_groups,
-                                 hipStream_t s) {
+                                 hipStream_t s, bool timed) {
+    timed = timed && g_timing.enabled;
     hipError_t err = launch_order(e, s);
     if (err != hipSuccess) return err;
     for (int g = 0; g < n_groups; ++g) {
         const GroupLaunch &G = groups[g];
         if (G.max_items == 0) continue;
-        hipEvent_t e0 = g_timing.enabled ? timing_mark(s) : nullptr;
+        hipEvent_t e0 = timed ? timing_mark(s) : nullptr;
         const bool pers = G.persistent && (G.spec ? G.spec_p != nullptr : G.rmax <= 16);
         const unsigned grid = pers ? std::min(G.max_items, G.persistent_waves) : G.max_items;
         if (G.spec) {
@@ -442,11 +444,11 @@ hipError_t lik::engine_iteration(const EngineArgs &e, const GroupLaunch *groups,
             err = launch_propagate(e, g, grid, G.netargs, G.umax, G.rmax, G.precision, pers, s);
         }
         if (err != hipSuccess) return err;
-        if (g_timing.enabled) g_timing.prop.push_back({e0, timing_mark(s)});
+        if (timed) g_timing.prop.push_back({e0, timing_mark(s)});
     }
-    hipEvent_t w0 = g_timing.enabled ? timing_mark(s) : nullptr;
+    hipEvent_t w0 = timed ? timing_mark(s) : nullptr;
     err = launch_weigh(e, s);
-    if (err == hipSuccess && g_timing.enabled) g_timing.weigh.push_back({w0, timing_mark(s)});
+    if (err == hipSuccess && timed) g_timing.weigh.push_back({w0, timing_mark(s)});
     return err;
 }
 
@@ -469,13 +471,45 @@ const void *lik::generic_netargs(const lik_network &net) {
                            : (const void *)&net.n32;
 }
 
-extern "C" {
+// Scratch of lik_eval_batch_device_noalloc: that entry point's workspace, in
+// a file-scope device array (every GPU the library runs on holds its own
+// copy, at its own address, until the process ends).  In host code the
+// array's name is a host-side stand-in, never a device address: host code
+// uses only the address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) unsigned char scratch[LIK_NOALLOC_SCRATCH_BYTES];
 
-int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
-                          int32_t n_theta, const double *theta, const lik_data *data,
-                          const int32_t *obs_offsets_host, int32_t n_particles, uint64_t seed,
-                          double *loglik_out, int32_t *status_out, const lik_aux *aux,
-                          void *workspace, size_t workspace_bytes, void *stream) {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];  // device address of each device's copy (null: not yet taken)
+
+// The current device's copy of `scratch`: taken once per device, with that
+// device current, on the first no-allocation call there.
+int scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(LIK_EUNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return LIK_OK;
+}
+
+// Body of the device-pointer entry points.  no_alloc: the caller cannot
+// allocate, so nothing here may -- no graph capture or instantiation, no
+// timing events, no compile or load of a specialised kernel (one already
+// loaded on this device by an earlier call is used).
+int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
+                int32_t n_theta, const double *theta, const lik_data *data,
+                const int32_t *obs_offsets_host, int32_t n_particles, uint64_t seed,
+                double *loglik_out, int32_t *status_out, const lik_aux *aux, void *workspace,
+                size_t workspace_bytes, void *stream, bool no_alloc) {
     if (!data) return fail(LIK_EINVAL, "data is NULL");
     int rc = check_common(net, obs, opts, n_theta, data->n_traj, n_particles);
     if (rc) return rc;
@@ -488,8 +522,15 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
         !data->x0)
         return fail(LIK_EINVAL, "NULL input or output pointer");
     const size_t need = lik_workspace_size(net, n_theta, data->n_traj, n_particles);
+    if (no_alloc && opts && (opts->flags & LIK_FLAG_GRAPH))
+        return fail(LIK_EINVAL, "LIK_FLAG_GRAPH needs allocation (graph capture)");
+    if (no_alloc && need > workspace_bytes)
+        return fail(LIK_EINVAL, "batch needs " + std::to_string(need) +
+                                    " bytes of workspace, above the no-allocation entry point's "
+                                    "maximum of LIK_NOALLOC_SCRATCH_BYTES");
     if (!workspace || workspace_bytes < need)
         return fail(LIK_EINVAL, "workspace too small (see lik_workspace_size)");
+    const bool timed = g_timing.enabled && !no_alloc;
 
     const int M = data->n_traj;
     const size_t F = (size_t)n_theta * M;
@@ -524,11 +565,20 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     G.rmax = net->rmax;
     G.precision = precision;
     std::string err;
-    if (!choose_specialized(*net, precision, variant, (double)F * H * t_max, &G.spec, &err))
+    if (no_alloc) {
+        if (variant != LIK_KERNEL_GENERIC) G.spec = loaded_specialized_kernel(*net, precision);
+        if (!G.spec && variant == LIK_KERNEL_SPECIALIZED)
+            return fail(LIK_EINVAL, "the specialised kernel is not loaded on this device yet "
+                                    "(an earlier call of another entry point loads it)");
+    } else if (!choose_specialized(*net, precision, variant, (double)F * H * t_max, &G.spec,
+                                   &err)) {
         return fail(LIK_EDEVICE, "specialised kernel unavailable: " + err);
+    }
     G.persistent = net->tuning.persistent != 0 && net->R <= kPersistentMaxR;
     G.persistent_waves = persistent_waves();
-    if (G.spec && G.persistent) G.spec_p = specialized_kernel(*net, precision, &err, kSpecPersistent);
+    if (G.spec && G.persistent)
+        G.spec_p = no_alloc ? loaded_specialized_kernel(*net, precision, kSpecPersistent)
+                            : specialized_kernel(*net, precision, &err, kSpecPersistent);
 
     // flow schedule: its kernel and one wavefront per work item the batch can
     // have (every interval of every filter in groups of 64)
@@ -538,7 +588,8 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
         // ... and only where its kernel keeps enough wavefronts resident
         int per_cu = 0;
         if (G.spec) {
-            flow_spec = specialized_kernel(*net, precision, &err, kSpecFlow);
+            flow_spec = no_alloc ? loaded_specialized_kernel(*net, precision, kSpecFlow)
+                                 : specialized_kernel(*net, precision, &err, kSpecFlow);
             if (!flow_spec) return fail(LIK_EDEVICE, "specialised flow kernel unavailable: " + err);
             if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, flow_spec, kPropBlock,
                                                                     0) != hipSuccess)
@@ -599,7 +650,7 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
         if (flow) {
             e = launch_flow_setup(L.e, L.fa, st);
             if (e != hipSuccess) return hip_fail(e, "flow setup launch");
-            hipEvent_t e0 = g_timing.enabled ? timing_mark(st) : nullptr;
+            hipEvent_t e0 = timed ? timing_mark(st) : nullptr;
             if (flow_spec) {
                 EngineArgs ea = L.e;
                 const FlowArgs *fb = flow_args_copy(L.fa.ctl);  // written by k_flow_init
@@ -610,12 +661,12 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
                 e = launch_flow(L.e, L.fa, flow_waves, G.netargs, G.umax, G.rmax, precision, st);
             }
             if (e != hipSuccess) return hip_fail(e, "flow launch");
-            if (g_timing.enabled) g_timing.prop.push_back({e0, timing_mark(st)});
+            if (timed) g_timing.prop.push_back({e0, timing_mark(st)});
             e = launch_flow_check(L.e, L.fa, st);
             if (e != hipSuccess) return hip_fail(e, "flow check launch");
         } else {
             for (int t = 0; t < t_max; ++t) {
-                e = engine_iteration(L.e, &G, 1, st);
+                e = engine_iteration(L.e, &G, 1, st, timed);
                 if (e != hipSuccess) return hip_fail(e, "iteration launch");
             }
         }
@@ -718,6 +769,31 @@ int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik
     e = hipGraphLaunch(g.exec, s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return LIK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lik_eval_batch_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,
+                          int32_t n_theta, const double *theta, const lik_data *data,
+                          const int32_t *obs_offsets_host, int32_t n_particles, uint64_t seed,
+                          double *loglik_out, int32_t *status_out, const lik_aux *aux,
+                          void *workspace, size_t workspace_bytes, void *stream) {
+    return eval_device(net, obs, opts, n_theta, theta, data, obs_offsets_host, n_particles, seed,
+                       loglik_out, status_out, aux, workspace, workspace_bytes, stream, false);
+}
+
+int lik_eval_batch_device_noalloc(lik_network_t net, const lik_obs_model *obs,
+                                  const lik_eval_opts *opts, int32_t n_theta, const double *theta,
+                                  const lik_data *data, const int32_t *obs_offsets_host,
+                                  int32_t n_particles, uint64_t seed, double *loglik_out,
+                                  int32_t *status_out, const lik_aux *aux, void *stream) {
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return eval_device(net, obs, opts, n_theta, theta, data, obs_offsets_host, n_particles, seed,
+                       loglik_out, status_out, aux, ws, LIK_NOALLOC_SCRATCH_BYTES, stream, true);
 }
 
 int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts *opts,

@@ -65,6 +65,10 @@ enum SpecKind { kSpecItem = 0, kSpecPersistent = 1, kSpecFlow = 2 };
 hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *err,
                                  int kind = kSpecItem);
 
+// The specialised kernel if an earlier call has already loaded it on the
+// current device, else nullptr; never compiles or loads (no allocation).
+hipFunction_t loaded_specialized_kernel(lik_network &net, int precision, int kind = kSpecItem);
+
 // Compile (or find in the disk cache) without loading: needs no device.
 bool precompile_specialized(const lik_network &net, int precision, std::string *err);
 
@@ -102,8 +106,9 @@ struct GroupLaunch {
 };
 
 // One iteration: order the work, propagate every group, weigh/resample.
+// `timed`: bracket the launches with timing events while timing is enabled.
 hipError_t engine_iteration(const EngineArgs &e, const GroupLaunch *groups, int n_groups,
-                            hipStream_t s);
+                            hipStream_t s, bool timed = true);
 
 // The specialised kernel if the variant and the amount of work call for it.
 // Returns false only when LIK_KERNEL_SPECIALIZED was asked for and failed.

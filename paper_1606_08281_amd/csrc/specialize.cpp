@@ -251,6 +251,16 @@ hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *e
     return pick(k);
 }
 
+hipFunction_t loaded_specialized_kernel(lik_network &net, int precision, int kind) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(net.spec_lock);
+    auto it = net.spec.find({dev, precision});
+    if (it == net.spec.end()) return nullptr;
+    const lik_network::SpecKernels &k = it->second;
+    return kind == kSpecPersistent ? k.persistent : kind == kSpecFlow ? k.flow : k.item;
+}
+
 void release_specialized(lik_network &net) {
     std::lock_guard<std::mutex> g(net.spec_lock);
     int cur = 0;

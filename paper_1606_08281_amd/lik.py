@@ -22,7 +22,8 @@ FLAG_GRAPH = 1
 MAX_OBSERVED = 8
 
 EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile", "lik_eval_batch",
-            "lik_workspace_size", "lik_eval_batch_device", "lik_server_create",
+            "lik_workspace_size", "lik_eval_batch_device", "lik_eval_batch_device_noalloc",
+            "lik_server_create",
             "lik_server_submit", "lik_server_wait", "lik_server_cancel", "lik_server_stats_get",
             "lik_server_destroy",
             "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version",
@@ -130,6 +131,9 @@ def lib():
         L.lik_eval_batch_device.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, u64, vp, vp, vp,
                                             vp, sz, vp]
         L.lik_eval_batch_device.restype = ctypes.c_int
+        L.lik_eval_batch_device_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, u64, vp, vp,
+                                                    vp, vp]
+        L.lik_eval_batch_device_noalloc.restype = ctypes.c_int
         L.lik_server_create.argtypes = [vp, ctypes.POINTER(vp)]
         L.lik_server_create.restype = ctypes.c_int
         L.lik_server_submit.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint64)]
@@ -332,6 +336,24 @@ class DeviceBatch:
             theta_dev.data_ptr(), ctypes.byref(self.data), self.offsets_host.ctypes.data,
             self.H, int(seed) & (2**64 - 1), self.loglik.data_ptr(), self.status.data_ptr(),
             ctypes.byref(aux), ws, self.ws_bytes + 256, ctypes.c_void_p(s.cuda_stream)))
+        return self.loglik, self.status
+
+    def run_noalloc(self, theta_dev, seed, theta_ids_dev=None, stream=None, final_state=None):
+        """The same evaluation through lik_eval_batch_device_noalloc: the
+        library's static scratch instead of this batch's workspace."""
+        torch = self.torch
+        assert theta_dev.dtype == torch.float64 and theta_dev.is_contiguous()
+        assert theta_dev.numel() == self.n_theta * self.net.R
+        s = stream if stream is not None else torch.cuda.current_stream()
+        opts = EvalOpts(self.precision, self.kernel, self.event_cap,
+                        None if theta_ids_dev is None else theta_ids_dev.data_ptr(), self.flags, 0)
+        aux = Aux(self.events.data_ptr(), self.filter_loglik.data_ptr(),
+                  None if final_state is None else final_state.data_ptr())
+        _check(lib().lik_eval_batch_device_noalloc(
+            self.net.handle, ctypes.byref(self.om), ctypes.byref(opts), self.n_theta,
+            theta_dev.data_ptr(), ctypes.byref(self.data), self.offsets_host.ctypes.data,
+            self.H, int(seed) & (2**64 - 1), self.loglik.data_ptr(), self.status.data_ptr(),
+            ctypes.byref(aux), ctypes.c_void_p(s.cuda_stream)))
         return self.loglik, self.status
 
     def autotune(self, theta_dev, seed, theta_ids_dev=None, stream=None):
