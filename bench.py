@@ -7,7 +7,13 @@ vectors x 10 observed trajectories x 1,000 filter particles x 50 log-normal
 observations, binary64.  Inputs are resident in device memory before the
 timed region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serving]
+
+The VALU roofline is priced with the lane-op issue slots per SSA event that
+rocprofv3 measured on the same kernel sources (SQ_THREAD_CYCLES_VALU divided
+by the launch's events, from the committed profile record); where no such
+record matches the sources, with the model count of the event's operations
+at their measured gfx950 issue costs.
 """
 import argparse
 import json
@@ -25,21 +31,31 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
+# Issue cost in full-rate VALU slots on gfx950, measured by
+# microbench/isa_cost.hip (four wavefronts per SIMD, 4.3-4.5 cycles for a
+# full-rate instruction; the table is in the profile summaries): a
+# 32 x 32 -> 64 multiply-add takes one slot, the IEEE-correct binary64 divide
+# sequence fifteen (58 cycles), the binary32 one ten (42 cycles).
+SLOTS_MAD_U64 = 1
+SLOTS_DIV_F64 = 15
+SLOTS_DIV_F32 = 10
+
+
 def ops_per_event(R, U, precision):
-    """Algorithmic VALU issue slots one direct-method SSA event needs (lane
-    operations, quarter-rate instructions counted 4x).  The derivation is
-    itemised in the design notes; it is the count for the method's arithmetic,
-    independent of how the kernel realises it."""
+    """Model count of the VALU issue slots one direct-method SSA event needs
+    (lane operations, each instruction weighted by its measured issue cost).
+    It counts the method's arithmetic, independent of how the kernel
+    realises it; the design notes itemise it."""
     if precision == 0:
-        philox = 10 * (2 * 4 + 2)       # 10 rounds: two 32x32->64 products, two 3-way xors
+        philox = 10 * (2 * SLOTS_MAD_U64 + 2)   # 10 rounds: two 32x32->64 products, two 3-way xors
         uniforms = 2 * 6                # 53-bit assembly, int->binary64, scale (two uniforms)
-        log = 7 + 12 + 3 + 10 + 5       # reduction, IEEE divide, squares, series, recombination
-        tau = 12                        # IEEE binary64 divide
+        log = 7 + SLOTS_DIV_F64 + 3 + 10 + 5   # reduction, divide, squares, series, recombination
+        tau = SLOTS_DIV_F64             # IEEE binary64 divide
     else:
-        philox = 10 * (2 * 4 + 2)       # the binary64 path's block (same stream)
+        philox = 10 * (2 * SLOTS_MAD_U64 + 2)   # the binary64 path's block (same stream)
         uniforms = 2 * 3                # 24-bit shift, int->binary32, scale (two uniforms)
-        log = 7 + 10 + 3 + 6 + 5
-        tau = 10
+        log = 7 + SLOTS_DIV_F32 + 3 + 6 + 5
+        tau = SLOTS_DIV_F32
     propensity = 3 * R                  # count -> float, times rate, running sum
     select = 1 + 2 * (R - 1)            # target, compare + select per reaction
     update = 2                          # species changed by one reaction (at most two here)
@@ -48,13 +64,32 @@ def ops_per_event(R, U, precision):
     return philox + uniforms + log + tau + propensity + select + update + clock + count
 
 
-def cpu_baseline(wl, budget_s=15.0, threads=16):
+def host_cores():
+    """Cores this process may run on, the machine's count and CPU model."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return usable, os.cpu_count(), model
+
+
+def cpu_baseline(wl, budget_s=15.0, share=16):
     """Time the CPU oracle on a seeded random sample of theta (all
-    trajectories, full particle count and length), two theta per call."""
+    trajectories, full particle count and length), two theta per call, on
+    every core this process may use up to the GPU's host share."""
     from oracle import oracle
     rng = np.random.default_rng(7)
     order = rng.permutation(wl.n_theta)
-    nthreads = min(threads, os.cpu_count() or 1)
+    usable, machine, model = host_cores()
+    nthreads = max(1, min(share, usable))
     done, t_total, events = [], 0.0, 0
     k = 0
     while t_total < budget_s and k < len(order):
@@ -70,6 +105,9 @@ def cpu_baseline(wl, budget_s=15.0, threads=16):
         done += idx.tolist()
     return {"value": len(done) / t_total, "unit": "likelihood evals/s", "cores": nthreads,
             "kind": "oracle",
+            "host": {"cores_usable": usable, "cores_machine": machine, "cpu_model": model,
+                     "threads_used": nthreads, "rule": "one oracle thread per usable core, at "
+                     "most the GPU's host share of 16"},
             "sample": f"{len(done)} theta of the same batch (seeded random pick: "
                       f"{done}), all {wl.n_traj} trajectories, H={wl.n_particles}, "
                       f"T={len(wl.trajectories[0]['t_obs'])}; {t_total:.1f} s wall, "
@@ -82,6 +120,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the served-vs-plain block (continuous batching against the same "
+                         "kernels launched once per request)")
+    ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--graph", action="store_true",
                     help="replay the step's launch sequence as a captured HIP graph")
@@ -197,7 +239,19 @@ def main():
             traffic = float(rec["hbm_bytes_per_launch"])
 
     evals = wl.n_theta * args.steps
-    ope = ops_per_event(wl.net.R, wl.net.U, args.precision)
+    model_ope = ops_per_event(wl.net.R, wl.net.U, args.precision)
+    # measured lane-op slots per event (the committed counter record of this
+    # kernel, configuration and sources), else the model count
+    ope, ope_basis = model_ope, "model count at measured instruction costs (no counter record " \
+                                "matches the current kernel sources)"
+    if args.precision == 0 and args.kernel in (0, 2) and not args.tuning and not args.autotune:
+        from paper_1606_08281_amd import profsum
+        rec = profsum.read_record(os.path.join(
+            ROOT, "profiles", f"{kname}_valu_telegraph_1024x10x1000x50_fp64.txt"))
+        if rec is not None:
+            ope = float(rec["lane_slots_per_event"])
+            ope_basis = ("measured: SQ_THREAD_CYCLES_VALU / SSA events of this kernel on these "
+                         "sources (profiles/" + f"{kname}_valu_telegraph_1024x10x1000x50_fp64.txt)")
     prop_s = tm["propagate_ms"] / 1e3
     # A replayed graph records no per-kernel events: its roofline is taken
     # over the whole step instead (a lower bound for the kernel's).
@@ -244,6 +298,9 @@ def main():
                        "interval"),
             "basis": basis,
             "ops_per_event": ope,
+            "ops_per_event_basis": ope_basis,
+            "model_ops_per_event": model_ope,
+            "model_frac": events * model_ope / prop_s / 1e12 / peak,
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": tm["propagate_ms"] / max(tm["propagate_launches"], 1),
             "launches": tm["propagate_launches"],
@@ -253,6 +310,17 @@ def main():
     }
     if fp32_error is not None:
         out["fp32_error_vs_fp64"] = fp32_error
+    if not args.no_serving:
+        print("[bench] serving block: served vs plain per-request launches", flush=True,
+              file=sys.stderr)
+        from paper_1606_08281_amd import serve_bench as SB
+        reqs = SB.request_stream(args.serving_requests)
+        t_s0 = time.perf_counter()
+        nets = SB.make_networks(reqs)
+        out["serving"] = SB.compare(reqs, nets, load=0.8,
+                                    log=lambda m: print("[bench] serving:", m, flush=True,
+                                                        file=sys.stderr))
+        out["serving"]["wall_s"] = time.perf_counter() - t_s0
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", flush=True, file=sys.stderr)
         out["cpu_baseline"] = cpu_baseline(wl)

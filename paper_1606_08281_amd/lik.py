@@ -288,6 +288,35 @@ def eval_batch(net, obs_kind, observed, sigma, theta, trajectories, n_particles,
     return out
 
 
+def eval_batch_device(net, obs_kind, observed, sigma, theta_dev, data_dev, offsets_host,
+                      n_particles, seed, loglik_dev, status_dev, workspace_dev, workspace_bytes,
+                      stream, precision=FP64, kernel=KERNEL_AUTO, event_cap=0,
+                      theta_ids_dev=None):
+    """lik_eval_batch_device on caller-owned device tensors: theta_dev
+    [n_theta * R] float64; data_dev a dict of device tensors obs_offsets,
+    t_obs, y, t0, x0 (as pack_trajectories lays them out); offsets_host the
+    host copy of obs_offsets; loglik_dev / status_dev outputs; workspace_dev
+    at least lik_workspace_size bytes; stream a torch stream.  Enqueues and
+    returns."""
+    n_theta = theta_dev.numel() // net.R
+    data = Data(len(offsets_host) - 1, data_dev["obs_offsets"].data_ptr(),
+                data_dev["t_obs"].data_ptr(), data_dev["y"].data_ptr(), data_dev["t0"].data_ptr(),
+                data_dev["x0"].data_ptr())
+    opts = EvalOpts(int(precision), int(kernel), int(event_cap),
+                    None if theta_ids_dev is None else theta_ids_dev.data_ptr(), 0, 0)
+    om = obs_model(obs_kind, observed, sigma)
+    offs = np.ascontiguousarray(offsets_host, dtype=np.int32)
+    _check(lib().lik_eval_batch_device(
+        net.handle, ctypes.byref(om), ctypes.byref(opts), n_theta, theta_dev.data_ptr(),
+        ctypes.byref(data), offs.ctypes.data, int(n_particles), int(seed) & (2**64 - 1),
+        loglik_dev.data_ptr(), None if status_dev is None else status_dev.data_ptr(), None,
+        workspace_dev.data_ptr(), int(workspace_bytes), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def workspace_size(net, n_theta, n_traj, n_particles):
+    return int(lib().lik_workspace_size(net.handle, int(n_theta), int(n_traj), int(n_particles)))
+
+
 class DeviceBatch:
     """Device-resident inputs + workspace for repeated lik_eval_batch_device
     calls (torch tensors on the current CUDA/HIP device)."""

@@ -2,7 +2,8 @@
 fingerprint that ties a hardware-counter reading to the kernel it was taken on.
 
   python -m paper_1606_08281_amd.profsum --stats DIR --fetch DIR --write DIR \\
-      [--util DIR] --bench BENCH_JSON --out profiles/NAME.md --traffic profiles/NAME.txt
+      [--util DIR] [--valu DIR --valu-bench JSON --valu-record profiles/NAME.txt] \\
+      [--isa FILE] --bench BENCH_JSON --out profiles/NAME.md --traffic profiles/NAME.txt
 
 DIR arguments are rocprofv3 output folders written with --output-format csv
 (--kernel-trace --stats for --stats; --pmc FETCH_SIZE / WRITE_SIZE /
@@ -10,6 +11,15 @@ VALUBusy VALUUtilization for the others, each run with bench.py
 --copy-calibration so that a device-to-device copy of 1 GiB is in the same
 trace).  FETCH_SIZE and WRITE_SIZE are in KiB per dispatch; each is scaled by
 the ratio of the copy's known bytes to what the counter read for it.
+
+--valu: a pass with SQ_THREAD_CYCLES_VALU, SQ_ACTIVE_INST_VALU, SQ_INSTS_VALU
+and GRBM_GUI_ACTIVE over one bench step whose JSON line is --valu-bench.
+SQ_THREAD_CYCLES_VALU counts quad-cycles of VALU issue times the lanes
+active in them: one full-rate wave64 instruction with every lane active is
+64, an instruction that takes two issue slots 128.  Divided by the SSA
+events of the launch it is the measured lane-op issue slots per event, the
+per-event work bench.py prices the VALU roofline with.  --isa adds the table
+printed by microbench/isa_cost.hip.
 """
 import argparse
 import csv
@@ -139,9 +149,9 @@ def traffic(fetch_dir, write_dir, kernel="lik_flow_spec"):
             "hbm_bytes_per_launch": fb + wb}
 
 
-def read_traffic(path):
-    """Traffic record written by this module, or None if absent or taken on
-    other kernel sources."""
+def read_record(path):
+    """A record written by this module (traffic or VALU work), or None if
+    absent or taken on other kernel sources."""
     if not os.path.exists(path):
         return None
     rec = {}
@@ -154,12 +164,37 @@ def read_traffic(path):
     return rec
 
 
+read_traffic = read_record
+
+
+VALU_COUNTERS = ("SQ_THREAD_CYCLES_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU",
+                 "GRBM_GUI_ACTIVE")
+
+
+def valu_work(valu_dir, bench_line, kernel):
+    """Per-launch VALU counters of `kernel` and the per-event figures."""
+    means = counter_means(valu_dir)
+    c = {n: means[(kernel, n)][0] for n in VALU_COUNTERS if (kernel, n) in means}
+    launches = bench_line["roofline"]["launches"]
+    events = bench_line["events_per_step"] * bench_line["steps"] / max(launches, 1)
+    out = {"events_per_launch": events, "launches_profiled": means[(kernel, VALU_COUNTERS[0])][1]}
+    out.update({n.lower(): v for n, v in c.items()})
+    out["lane_slots_per_event"] = c["SQ_THREAD_CYCLES_VALU"] / events
+    out["wave_insts_per_event"] = c["SQ_INSTS_VALU"] / events
+    out["lane_utilisation"] = c["SQ_THREAD_CYCLES_VALU"] / (c["SQ_ACTIVE_INST_VALU"] * 64.0)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--util")
+    ap.add_argument("--valu", help="rocprofv3 --pmc folder with the VALU work counters")
+    ap.add_argument("--valu-bench", help="bench.py JSON line of the --valu run")
+    ap.add_argument("--valu-record", help="record file of the measured VALU work per event")
+    ap.add_argument("--isa", help="output of microbench/isa_cost.hip")
     ap.add_argument("--bench", required=True, help="bench.py JSON line of the same configuration")
     ap.add_argument("--kernel", default="lik_flow_spec", help="kernel whose traffic is recorded")
     ap.add_argument("--title", default="lik_flow_spec — telegraph 1024 theta x 10 traj x "
@@ -201,6 +236,25 @@ def main():
               f" KiB -> {tr['fetch_bytes_per_launch'] / 1e6:.1f} MB; WRITE_SIZE "
               f"{tr['write_kib_per_launch']:.0f} KiB -> {tr['write_bytes_per_launch'] / 1e6:.1f} MB;"
               f" total {tr['hbm_bytes_per_launch'] / 1e6:.1f} MB"]
+    vw = None
+    if a.valu:
+        vb = json.loads(open(a.valu_bench).read().strip().splitlines()[-1])
+        vw = valu_work(a.valu, vb, a.kernel)
+        lines += ["", f"VALU work of {a.kernel} (rocprofv3 --pmc "
+                      f"{' '.join(VALU_COUNTERS)}, one bench step):", "",
+                  f"- SSA events in the launch: {vw['events_per_launch']:.6g}",
+                  f"- SQ_THREAD_CYCLES_VALU {vw['sq_thread_cycles_valu']:.6g}, "
+                  f"SQ_ACTIVE_INST_VALU {vw['sq_active_inst_valu']:.6g}, SQ_INSTS_VALU "
+                  f"{vw['sq_insts_valu']:.6g}, GRBM_GUI_ACTIVE {vw.get('grbm_gui_active', 0):.6g}",
+                  f"- lane-op issue slots per event (SQ_THREAD_CYCLES_VALU / events): "
+                  f"{vw['lane_slots_per_event']:.2f}",
+                  f"- wave64 VALU instructions per event (SQ_INSTS_VALU / events): "
+                  f"{vw['wave_insts_per_event']:.3f}",
+                  f"- active lanes per VALU issue slot: {vw['lane_utilisation']:.3f}"]
+    if a.isa:
+        lines += ["", "Issue cost of the event loop's instructions on gfx950 "
+                      "(microbench/isa_cost.hip, one compute unit):", "", "```"]
+        lines += open(a.isa).read().strip().splitlines() + ["```"]
     if util:
         lines += ["", "Utilisation counters (mean per dispatch):", ""]
         for (k, c), (v, n) in sorted(util.items()):
@@ -209,12 +263,21 @@ def main():
     lines += ["", f"Kernel sources fingerprint (sha256): {sha}", ""]
     open(a.out, "w").write("\n".join(lines))
     with open(a.traffic, "w") as f:
-        f.write(f"# HBM traffic of {a.kernel} per launch, telegraph 1024x10x1000x50 FP64,\n"
+        f.write(f"# HBM traffic of {a.kernel} per launch, {a.title},\n"
                 "# default work partitioning; read by bench.py while the kernel sources match.\n")
         f.write(f"source_sha256: {sha}\n")
         for k in ("fetch_scale", "write_scale", "fetch_bytes_per_launch",
                   "write_bytes_per_launch", "hbm_bytes_per_launch"):
             f.write(f"{k}: {tr[k]:.6g}\n")
+    if vw is not None and a.valu_record:
+        with open(a.valu_record, "w") as f:
+            f.write(f"# VALU work of {a.kernel} per SSA event, {a.title};\n"
+                    "# read by bench.py while the kernel sources match.\n")
+            f.write(f"source_sha256: {sha}\n")
+            for k in ("events_per_launch", "sq_thread_cycles_valu", "sq_active_inst_valu",
+                      "sq_insts_valu", "lane_slots_per_event", "wave_insts_per_event",
+                      "lane_utilisation"):
+                f.write(f"{k}: {vw[k]:.6g}\n")
     print(a.out, a.traffic)
 
 

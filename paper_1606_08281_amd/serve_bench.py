@@ -1,5 +1,5 @@
 """Served likelihood requests: continuous batching against plain per-request
-launches on one MI355X.
+launches of the same kernels on one MI355X.
 
 The request stream mixes three networks: telegraph (60 %: 1-32 rate vectors
 drawn from the prior, as a level-set sampler emits them in a proposal round,
@@ -9,8 +9,15 @@ observations) and the 20-species, 40-reaction random network (20 %: 1-8 rate
 vectors, its trajectory of 100 observations, 512 particles); each request has
 its own seed.
 
-  1. saturation: all requests submitted at once, to the server and, one after
-     another, to lik_eval_batch (plain launches per request);
+The plain path is the same network-specialised kernels launched once per
+request through lik_eval_batch_device: device buffers and the workspace are
+allocated once, for the largest request, and reused; every request copies
+its inputs in, runs on one long-lived stream and copies its results back
+before the next starts.  The served path submits the same requests to a
+lik_server.
+
+  1. saturation: every request submitted at once to the server, and one
+     after another through the plain path;
   2. Poisson arrivals at a fixed rate (a fraction of the plain path's
      saturated rate): latency submit -> result, p50/p99, and evals/s.
 
@@ -31,6 +38,11 @@ if ROOT not in sys.path:
 
 from paper_1606_08281_amd import lik  # noqa: E402
 from paper_1606_08281_amd import workloads as W  # noqa: E402
+
+STREAM_WORKLOAD = ("telegraph (60%: 1-32 theta, 1-3 trajectories, 10-50 observations, H in "
+                   "{128, 512, 1000}), immigration-death (20%: 1-32 theta, 10-20 observations) "
+                   "and random 20x40 network (20%: 1-8 theta, 100 observations, H 512) "
+                   "requests; FP64")
 
 
 def request_stream(n, seed=13):
@@ -74,26 +86,99 @@ def uneven_batch(n=8192, seed=17):
     return reqs
 
 
-def run_plain(reqs, nets, arrivals=None):
-    """Requests one at a time through lik_eval_batch, in arrival order."""
-    lat = []
-    t0 = time.perf_counter()
-    for k, r in enumerate(reqs):
-        if arrivals is not None:
-            wait = t0 + arrivals[k] - time.perf_counter()
-            if wait > 0:
-                time.sleep(wait)
+def make_networks(reqs, precompile=True):
+    nets = {}
+    for r in reqs:
         wl = r["wl"]
-        lik.eval_batch(nets[wl.name], wl.obs_kind, wl.observed, wl.sigma, r["theta"], r["trajs"],
-                       r["H"], r["seed"], theta_ids=r["ids"])
-        done = time.perf_counter()
-        lat.append(done - (t0 + (arrivals[k] if arrivals is not None else 0.0)))
-    return time.perf_counter() - t0, np.array(lat)
+        if wl.name not in nets:
+            nets[wl.name] = lik.Network(wl.net.orders, wl.net.stoich)
+            if precompile:
+                nets[wl.name].precompile(lik.FP64)
+    return nets
 
 
-def run_server(reqs, nets, arrivals=None, tuning=None):
+class PlainRunner:
+    """The same kernels once per request through lik_eval_batch_device, with
+    device buffers and the workspace allocated once (for the largest request
+    of the set) and one long-lived stream."""
+
+    def __init__(self, reqs, nets, kernel=lik.KERNEL_SPECIALIZED):
+        import torch
+        self.torch = torch
+        self.nets = nets
+        self.kernel = kernel
+        self.packed = []
+        mx = dict(theta=1, ids=1, obs_offsets=2, t_obs=1, y=1, t0=1, x0=1, ws=256, out=1)
+        for r in reqs:
+            wl = r["wl"]
+            d = lik.pack_trajectories(r["trajs"], len(wl.observed))
+            self.packed.append(d)
+            net = nets[wl.name]
+            mx["theta"] = max(mx["theta"], r["theta"].size)
+            mx["ids"] = max(mx["ids"], len(r["ids"]))
+            for k in ("obs_offsets", "t_obs", "y", "t0", "x0"):
+                mx[k] = max(mx[k], d[k].size)
+            mx["ws"] = max(mx["ws"], lik.workspace_size(net, len(r["theta"]), len(r["trajs"]),
+                                                        r["H"]))
+            mx["out"] = max(mx["out"], len(r["theta"]))
+        dev = "cuda"
+        self.theta = torch.empty(mx["theta"], dtype=torch.float64, device=dev)
+        self.ids = torch.empty(mx["ids"], dtype=torch.int32, device=dev)
+        self.data = {"obs_offsets": torch.empty(mx["obs_offsets"], dtype=torch.int32, device=dev),
+                     "t_obs": torch.empty(mx["t_obs"], dtype=torch.float64, device=dev),
+                     "y": torch.empty(mx["y"], dtype=torch.float64, device=dev),
+                     "t0": torch.empty(mx["t0"], dtype=torch.float64, device=dev),
+                     "x0": torch.empty(mx["x0"], dtype=torch.int32, device=dev)}
+        self.ws_bytes = mx["ws"]
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self.ll = torch.empty(mx["out"], dtype=torch.float64, device=dev)
+        self.st = torch.empty(mx["out"], dtype=torch.int32, device=dev)
+        self.ll_host = torch.empty(mx["out"], dtype=torch.float64).pin_memory()
+        self.stream = torch.cuda.Stream()   # default priority
+
+    def run_one(self, k, r):
+        """Inputs in, one evaluation, results out; returns the log-likelihoods."""
+        torch = self.torch
+        wl = r["wl"]
+        d = self.packed[k]
+        n = len(r["theta"])
+        with torch.cuda.stream(self.stream):
+            self.theta[:r["theta"].size].copy_(torch.from_numpy(r["theta"].ravel()),
+                                               non_blocking=True)
+            self.ids[:n].copy_(torch.from_numpy(r["ids"].astype(np.int32)), non_blocking=True)
+            view = {}
+            for key, t in self.data.items():
+                t[:d[key].size].copy_(torch.from_numpy(d[key].ravel()), non_blocking=True)
+                view[key] = t
+            lik.eval_batch_device(self.nets[wl.name], wl.obs_kind, wl.observed, wl.sigma,
+                                  self.theta[:r["theta"].size], view, d["obs_offsets"], r["H"],
+                                  r["seed"], self.ll, self.st, self.ws, self.ws_bytes + 256,
+                                  self.stream, kernel=self.kernel, theta_ids_dev=self.ids)
+            self.ll_host[:n].copy_(self.ll[:n], non_blocking=True)
+        self.stream.synchronize()
+        return self.ll_host[:n].numpy().copy()
+
+    def run(self, reqs, arrivals=None):
+        """Requests one at a time, in arrival order.  Returns (wall seconds,
+        latencies, results)."""
+        lat, out = [], []
+        t0 = time.perf_counter()
+        for k, r in enumerate(reqs):
+            if arrivals is not None:
+                wait = t0 + arrivals[k] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+            out.append(self.run_one(k, r))
+            lat.append(time.perf_counter() - (t0 + (arrivals[k] if arrivals is not None else 0.0)))
+        return time.perf_counter() - t0, np.array(lat), out
+
+
+def run_server(reqs, nets, arrivals=None, tuning=None, arena_bytes=8 << 30):
+    """Every request through one server.  Returns (wall seconds, latencies,
+    statistics, results)."""
     lat = np.zeros(len(reqs))
-    with lik.Server(arena_bytes=8 << 30, kernel=lik.KERNEL_SPECIALIZED, tuning=tuning) as srv:
+    results = [None] * len(reqs)
+    with lik.Server(arena_bytes=arena_bytes, kernel=lik.KERNEL_SPECIALIZED, tuning=tuning) as srv:
         t0 = time.perf_counter()
         tickets = [None] * len(reqs)
         sub_t = np.zeros(len(reqs))
@@ -102,7 +187,7 @@ def run_server(reqs, nets, arrivals=None, tuning=None):
             for k in range(len(reqs)):
                 while tickets[k] is None:
                     time.sleep(1e-4)
-                srv.wait(tickets[k])
+                results[k] = srv.wait(tickets[k])[0]
                 lat[k] = time.perf_counter() - sub_t[k]
 
         th = threading.Thread(target=waiter)
@@ -119,25 +204,49 @@ def run_server(reqs, nets, arrivals=None, tuning=None):
         th.join()
         total = time.perf_counter() - t0
         stats = srv.stats()
-    return total, lat, stats
+    return total, lat, stats, results
 
 
-def check_equal(reqs, nets, n=8):
-    """Served results equal alone results, bit for bit (a sample)."""
-    with lik.Server(arena_bytes=2 << 30, kernel=lik.KERNEL_SPECIALIZED) as srv:
-        ts = []
-        for r in reqs[:n]:
-            wl = r["wl"]
-            ts.append(srv.submit(nets[wl.name], wl.obs_kind, wl.observed, wl.sigma, r["theta"],
-                                 r["trajs"], r["H"], r["seed"], theta_ids=r["ids"]))
-        served = [srv.wait(t)[0] for t in ts]
-    for r, s in zip(reqs[:n], served):
-        wl = r["wl"]
-        alone = lik.eval_batch(nets[wl.name], wl.obs_kind, wl.observed, wl.sigma, r["theta"],
-                               r["trajs"], r["H"], r["seed"], theta_ids=r["ids"])["loglik"]
-        if not np.array_equal(alone, s, equal_nan=True):
-            return False
-    return True
+def _ms(lat):
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+
+
+def compare(reqs, nets, load=0.8, tuning=None, log=None):
+    """Saturated and at-load comparison of the served and plain paths on one
+    request set; the served results must equal the plain ones bit for bit."""
+    say = log or (lambda *a: None)
+    n_evals = sum(len(r["theta"]) for r in reqs)
+    plain = PlainRunner(reqs, nets)
+    plain.run(reqs[:4])          # kernel loads, allocator, stream
+    run_server(reqs[:4], nets, tuning=tuning)
+    say("warm")
+    t_plain, _, res_plain = plain.run(reqs)
+    say(f"plain saturated {n_evals / t_plain:.1f} evals/s")
+    t_srv, _, st_sat, res_srv = run_server(reqs, nets, tuning=tuning)
+    say(f"server saturated {n_evals / t_srv:.1f} evals/s")
+    equal = all(np.array_equal(a, b, equal_nan=True) for a, b in zip(res_plain, res_srv))
+    rate = load * len(reqs) / t_plain   # requests per second
+    arrivals = np.cumsum(np.random.default_rng(6).exponential(1.0 / rate, len(reqs)))
+    tp, lat_p, _ = plain.run(reqs, arrivals)
+    say("plain at load done")
+    ts, lat_s, st, res_load = run_server(reqs, nets, arrivals, tuning=tuning)
+    say("server at load done")
+    equal = equal and all(np.array_equal(a, b, equal_nan=True) for a, b in zip(res_plain, res_load))
+    return {
+        "requests": len(reqs), "evals": n_evals,
+        "saturated": {"served_evals_per_s": n_evals / t_srv, "plain_evals_per_s": n_evals / t_plain,
+                      "speedup": t_plain / t_srv},
+        "at_load": {"arrival_rate_req_per_s": rate, "load_vs_plain_saturation": load,
+                    "served": dict(evals_per_s=n_evals / ts, **_ms(lat_s)),
+                    "plain": dict(evals_per_s=n_evals / tp, **_ms(lat_p))},
+        "server_stats": st,
+        "served_equals_alone": bool(equal),
+        "plain_path": "same specialised kernels once per request via lik_eval_batch_device; "
+                      "buffers and workspace allocated once, one long-lived stream, inputs "
+                      "copied in and results out per request",
+        "workload": STREAM_WORKLOAD,
+    }
 
 
 def main():
@@ -161,70 +270,35 @@ def main():
     import torch
     torch.cuda.set_device(0)
     reqs = uneven_batch() if args.uneven else request_stream(args.requests)
-    nets = {}
-    for r in reqs:
-        wl = r["wl"]
-        if wl.name not in nets:
-            nets[wl.name] = lik.Network(wl.net.orders, wl.net.stoich)
-            nets[wl.name].precompile(lik.FP64)
+    nets = make_networks(reqs)
     n_evals = sum(len(r["theta"]) for r in reqs)
+
+    def say(m):
+        print("[serve]", m, flush=True, file=sys.stderr)
+
     if args.uneven:
         run_server(reqs[:8], nets, tuning=tuning)
-        print("[serve] warm", flush=True, file=sys.stderr)
-        t_srv, lat, st = run_server(reqs, nets, tuning=tuning)
-        print(f"[serve] uneven batch served in {t_srv:.2f} s", flush=True, file=sys.stderr)
-        sample = reqs[:args.plain_sample]
-        if args.plain_sample == 0:
-            out = {"requests": len(reqs), "makespan_s": t_srv, "server_evals_per_s": n_evals / t_srv,
-                   "tuning": tuning}
-            print(json.dumps(out), flush=True)
-            return
-        t_plain, _ = run_plain(sample, nets)
+        say("warm")
+        t_srv, lat, st, _ = run_server(reqs, nets, tuning=tuning)
+        say(f"uneven batch served in {t_srv:.2f} s")
         out = {"metric": "uneven batch: likelihood evals/s, makespan, p50/p99 completion",
                "requests": len(reqs), "makespan_s": t_srv, "server_evals_per_s": n_evals / t_srv,
                "p50_completion_ms": float(np.percentile(lat, 50) * 1e3),
                "p99_completion_ms": float(np.percentile(lat, 99) * 1e3),
-               "plain_evals_per_s": len(sample) / t_plain,
-               "plain_sample": f"first {len(sample)} requests one at a time via lik_eval_batch",
-               "server_stats": st,
+               "server_stats": st, "tuning": tuning,
                "workload": "8192 single-theta requests, immigration-death and telegraph halves, "
                            "T uniform 10-200, H in {128, 512, 1024, 4096}; FP64"}
+        if args.plain_sample:
+            sample = reqs[:args.plain_sample]
+            plain = PlainRunner(sample, nets)
+            plain.run(sample[:4])
+            t_plain, _, _ = plain.run(sample)
+            out["plain_evals_per_s"] = len(sample) / t_plain
+            out["plain_sample"] = f"first {len(sample)} requests one at a time (plain path)"
         print(json.dumps(out), flush=True)
         return
-    # warm both paths (kernel loads, allocator)
-    run_plain(reqs[:4], nets)
-    run_server(reqs[:4], nets, tuning=tuning)
-    print("[serve] warm", flush=True, file=sys.stderr)
-    t_plain, _ = run_plain(reqs, nets)
-    print(f"[serve] plain saturated {n_evals / t_plain:.1f} evals/s", flush=True, file=sys.stderr)
-    t_srv, _, st_sat = run_server(reqs, nets, tuning=tuning)
-    print(f"[serve] server saturated {n_evals / t_srv:.1f} evals/s", flush=True, file=sys.stderr)
-    rate = args.load * len(reqs) / t_plain   # requests per second
-    arrivals = np.cumsum(np.random.default_rng(6).exponential(1.0 / rate, len(reqs)))
-    tp, lat_p = run_plain(reqs, nets, arrivals)
-    print("[serve] plain at load done", flush=True, file=sys.stderr)
-    ts, lat_s, st = run_server(reqs, nets, arrivals, tuning=tuning)
-    print("[serve] server at load done", flush=True, file=sys.stderr)
-    equal = check_equal(reqs, nets)
-    out = {
-        "metric": "served likelihood evals/s; p50/p99 latency",
-        "requests": len(reqs), "evals": n_evals,
-        "saturated": {"server_evals_per_s": n_evals / t_srv, "plain_evals_per_s": n_evals / t_plain,
-                      "speedup": t_plain / t_srv},
-        "at_load": {"arrival_rate_req_per_s": rate, "load_vs_plain_saturation": args.load,
-                    "server": {"evals_per_s": n_evals / ts,
-                               "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
-                               "p99_ms": float(np.percentile(lat_s, 99) * 1e3)},
-                    "plain": {"evals_per_s": n_evals / tp,
-                              "p50_ms": float(np.percentile(lat_p, 50) * 1e3),
-                              "p99_ms": float(np.percentile(lat_p, 99) * 1e3)}},
-        "server_stats": st,
-        "served_equals_alone": equal,
-        "workload": "telegraph (60%: 1-32 theta, 1-3 trajectories, 10-50 observations, H in "
-                    "{128, 512, 1000}), immigration-death (20%: 1-32 theta, 10-20 observations) "
-                    "and random 20x40 network (20%: 1-8 theta, 100 observations, H 512) "
-                    "requests; FP64",
-    }
+    out = compare(reqs, nets, load=args.load, tuning=tuning, log=say)
+    out["metric"] = "served likelihood evals/s; p50/p99 latency"
     print(json.dumps(out), flush=True)
 
 

@@ -64,3 +64,25 @@ def test_committed_traffic_records_are_well_formed():
         total = float(rec["hbm_bytes_per_launch"])
         assert abs(total - float(rec["fetch_bytes_per_launch"])
                    - float(rec["write_bytes_per_launch"])) <= 1e-4 * total, n
+
+
+def test_valu_work_per_event_from_counters(tmp_path):
+    # SQ_THREAD_CYCLES_VALU / events of the launch is the measured lane-op
+    # issue slots per event; a record is read only for matching sources
+    d = tmp_path / "pmc"
+    d.mkdir()
+    rows = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value",
+            "1,lik_flow_spec.kd,SQ_THREAD_CYCLES_VALU,6400",
+            "1,lik_flow_spec.kd,SQ_ACTIVE_INST_VALU,125",
+            "1,lik_flow_spec.kd,SQ_INSTS_VALU,120",
+            "1,lik_flow_spec.kd,GRBM_GUI_ACTIVE,999",
+            "2,lik::k_admit(),SQ_THREAD_CYCLES_VALU,5"]
+    (d / "x_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    bench = {"events_per_step": 40, "steps": 1, "roofline": {"launches": 1}}
+    vw = profsum.valu_work(str(d), bench, "lik_flow_spec")
+    assert vw["lane_slots_per_event"] == 160.0
+    assert vw["wave_insts_per_event"] == 3.0
+    assert vw["lane_utilisation"] == 6400 / (125 * 64)
+    rec = tmp_path / "valu.txt"
+    rec.write_text(f"source_sha256: {profsum.source_sha256()}\nlane_slots_per_event: 160\n")
+    assert float(profsum.read_record(str(rec))["lane_slots_per_event"]) == 160.0
