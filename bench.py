@@ -2,12 +2,17 @@
 
 A step is one lik_eval_batch_device call: the whole hot path (direct-method
 SSA propagation, observation weighting, log-sum-exp, systematic resampling,
-per-theta reduction) over the telegraph gene-expression batch: 1,024 rate
-vectors x 10 observed trajectories x 1,000 filter particles x 50 log-normal
-observations, binary64.  Inputs are resident in device memory before the
-timed region.  Prints one JSON line.
+per-theta reduction) over one batch.  Default workload: the telegraph
+gene-expression batch, 1,024 rate vectors x 10 observed trajectories x 1,000
+filter particles x 50 log-normal observations, binary64.  --workload random:
+the seeded 20-species, 40-reaction mass-action network, 4,096 rate vectors x
+1 trajectory x 512 particles x 100 Gaussian observations, at the observation
+interval where the median rate vector realises 1e4 SSA events per particle
+per interval (~2.4e12 events per batch).  Inputs are resident in device
+memory before the timed region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serving]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload telegraph|random]
+                  [--precision 0|1] [--no-cpu-baseline] [--no-serving]
 
 The VALU roofline is priced with the lane-op issue slots per SSA event that
 rocprofv3 measured on the same kernel sources (SQ_THREAD_CYCLES_VALU divided
@@ -81,37 +86,63 @@ def host_cores():
     return usable, os.cpu_count(), model
 
 
-def cpu_baseline(wl, budget_s=15.0, share=16):
+def cpu_baseline(wl, budget_s=15.0, share=16, per_call=2, t_sub=None):
     """Time the CPU oracle on a seeded random sample of theta (all
-    trajectories, full particle count and length), two theta per call, on
-    every core this process may use up to the GPU's host share."""
+    trajectories, full particle count), per_call theta per call, on every
+    core this process may use up to the GPU's host share.  t_sub: time only
+    the first t_sub observations of each trajectory and scale the rate by
+    t_sub / T (equal observation intervals: a bounded sample where one whole
+    theta is minutes of CPU work)."""
     from oracle import oracle
     rng = np.random.default_rng(7)
     order = rng.permutation(wl.n_theta)
     usable, machine, model = host_cores()
     nthreads = max(1, min(share, usable))
+    T = len(wl.trajectories[0]["t_obs"])
+    trajs = wl.trajectories
+    if t_sub:
+        trajs = [dict(tr, t_obs=tr["t_obs"][:t_sub], y=tr["y"][:t_sub]) for tr in trajs]
+    scale = (t_sub / T) if t_sub else 1.0
     done, t_total, events = [], 0.0, 0
     k = 0
     while t_total < budget_s and k < len(order):
-        idx = order[k:k + 2]
+        idx = order[k:k + per_call]
         k += len(idx)
         P = oracle.Problem(wl.net.orders, wl.net.stoich, wl.obs_kind, wl.observed, wl.sigma,
-                           wl.theta[idx], wl.trajectories, wl.n_particles, wl.seed,
-                           theta_ids=idx)
+                           wl.theta[idx], trajs, wl.n_particles, wl.seed, theta_ids=idx)
         t0 = time.perf_counter()
         out = oracle.evaluate(P, nthreads=nthreads)
         t_total += time.perf_counter() - t0
         events += int(out["events"].sum())
         done += idx.tolist()
-    return {"value": len(done) / t_total, "unit": "likelihood evals/s", "cores": nthreads,
+    return {"value": len(done) * scale / t_total, "unit": "likelihood evals/s", "cores": nthreads,
             "kind": "oracle",
             "host": {"cores_usable": usable, "cores_machine": machine, "cpu_model": model,
                      "threads_used": nthreads, "rule": "one oracle thread per usable core, at "
                      "most the GPU's host share of 16"},
             "sample": f"{len(done)} theta of the same batch (seeded random pick: "
                       f"{done}), all {wl.n_traj} trajectories, H={wl.n_particles}, "
-                      f"T={len(wl.trajectories[0]['t_obs'])}; {t_total:.1f} s wall, "
-                      f"{events / t_total:.3g} SSA events/s"}
+                      + (f"the first {t_sub} of T={T} observations (rate scaled by {t_sub}/{T})"
+                         if t_sub else f"T={T}")
+                      + f"; {t_total:.1f} s wall, {events / t_total:.3g} SSA events/s"}
+
+
+def workload(name):
+    """(workload, description, record tag) of a bench workload."""
+    from paper_1606_08281_amd import workloads as W
+    if name == "telegraph":
+        return (W.telegraph_workload(),
+                "telegraph gene expression, 6 mass-action rates log-uniform over two decades; "
+                "1024 theta x 10 trajectories x 1000 filter particles x 50 log-normal "
+                "observations (sigma 0.1)", "telegraph_1024x10x1000x50")
+    if name == "random":
+        return (W.random_network_workload(dt=W.RANDOM_DT_1E4),
+                "seeded random mass-action network, 20 species x 40 reactions (orders 0-2, net "
+                "changes -2..2), rates log-uniform on [1e-3, 1]; 4096 theta x 1 trajectory x 512 "
+                "filter particles x 100 Gaussian observations (sigma 10, species 0 and 1) at the "
+                "interval where the median theta realises 1e4 SSA events per particle per "
+                "interval", "random20x40_4096x1x512x100")
+    raise SystemExit(f"unknown workload {name!r}")
 
 
 def main():
@@ -125,6 +156,7 @@ def main():
                          "kernels launched once per request)")
     ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--workload", default="telegraph", choices=["telegraph", "random"])
     ap.add_argument("--graph", action="store_true",
                     help="replay the step's launch sequence as a captured HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -151,7 +183,7 @@ def main():
     from paper_1606_08281_amd import workloads as W
 
     torch.cuda.set_device(0)
-    wl = W.telegraph_workload()
+    wl, wl_desc, wl_tag = workload(args.workload)
     net = lik.Network(wl.net.orders, wl.net.stoich)
     db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
                          wl.n_particles, precision=args.precision, kernel=args.kernel,
@@ -228,13 +260,17 @@ def main():
 
     # HBM bytes per launch from the committed rocprofv3 counter summary of
     # this kernel and configuration; null once the kernel sources differ.
-    flow = tuning.get("schedule", 0) == 1
+    # The schedule that ran: the flow schedule makes one propagation launch
+    # per step (the library takes the per-interval one where the flow
+    # kernel's occupancy is too low, whatever the tuning asks for).
+    flow = tm["propagate_launches"] == args.steps and tuning.get("schedule", 0) == 1
     kname = "lik_flow_spec" if flow else "lik_propagate_spec"
+    fp = "fp64" if args.precision == 0 else "fp32mixed"
     traffic = None
-    if (args.precision == 0 and args.kernel in (0, 2) and not args.tuning and not args.autotune):
+    if args.kernel in (0, 2) and not args.tuning and not args.autotune:
         from paper_1606_08281_amd import profsum
-        rec = profsum.read_traffic(os.path.join(
-            ROOT, "profiles", f"{kname}_traffic_telegraph_1024x10x1000x50_fp64.txt"))
+        rec = profsum.read_traffic(os.path.join(ROOT, "profiles",
+                                                f"{kname}_traffic_{wl_tag}_{fp}.txt"))
         if rec is not None:
             traffic = float(rec["hbm_bytes_per_launch"])
 
@@ -244,14 +280,14 @@ def main():
     # kernel, configuration and sources), else the model count
     ope, ope_basis = model_ope, "model count at measured instruction costs (no counter record " \
                                 "matches the current kernel sources)"
-    if args.precision == 0 and args.kernel in (0, 2) and not args.tuning and not args.autotune:
+    if args.kernel in (0, 2) and not args.tuning and not args.autotune:
         from paper_1606_08281_amd import profsum
-        rec = profsum.read_record(os.path.join(
-            ROOT, "profiles", f"{kname}_valu_telegraph_1024x10x1000x50_fp64.txt"))
+        rec_name = f"{kname}_valu_{wl_tag}_{fp}.txt"
+        rec = profsum.read_record(os.path.join(ROOT, "profiles", rec_name))
         if rec is not None:
             ope = float(rec["lane_slots_per_event"])
             ope_basis = ("measured: SQ_THREAD_CYCLES_VALU / SSA events of this kernel on these "
-                         "sources (profiles/" + f"{kname}_valu_telegraph_1024x10x1000x50_fp64.txt)")
+                         "sources (profiles/" + rec_name + ")")
     prop_s = tm["propagate_ms"] / 1e3
     # A replayed graph records no per-kernel events: its roofline is taken
     # over the whole step instead (a lower bound for the kernel's).
@@ -275,9 +311,7 @@ def main():
         "dtype": "f64" if args.precision == 0 else "f32-mixed (f64 clock/weights)",
         "data": "synthetic",
         "config": {
-            "workload": "telegraph gene expression, 6 mass-action rates log-uniform over two "
-                        "decades; 1024 theta x 10 trajectories x 1000 filter particles x 50 "
-                        "log-normal observations (sigma 0.1)",
+            "workload": wl_desc,
             "n_theta": wl.n_theta, "n_traj": wl.n_traj, "n_particles": wl.n_particles,
             "n_obs": len(wl.trajectories[0]["t_obs"]), "precision": args.precision,
             "kernel": ["auto", "generic", "specialised"][args.kernel],
@@ -323,7 +357,8 @@ def main():
         out["serving"]["wall_s"] = time.perf_counter() - t_s0
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", flush=True, file=sys.stderr)
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = (cpu_baseline(wl, per_call=1, t_sub=10) if args.workload == "random"
+                               else cpu_baseline(wl))
     print(json.dumps(out), flush=True)
 
 

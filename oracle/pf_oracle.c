@@ -427,8 +427,42 @@ static int bad_theta(const orc_problem *P, const double *c)
     return 0;
 }
 
+/* Simulation of particles j0 .. j1-1 over one interval (the "Simulate" step):
+ * each particle runs on its own state and stream, so the particles of an
+ * interval may be split between threads; the interval's events are their
+ * sum and its status their largest. */
+typedef struct {
+    const orc_problem *P;
+    const double *c;
+    int32_t *x;
+    double t_start, t_end;
+    uint32_t c2, theta_id;
+    int j0, j1;
+    uint64_t events;
+    int worst;
+} orc_span;
+
+static void *simulate_span(void *arg)
+{
+    orc_span *s = (orc_span *)arg;
+    int U = s->P->n_species;
+    s->events = 0;
+    s->worst = ORC_OK;
+    for (int j = s->j0; j < s->j1; ++j) {
+        int st;
+        int32_t *xj = s->x + (size_t)j * U;
+        s->events += ssa_interval(s->P, s->c, xj, s->t_start, s->t_end, (uint32_t)j, s->c2,
+                                  s->theta_id, &st);
+        for (int u = 0; u < U; ++u)
+            if (xj[u] > ORC_COUNT_LIMIT) st = st > ORC_COUNT_OVERFLOW ? st : ORC_COUNT_OVERFLOW;
+        if (st > s->worst) s->worst = st;
+    }
+    return NULL;
+}
+
 static int run_filter(const orc_problem *P, int i, int m, double *ll_out,
-                      uint64_t *events_out, int32_t *final_state, orc_trace *tr)
+                      uint64_t *events_out, int32_t *final_state, orc_trace *tr,
+                      int threads)
 {
     int U = P->n_species, H = P->n_particles;
     const double *c = P->theta + (size_t)i * P->n_reactions;
@@ -463,17 +497,30 @@ static int run_filter(const orc_problem *P, int i, int m, double *ll_out,
         } else {
             for (int j = 0; j < H; ++j) anc[j] = j;
         }
-        /* 2. simulate every particle forward to the observation time */
+        /* 2. simulate every particle forward to the observation time
+         *    (in `threads` spans of consecutive particles) */
         double t_end = P->t_obs[first + t];
         int worst = ORC_OK;
-        for (int j = 0; j < H; ++j) {
-            int st;
-            int32_t *xj = x + (size_t)j * U;
-            events += ssa_interval(P, c, xj, t_prev, t_end, (uint32_t)j,
-                                   ((uint32_t)m << 16) | (uint32_t)t, theta_id, &st);
-            for (int u = 0; u < U; ++u)
-                if (xj[u] > ORC_COUNT_LIMIT) st = st > ORC_COUNT_OVERFLOW ? st : ORC_COUNT_OVERFLOW;
-            if (st > worst) worst = st;
+        int nspan = threads < H ? threads : H;
+        orc_span span[64];
+        pthread_t th[64];
+        for (int k = 0; k < nspan; ++k) {
+            span[k].P = P;
+            span[k].c = c;
+            span[k].x = x;
+            span[k].t_start = t_prev;
+            span[k].t_end = t_end;
+            span[k].c2 = ((uint32_t)m << 16) | (uint32_t)t;
+            span[k].theta_id = theta_id;
+            span[k].j0 = (int)(((int64_t)H * k) / nspan);
+            span[k].j1 = (int)(((int64_t)H * (k + 1)) / nspan);
+        }
+        for (int k = 1; k < nspan; ++k) pthread_create(&th[k], NULL, simulate_span, &span[k]);
+        simulate_span(&span[0]);
+        for (int k = 1; k < nspan; ++k) pthread_join(th[k], NULL);
+        for (int k = 0; k < nspan; ++k) {
+            events += span[k].events;
+            if (span[k].worst > worst) worst = span[k].worst;
         }
         if (worst != ORC_OK) { status = worst; break; }
         /* 3. weight */
@@ -520,6 +567,7 @@ static int run_filter(const orc_problem *P, int i, int m, double *ll_out,
 typedef struct {
     const orc_problem *P;
     int next;
+    int inner;       /* threads per filter for its particles */
     pthread_mutex_t lock;
     double *fll;
     uint64_t *fev;
@@ -540,7 +588,7 @@ static void *worker(void *arg)
         if (f >= F) break;
         int i = f / P->n_traj, m = f % P->n_traj;
         b->fst[f] = run_filter(P, i, m, &b->fll[f], &b->fev[f],
-                               b->final_state ? b->final_state + per * f : NULL, NULL);
+                               b->final_state ? b->final_state + per * f : NULL, NULL, b->inner);
     }
     return NULL;
 }
@@ -564,9 +612,18 @@ int orc_eval(const orc_problem *P, int nthreads, double *loglik, int32_t *status
     b.final_state = final_state;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
+    /* fewer filters than threads: the spare threads share each filter's
+     * particles (at most 64 per filter) */
+    int outer = nthreads;
+    b.inner = 1;
+    if (F > 0 && F < nthreads) {
+        outer = F;
+        b.inner = nthreads / F;
+        if (b.inner > 64) b.inner = 64;
+    }
     pthread_t th[256];
-    for (int k = 0; k < nthreads; ++k) pthread_create(&th[k], NULL, worker, &b);
-    for (int k = 0; k < nthreads; ++k) pthread_join(th[k], NULL);
+    for (int k = 0; k < outer; ++k) pthread_create(&th[k], NULL, worker, &b);
+    for (int k = 0; k < outer; ++k) pthread_join(th[k], NULL);
     for (int i = 0; i < P->n_theta; ++i) {
         double s = 0.0;
         int32_t st = ORC_OK;
@@ -590,7 +647,7 @@ int orc_trace_filter(const orc_problem *P, int i, int m, int32_t *states, double
                      int32_t *ancestors, double *ll_inc, double *ll_out, uint64_t *events_out)
 {
     orc_trace tr = {states, logw, ancestors, ll_inc};
-    return run_filter(P, i, m, ll_out, events_out, NULL, &tr);
+    return run_filter(P, i, m, ll_out, events_out, NULL, &tr, 1);
 }
 
 /* Plain SSA paths (no observations): n_paths particles from x0 over

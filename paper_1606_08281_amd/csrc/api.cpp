@@ -362,6 +362,7 @@ size_t lik_workspace_size(lik_network_t net, int32_t n_theta, int32_t n_traj,
     b += align256(F * (Hp / 64) * 4);         // items
     b += align256(kMaxGroups * 4);            // item_count
     b += align256(kMaxGroups * 4);            // item_cursor
+    b += 2 * align256(kMaxGroups * kCostKeys * 4) + align256(2 * 4);  // ordering passes
     b += align256((size_t)flow_ring_capacity(F, Hp / 64) * 8 * kFlowRings);  // flow rings
     b += align256(F * 4);                     // flow: items left per slot
     b += align256(kCtlWords * 4);             // flow: control words
@@ -412,6 +413,9 @@ EngineLayout carve_engine(char *p, size_t slots, size_t items, size_t state_byte
     L.e.items = (uint32_t *)take(items * 4);
     L.e.item_count = (uint32_t *)take(kMaxGroups * 4);
     L.e.item_cursor = (uint32_t *)take(kMaxGroups * 4);
+    L.e.order_count = (uint32_t *)take(kMaxGroups * kCostKeys * 4);
+    L.e.order_pos = (uint32_t *)take(kMaxGroups * kCostKeys * 4);
+    L.e.order_ctl = (uint32_t *)take(2 * 4);
     memset(&L.fa, 0, sizeof(L.fa));
     L.fa.ring = (uint64_t *)take((size_t)ring_capacity * 8 * kFlowRings);
     L.fa.remaining = (uint32_t *)take(slots * 4);
@@ -555,6 +559,7 @@ int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts
     L.e.priority = net->tuning.priority;
     L.e.pool_min_items = (uint32_t)net->tuning.items_per_cu * compute_units();
     L.e.h_max = H;
+    L.e.pool_chunks = (uint32_t)std::min<size_t>(F * nchunk, 0xFFFFFFFFu);
 
     const int precision = opts ? opts->precision : LIK_FP64;
     const int variant = opts ? opts->kernel : LIK_KERNEL_AUTO;
@@ -665,6 +670,8 @@ int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts
             e = launch_flow_check(L.e, L.fa, st);
             if (e != hipSuccess) return hip_fail(e, "flow check launch");
         } else {
+            e = launch_order_reset(L.e, st);
+            if (e != hipSuccess) return hip_fail(e, "order reset launch");
             for (int t = 0; t < t_max; ++t) {
                 e = engine_iteration(L.e, &G, 1, st, timed);
                 if (e != hipSuccess) return hip_fail(e, "iteration launch");

@@ -121,8 +121,8 @@ void fill_reactant_tables(RequestArgs &r, const int32_t *kind, const int32_t *s1
 // order: the pool size of each slot, and a counting sort of the active slots
 // over (group, duration key): the expected events per lane of the slot's
 // work items (expected events per particle times the groups per pool), in
-// quarter octaves, longest first.  Order inside a key is arbitrary: it only
-// changes which wavefront starts first, never a result.
+// quarter octaves, longest first.  Order inside a key is arbitrary (atomics
+// decide it): it only changes which wavefront starts first, never a result.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int duration_key(uint64_t c) {
     if (c == 0) return kCostKeys - 1;
@@ -133,63 +133,84 @@ __device__ __forceinline__ int duration_key(uint64_t c) {
     return 4 * (32 - b) + (3 - frac);  // 0 = longest
 }
 
-__global__ __launch_bounds__(1024) void k_order(EngineArgs e) {
+// Three passes over the slots, each a grid of kOrderBlock-slot blocks:
+// count (items per (group, key) and the most expected events per particle),
+// scan (one block: first positions of every (group, key), per-group totals),
+// place (each slot takes its positions with one atomic and writes its items).
+// Pool sizes are capped by g_par = pool_chunks / pool_min_items, with
+// pool_chunks the host's count of groups of 64 particles over the slots that
+// may be active, so that a small iteration still spreads its particles over
+// as many wavefronts as it can.
+__device__ __forceinline__ int order_gpar(const EngineArgs &e) {
+    return (int)max(1u, e.pool_chunks / max(e.pool_min_items, 1u));
+}
+
+__global__ __launch_bounds__(kOrderBlock) void k_order_count(EngineArgs e) {
     __shared__ uint32_t hist[kMaxGroups * kCostKeys];
-    __shared__ uint32_t max_per;  // most expected events per particle of any slot
-    __shared__ uint32_t chunks;   // groups of 64 particles over all active slots
+    __shared__ uint32_t max_per;
     for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x) hist[k] = 0;
-    if (threadIdx.x == 0) {
-        max_per = 0;
-        chunks = 0;
-    }
-    if (threadIdx.x < kMaxGroups) e.item_cursor[threadIdx.x] = 0;
+    if (threadIdx.x == 0) max_per = 0;
     __syncthreads();
-    for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x)
-        if (slot_active(e, f)) atomicAdd(&chunks, (uint32_t)(e.desc[f].Hp >> 6));
-    __syncthreads();
-    // Pools only when the iteration has work to spare: at most
-    // chunks / pool_min_items groups per pool, so that a small batch still
-    // spreads its particles over as many wavefronts as it can.
-    const int g_par = (int)max(1u, chunks / max(e.pool_min_items, 1u));
-    for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x) {
-        if (!slot_active(e, f)) continue;
+    const int f = e.f_lo + (int)(blockIdx.x * kOrderBlock + threadIdx.x);
+    if (f < e.f_hi && slot_active(e, f)) {
         const uint32_t c = e.cost[f];
         const int nchunk = e.desc[f].Hp >> 6;
-        const int g = pool_size(e, f, c, g_par);
+        const int g = pool_size(e, f, c, order_gpar(e));
         const int key = duration_key((uint64_t)(c / (uint32_t)e.desc[f].H) * (uint64_t)g);
         atomicAdd(&hist[e.desc[f].group * kCostKeys + key], (uint32_t)((nchunk + g - 1) / g));
         atomicMax(&max_per, c / (uint32_t)e.desc[f].H);
     }
     __syncthreads();
-    if (threadIdx.x < kMaxGroups) {
-        const int g = threadIdx.x;
+    for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x)
+        if (hist[k]) atomicAdd(&e.order_count[k], hist[k]);
+    if (threadIdx.x == 0 && max_per) atomicMax(&e.order_ctl[0], max_per);
+}
+
+// One block: exclusive scan per group in key order (longest first), from the
+// group's first item; leaves the counts zero for the next iteration.
+__global__ __launch_bounds__(64) void k_order_scan(EngineArgs e) {
+    const int g = threadIdx.x;
+    if (g < kMaxGroups) {
         uint32_t run = e.group_off[g];
         for (int k = 0; k < kCostKeys; ++k) {
-            const uint32_t h = hist[g * kCostKeys + k];
-            hist[g * kCostKeys + k] = run;
+            const uint32_t h = e.order_count[g * kCostKeys + k];
+            e.order_pos[g * kCostKeys + k] = run;
+            e.order_count[g * kCostKeys + k] = 0u;
             run += h;
         }
         e.item_count[g] = run - e.group_off[g];
+        e.item_cursor[g] = 0;
     }
-    __syncthreads();
-    for (int f = e.f_lo + (int)threadIdx.x; f < e.f_hi; f += blockDim.x) {
-        if (!slot_active(e, f)) continue;
-        const uint32_t c = e.cost[f];
-        const int nchunk = e.desc[f].Hp >> 6;
-        const int g = pool_size(e, f, c, g_par);
-        const int key = duration_key((uint64_t)(c / (uint32_t)e.desc[f].H) * (uint64_t)g);
-        const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
-        const uint32_t pos = atomicAdd(&hist[e.desc[f].group * kCostKeys + key], n_items);
-        for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);
-        // Wavefront priority: the slots whose particles are expected to need
-        // the most events are the ones the iteration waits for; their
-        // wavefronts issue first on a SIMD they share with lighter ones.
-        const uint32_t per = c / (uint32_t)e.desc[f].H;
-        int prio = 0;
-        if (e.priority && per > 0)
-            prio = (uint64_t)per * 4u >= max_per ? 3 : (uint64_t)per * 32u >= max_per ? 1 : 0;
-        e.pool[f] = (uint8_t)((prio << 6) | (g - 1));
+    if (threadIdx.x == 0) {
+        e.order_ctl[1] = e.order_ctl[0];
+        e.order_ctl[0] = 0u;
     }
+}
+
+__global__ __launch_bounds__(kOrderBlock) void k_order_place(EngineArgs e) {
+    const int f = e.f_lo + (int)(blockIdx.x * kOrderBlock + threadIdx.x);
+    if (f >= e.f_hi || !slot_active(e, f)) return;
+    const uint32_t c = e.cost[f];
+    const int nchunk = e.desc[f].Hp >> 6;
+    const int g = pool_size(e, f, c, order_gpar(e));  // as in the counting pass
+    const int key = duration_key((uint64_t)(c / (uint32_t)e.desc[f].H) * (uint64_t)g);
+    const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
+    const uint32_t pos = atomicAdd(&e.order_pos[e.desc[f].group * kCostKeys + key], n_items);
+    for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);
+    // Wavefront priority: the slots whose particles are expected to need
+    // the most events are the ones the iteration waits for; their
+    // wavefronts issue first on a SIMD they share with lighter ones.
+    const uint32_t max_per = e.order_ctl[1];
+    const uint32_t per = c / (uint32_t)e.desc[f].H;
+    int prio = 0;
+    if (e.priority && per > 0)
+        prio = (uint64_t)per * 4u >= max_per ? 3 : (uint64_t)per * 32u >= max_per ? 1 : 0;
+    e.pool[f] = (uint8_t)((prio << 6) | (g - 1));
+}
+
+__global__ void k_order_reset(EngineArgs e) {
+    for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x) e.order_count[k] = 0u;
+    if (threadIdx.x < 2) e.order_ctl[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -488,7 +509,16 @@ hipError_t launch_stop(const EngineArgs &e, int32_t base, int32_t F, hipStream_t
 }
 
 hipError_t launch_order(const EngineArgs &e, hipStream_t s) {
-    hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, e);
+    const int F = e.f_hi - e.f_lo;
+    const unsigned blocks = (unsigned)((F + kOrderBlock - 1) / kOrderBlock);
+    if (blocks) hipLaunchKernelGGL(k_order_count, dim3(blocks), dim3(kOrderBlock), 0, s, e);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, e);
+    if (blocks) hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(kOrderBlock), 0, s, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_order_reset(const EngineArgs &e, hipStream_t s) {
+    hipLaunchKernelGGL(k_order_reset, dim3(1), dim3(256), 0, s, e);
     return hipGetLastError();
 }
 

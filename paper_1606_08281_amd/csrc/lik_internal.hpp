@@ -89,6 +89,13 @@ struct EngineArgs {
     uint32_t *items;          // propagation work items (slot << 6 | chunk), grouped
     uint32_t *item_count;     // [kMaxGroups] items written per group
     uint32_t *item_cursor;    // [kMaxGroups] next item to take (persistent kernels)
+    // Ordering of an iteration's work (three passes: count, scan, place).
+    uint32_t *order_count;    // [kMaxGroups * kCostKeys] items per (group, duration key);
+                              // zero between iterations
+    uint32_t *order_pos;      // [kMaxGroups * kCostKeys] next position of each (group, key)
+    uint32_t *order_ctl;      // [2]: most expected events per particle of any slot (zero
+                              // between iterations), and its copy for the placing pass
+    uint32_t pool_chunks;     // groups of 64 particles over the slots that may be active
     int32_t f_lo, f_hi;       // slot range that may hold active filters
     // Pool size G per slot: G = clamp(pool_events / (events per particle in
     // the last interval), pool_min, pool_max); pool_first for the first one.
@@ -148,6 +155,8 @@ __host__ __device__ inline const FlowArgs *flow_args_copy(uint32_t *ctl) {
 #ifndef __HIPCC_RTC__
 // Host-side launchers (kernels.hip).
 hipError_t launch_order(const EngineArgs &e, hipStream_t s);
+hipError_t launch_order_reset(const EngineArgs &e, hipStream_t s);  // before a batch's first
+constexpr int kOrderBlock = 256;  // slots per block of the ordering passes
 hipError_t launch_propagate(const EngineArgs &e, int group, unsigned n_items, const void *net,
                             int umax, int rmax, int precision, bool persistent, hipStream_t s);
 constexpr int kPersistentMaxR = 16;  // rates per lane in registers: small networks only

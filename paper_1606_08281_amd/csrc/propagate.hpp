@@ -63,6 +63,52 @@ __device__ __forceinline__ void select_reaction(const NetT &net, const Real *S, 
     }
 }
 
+// Networks of more than kRegRatesMax reactions keep their rates and net
+// changes in the wavefront's LDS instead of registers: 40 binary64 rates
+// would overflow the scalar registers (each spilled rate costs a vector
+// read-back per event).  The rates are read at a wave-uniform address at
+// every event; the reaction that fires is found as an index (the number of
+// running sums not above the target) and its net changes are read from a
+// table of signed bytes, ceil(U / 4) words per reaction padded to whole
+// 16-byte rows.
+constexpr int kRegRatesMax = 16;
+template <int RMAX>
+struct LdsNet {
+    static constexpr bool on = RMAX > kRegRatesMax;
+};
+template <int UMAX>
+__host__ __device__ constexpr int nu_row_words() {
+    return ((UMAX + 3) / 4 + 3) / 4 * 4;
+}
+
+// Index of the reaction that fires, r* = min{r : S_r > target}, else R - 1
+// (no sum above a NaN or infinite target), as select_reaction picks it.
+template <class NetT, int RMAX, class Real>
+__device__ __forceinline__ int select_index(const NetT &net, const Real *S, Real target) {
+    int rs = net.R - 1;
+#pragma unroll
+    for (int r = RMAX - 2; r >= 0; --r)
+        if (r < net.R - 1) rs = (S[r] > target) ? r : rs;
+    return rs;
+}
+
+// x += the net changes of reaction rs, read from its row of the byte table.
+template <int UMAX>
+__device__ __forceinline__ void apply_row(int U, const uint32_t *tab, int rs, int *x) {
+    constexpr int kRow = nu_row_words<UMAX>();
+    const uint4 *row = reinterpret_cast<const uint4 *>(tab + rs * kRow);
+#pragma unroll
+    for (int q = 0; q < kRow / 4; ++q) {
+        const uint4 v = row[q];
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int u = 16 * q + k;
+            if (u < UMAX && u < U) x[u] += (int)(signed char)(w4[k >> 2] >> (8 * (k & 3)));
+        }
+    }
+}
+
 template <int UMAX, int W>
 __device__ __forceinline__ void apply_change(int U, const uint32_t *sel, int *x) {
     if (nu_bytes(U)) {
@@ -180,11 +226,15 @@ __device__ __forceinline__ EventDraw<PREC> event_draw_uniform(uint32_t n, uint32
 // draw() gives the event's EventDraw (for the particle's current n).
 // a0_end keeps the last total propensity (a scheduling estimate, stored as
 // binary32 when the particle is).
+// nu_tab: the byte table of net changes in LDS (large networks), else null.
 template <class NetT, int UMAX, int RMAX, int W, int PREC, class Real, class DrawFn>
 __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x, Real *S,
                                           double t_end, uint32_t event_cap, double &clock,
                                           uint32_t &n, int &st, Real &a0_end, bool &have,
-                                          DrawFn &&draw) {
+                                          const uint32_t *nu_tab, DrawFn &&draw) {
+    // large networks: the rates are read from LDS again at every event (the
+    // compiler would otherwise keep all of them in vector registers)
+    if (LdsNet<RMAX>::on) asm volatile("" ::: "memory");
     const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
     a0_end = s;
     if (!(s > (Real)0)) {
@@ -206,9 +256,13 @@ __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x
         if (clock + tau > t_end) {
             have = false;  // the pending event is discarded
         } else {
-            uint32_t sel[W];
-            select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
-            apply_change<UMAX, W>(net.U, sel, x);
+            if (LdsNet<RMAX>::on) {
+                apply_row<UMAX>(net.U, nu_tab, select_index<NetT, RMAX, Real>(net, S, target), x);
+            } else {
+                uint32_t sel[W];
+                select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
+                apply_change<UMAX, W>(net.U, sel, x);
+            }
             clock = clock + tau;
             n = n + 1;
         }
@@ -270,10 +324,38 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     const int refill_min = e.refill_min;
 
     using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
-    // Rates are the same for the whole wavefront: kept in scalar registers.
-    Real c[RMAX];
+    // Rates are the same for the whole wavefront: kept in scalar registers,
+    // or for a large network in LDS with its net-change table.
+    constexpr bool kLds = LdsNet<RMAX>::on;
+    constexpr int kRow = nu_row_words<UMAX>();
+    __shared__ __attribute__((aligned(16))) Real c_lds[kLds ? RMAX : 1];
+    __shared__ __attribute__((aligned(16))) uint32_t nu_lds[kLds ? RMAX * kRow : 1];
+    Real c_reg[kLds ? 1 : RMAX];
+    if (kLds) {
+        for (int r = lane; r < R; r += kPropBlock) c_lds[r] = (Real)d.theta[r];
+        // net changes as signed bytes, from the network's packed fields
+        for (int q = lane; q < R * kRow; q += kPropBlock) {
+            const int r = q / kRow, w = q - r * kRow;
+            uint32_t word = 0u;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) c[r] = (r < R) ? wave_uniform((Real)d.theta[r]) : (Real)0;
+            for (int k = 0; k < 4; ++k) {
+                const int u = 4 * w + k;
+                int v = 0;
+                if (u < U)
+                    v = nu_bytes(U) ? (int)(signed char)(net.nu[r][0] >> (8 * u))
+                                    : __builtin_amdgcn_sbfe(net.nu[r][u >> 3], 4 * (u & 7), 4);
+                word |= ((uint32_t)v & 0xFFu) << (8 * k);
+            }
+            nu_lds[q] = word;
+        }
+        __syncthreads();  // the workgroup is this one wavefront
+    } else {
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+            c_reg[r] = (r < R) ? wave_uniform((Real)d.theta[r]) : (Real)0;
+    }
+    const Real *c = kLds ? c_lds : c_reg;
+    const uint32_t *nu_tab = kLds ? nu_lds : nullptr;
 
     // A pool of more than 64 particles first stages its ancestors' counts in
     // LDS ([u][particle - p0]); a lane taking a new particle reads them from
@@ -425,7 +507,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     for (;;) {
         if (have)
             ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
-                net, c, x, S, t_end, event_cap, clock, n, st, a0_end, have,
+                net, c, x, S, t_end, event_cap, clock, n, st, a0_end, have, nu_tab,
                 [&] { return event_draw_uniform<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
         // Once at least refill_min lanes are idle (or all are), the idle
         // lanes store what they hold and take the next particles of the
@@ -497,7 +579,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
         for (int i = 0; i < D; ++i) {
             if (have)
                 ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(net, c, x, S, t_end, event_cap, clock,
-                                                           n, st, a0_end, have,
+                                                           n, st, a0_end, have, nu_tab,
                                                            [&] { return dbuf[slot + i]; });
             if (__ballot(have) == 0ull) break;
         }
@@ -593,6 +675,7 @@ __device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const 
         if (have)
             ssa_event<NetT, UMAX, RMAX, W, PREC, Real>(
                 net, c, x, S, t_end, cap, clock, n, st, a0_end, have,
+                static_cast<const uint32_t *>(nullptr),
                 [&] { return event_draw<PREC>(n, (uint32_t)j, c2, c3, k0, k1); });
         uint64_t idle = __ballot(!have);
         const int n_idle = (int)__popcll(idle);

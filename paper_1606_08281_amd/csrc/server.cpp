@@ -436,6 +436,7 @@ void worker_main(lik_server *S) {
         }
         S->e.f_lo = 0;
         S->e.f_hi = (int32_t)S->slots.high_water();
+        S->e.pool_chunks = off;  // groups of 64 particles of the slots still running
         if (engine_iteration(S->e, launches, kMaxGroups, S->stream) != hipSuccess)
             S->worker_error = "iteration launch failed";
         S->n_iterations += 1;
@@ -494,7 +495,8 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
                          align256(slots) +
                          2 * align256(slots * 8) + align256(slots * 64 * 4) +
                          2 * align256(kMaxGroups * 4) + align256(slots * 8) +
-                         align256(slots * 4);
+                         align256(slots * 4) + 2 * align256(kMaxGroups * kCostKeys * 4) +
+                         align256(2 * 4);
     hipError_t err = hipMalloc((void **)&S->dev_base, table + o.arena_bytes + 256);
     if (err != hipSuccess) return fail(LIK_ENOMEM, "device arena allocation failed");
     const size_t pinned_bytes = o.staging_bytes + slots * 12 + 512;
@@ -522,6 +524,9 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->e.items = (uint32_t *)take(slots * 64 * 4);
     S->e.item_count = (uint32_t *)take(kMaxGroups * 4);
     S->e.item_cursor = (uint32_t *)take(kMaxGroups * 4);
+    S->e.order_count = (uint32_t *)take(kMaxGroups * kCostKeys * 4);
+    S->e.order_pos = (uint32_t *)take(kMaxGroups * kCostKeys * 4);
+    S->e.order_ctl = (uint32_t *)take(2 * 4);
     S->dev_loglik = (double *)take(slots * 8);
     S->dev_status = (int32_t *)take(slots * 4);
     S->arena = p;
@@ -542,8 +547,13 @@ int lik_server_create(const lik_server_opts *opts, lik_server_t *out) {
     S->pmem.init(o.staging_bytes, 256);
     // every slot starts inactive (stopped), so stale slots are never ordered
     std::vector<uint32_t> stopped(slots, kFlagStopped);
+    // the ordering passes' counts start at zero (each iteration leaves them so)
+    std::vector<uint32_t> zeros(kMaxGroups * kCostKeys + 2, 0u);
     if (hipStreamCreate(&S->stream) != hipSuccess ||
-        hipMemcpy(S->e.fflags, stopped.data(), slots * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(S->e.fflags, stopped.data(), slots * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(S->e.order_count, zeros.data(), kMaxGroups * kCostKeys * 4,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(S->e.order_ctl, zeros.data(), 2 * 4, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipHostFree(S->pinned);
         (void)hipFree(S->dev_base);
         return fail(LIK_EDEVICE, "stream or slot initialisation failed");

@@ -84,7 +84,8 @@ def _kind(name):
         return "lik_propagate_spec" if "spec" in name else "lik::k_propagate"
     if "lik_flow_spec" in name:
         return "lik_flow_spec"
-    for k in ("k_flow_init", "k_flow_seed", "k_flow_check", "k_flow", "k_order", "k_weigh",
+    for k in ("k_flow_init", "k_flow_seed", "k_flow_check", "k_flow", "k_order_count",
+              "k_order_scan", "k_order_place", "k_order_reset", "k_order", "k_weigh",
               "k_admit", "k_finish", "k_aux_filters", "k_aux_state"):
         if k in name:
             return "lik::" + k
@@ -213,7 +214,8 @@ def main():
              ("One bench step = k_admit, the flow set-up kernels, one lik_flow_spec launch (every "
               "interval: SSA work items and each filter's weighing) and k_finish."
               if a.kernel == "lik_flow_spec" else
-              "Engine iteration = k_order + lik_propagate_spec + k_weigh; 50 iterations per "
+              "Engine iteration = k_order_count + k_order_scan + k_order_place + "
+              "lik_propagate_spec + k_weigh; 50 iterations per "
               "bench step."), "", "Commands (repository root on one MI355X, `R` = its path):", "",
              "```"] + open(a.commands).read().strip().splitlines() + ["```", "",
              "Kernel statistics (rocprofv3 --kernel-trace --stats):", "",
@@ -258,7 +260,8 @@ def main():
     if util:
         lines += ["", "Utilisation counters (mean per dispatch):", ""]
         for (k, c), (v, n) in sorted(util.items()):
-            if k in ("lik_propagate_spec", "lik_flow_spec", "lik::k_weigh", "lik::k_order"):
+            if k in ("lik_propagate_spec", "lik_flow_spec", "lik::k_weigh", "lik::k_order_count",
+                     "lik::k_order_scan", "lik::k_order_place"):
                 lines.append(f"- {k} {c}: {v:.2f} ({n} dispatches)")
     lines += ["", f"Kernel sources fingerprint (sha256): {sha}", ""]
     open(a.out, "w").write("\n".join(lines))

@@ -254,22 +254,73 @@ def tau_leap_path(net, c, x0, t_points, rng, n_sub=200):
     return out
 
 
-def random_network_workload(n_theta=4096, n_particles=512, n_obs=100, events_per_interval=1e4):
+def mean_field_path(net, c, x0, t_points):
+    """The network's rate equations dx/dt = sum_r nu_r c_r h_r(x) (mass-action
+    factors of continuous counts) from x0, solved by scipy's stiff LSODA, at
+    t_points: a deterministic synthetic data path where an exact stochastic
+    one is too slow to simulate (float64 [len(t_points), U], clipped at 0)."""
+    from scipy.integrate import solve_ivp
+    nu = net.stoich.astype(np.float64)
+
+    def rhs(_, x):
+        return (c * net.propensity_factor(np.maximum(x, 0.0))) @ nu
+
+    sol = solve_ivp(rhs, (0.0, float(t_points[-1])), np.asarray(x0, dtype=np.float64),
+                    method="LSODA", t_eval=np.asarray(t_points, dtype=np.float64),
+                    rtol=1e-7, atol=1e-6)
+    if not sol.success:
+        raise RuntimeError("mean-field data path: " + sol.message)
+    return np.maximum(sol.y.T, 0.0)
+
+
+def random_network_x0(net):
+    return np.random.Generator(np.random.PCG64(SEED_NET + 100)).poisson(100, net.U).astype(np.int32)
+
+
+def random_network_theta(net, n_theta):
+    return log_uniform(np.random.Generator(np.random.PCG64(SEED_THETA)),
+                       np.full(net.R, 1e-3), np.full(net.R, 1.0), n_theta)
+
+
+# Observation interval at which the median rate vector of the 20 x 40
+# network's prior realises 1e4 direct-method events per particle per interval
+# (tests/helpers/calibrate_random_interval.py: exact SSA paths of 256 prior
+# draws from x0 over 100 intervals; median 9,973, mean 11,673, p99 34,696
+# events per interval).  The network relaxes fast from x0, so this interval
+# is ~4,200 times the one at which the median rate vector's total propensity
+# at x0 gives 1e4 events.
+RANDOM_DT_1E4 = 2797.88
+
+
+def random_network_workload(n_theta=4096, n_particles=512, n_obs=100, events_per_interval=1e4,
+                            dt=None):
     """20 species / 40 reactions, x0 ~ Poisson(100) once, rates log-uniform on
-    [1e-3, 1]; the observation interval is set so that the median over the
-    drawn rate vectors of the total propensity at x0 times the interval is
-    `events_per_interval`; Gaussian noise sigma 10 on species 0 and 1."""
+    [1e-3, 1]; Gaussian noise sigma 10 on species 0 and 1.
+
+    dt None: the observation interval is set so that the median over the
+    drawn rate vectors of the total propensity *at x0* times the interval is
+    `events_per_interval` (the network then relaxes and realises far fewer,
+    ~36 events per particle per interval at 1e4); data from a tau-leaped path
+    at rates 10^-1.5.  dt given (RANDOM_DT_1E4 for ~1e4 realised events per
+    particle per interval): that interval, and data from the rate equations'
+    mean-field path at rates 10^-1.5 (tau-leaping is unstable at that
+    interval, and an exact path takes millions of events)."""
     net = random_network()
-    x0 = np.random.Generator(np.random.PCG64(SEED_NET + 100)).poisson(100, net.U).astype(np.int32)
-    theta = log_uniform(np.random.Generator(np.random.PCG64(SEED_THETA)),
-                        np.full(net.R, 1e-3), np.full(net.R, 1.0), n_theta)
-    a0 = np.array([(th * net.propensity_factor(x0)).sum() for th in theta])
-    dt = float(events_per_interval / np.median(a0))
-    t_obs = dt * np.arange(1, n_obs + 1, dtype=np.float64)
+    x0 = random_network_x0(net)
+    theta = random_network_theta(net, n_theta)
     truth = np.full(net.R, 10 ** -1.5)
-    rng = np.random.Generator(np.random.PCG64(SEED_DATA))
-    states = tau_leap_path(net, truth, x0, t_obs, rng, n_sub=20)
+    if dt is None:
+        a0 = np.array([(th * net.propensity_factor(x0)).sum() for th in theta])
+        dt = float(events_per_interval / np.median(a0))
+        t_obs = dt * np.arange(1, n_obs + 1, dtype=np.float64)
+        rng = np.random.Generator(np.random.PCG64(SEED_DATA))
+        states = tau_leap_path(net, truth, x0, t_obs, rng, n_sub=20)
+        name = "random-20x40"
+    else:
+        t_obs = float(dt) * np.arange(1, n_obs + 1, dtype=np.float64)
+        states = mean_field_path(net, truth, x0, t_obs)
+        name = "random-20x40-1e4"
     y = states[:, :2] + np.random.Generator(np.random.PCG64(SEED_NOISE)).normal(0, 10.0, (n_obs, 2))
     traj = {"t_obs": t_obs, "y": y, "t0": 0.0, "x0": x0, "x_true": states}
-    return Workload("random-20x40", net, OBS_GAUSSIAN, [0, 1], 10.0, theta, [traj],
+    return Workload(name, net, OBS_GAUSSIAN, [0, 1], 10.0, theta, [traj],
                     n_particles, truth=truth)

@@ -619,3 +619,41 @@ def test_random_network_full_batch_sampled(orc, precision):
     if precision:
         assert np.all(err <= FP32_ABS)
     assert np.all(st == 0) and np.all(np.isfinite(ll))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_random_network_1e4_events_full_batch_sampled(orc, precision):
+    # the 20-species, 40-reaction network at the interval where the median
+    # rate vector realises 1e4 SSA events per particle per interval
+    # (4096 theta x 512 particles x 100 observations, ~2.4e12 events), in the
+    # benchmark's launch configuration; two seeded rate vectors recomputed by
+    # the oracle at full size: statuses, event counts, final particle counts,
+    # log-likelihoods
+    import torch
+    from paper_1606_08281_amd import lik
+    wl = W.random_network_workload(dt=W.RANDOM_DT_1E4)
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    db = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories, wl.n_theta,
+                         wl.n_particles, precision=precision)
+    final = torch.empty((wl.n_theta, wl.net.U, wl.n_particles), dtype=torch.int32,
+                        device="cuda")
+    _say("random 20x40 at 1e4 events/interval, full batch 4096x512x100 precision", precision)
+    ll, st = db.run(torch.from_numpy(wl.theta).cuda(), wl.seed, final_state=final)
+    torch.cuda.synchronize()
+    ll, st = ll.cpu().numpy(), st.cpu().numpy()
+    events = db.events.cpu().numpy().astype(np.uint64)
+    idx = np.sort(np.random.default_rng(23).choice(wl.n_theta, 2, replace=False))
+    _say("oracle sample", idx.tolist(), "events", events[idx].tolist())
+    ref = _oracle(orc, wl, theta=wl.theta[idx], theta_ids=idx, precision=precision)
+    assert np.array_equal(st[idx], ref["status"])
+    assert np.array_equal(events[idx], ref["events"])
+    assert np.array_equal(final[torch.from_numpy(idx).cuda()].cpu().numpy(), ref["final_state"])
+    fin = np.isfinite(ref["loglik"])
+    err = np.abs(ll[idx][fin] - ref["loglik"][fin])
+    assert np.all(err <= REL * np.abs(ref["loglik"][fin]))
+    if precision:
+        assert np.all(err <= FP32_ABS)
+    # the batch realises ~1e4 events per particle per interval at its median
+    per = events.astype(np.float64) / (wl.n_particles * len(wl.trajectories[0]["t_obs"]))
+    assert 5e3 < np.median(per[st == 0]) < 2e4, np.median(per[st == 0])
+    assert np.mean(st == 0) > 0.99

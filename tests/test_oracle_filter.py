@@ -128,6 +128,16 @@ def test_theta_ids_subset_reproduces_batch(orc):
     # the thread count never changes a result
     one = orc.evaluate(problem_from(orc, wl), nthreads=1)
     assert np.array_equal(one["loglik"], full["loglik"])
+    # nor does sharing a filter's particles between threads (fewer filters
+    # than threads), in either precision, with a status in the mix
+    for prec in (0, 1):
+        th = np.vstack([wl.theta[:2], [[10.0, 0.1]]])
+        a = orc.evaluate(problem_from(orc, wl, theta=th, precision=prec, event_cap=40),
+                         nthreads=1, want_final_state=True)
+        b = orc.evaluate(problem_from(orc, wl, theta=th, precision=prec, event_cap=40),
+                         nthreads=16, want_final_state=True)
+        for k in ("loglik", "status", "events", "filter_ll", "final_state"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
 def test_statuses(orc):
