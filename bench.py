@@ -355,6 +355,12 @@ def main():
                                     log=lambda m: print("[bench] serving:", m, flush=True,
                                                         file=sys.stderr))
         out["serving"]["wall_s"] = time.perf_counter() - t_s0
+        print("[bench] uneven block: 8192 mixed requests in one persistent launch", flush=True,
+              file=sys.stderr)
+        t_u0 = time.perf_counter()
+        out["uneven"] = SB.uneven_block(log=lambda m: print("[bench] uneven:", m, flush=True,
+                                                            file=sys.stderr))
+        out["uneven"]["wall_s"] = time.perf_counter() - t_u0
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", flush=True, file=sys.stderr)
         out["cpu_baseline"] = (cpu_baseline(wl, per_call=1, t_sub=10) if args.workload == "random"

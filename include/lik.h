@@ -349,6 +349,53 @@ typedef struct lik_server_stats {
     uint64_t cancelled;                     /* requests withdrawn (cancelled or timed out) */
 } lik_server_stats;
 
+/*
+ * lik_eval_requests -- many requests evaluated together (each a lik_request:
+ * its own network, observation model, rate vectors, trajectories, particle
+ * count, seed and event cap; lik_request.timeout_us must be 0).  Every filter
+ * of every request is admitted in one launch; with the flow schedule
+ * (tuning->schedule = 1, the default) one persistent launch then runs every
+ * interval of every filter, each work item with its own network's
+ * propagation body (one kernel compiled for the set of networks, or the
+ * generic kernel), and one launch sums each request's trajectories.  Where
+ * the flow schedule does not qualify (large networks: too few resident
+ * wavefronts; 2^26 or more work items) the same filters advance in shared
+ * per-interval iterations.  Each request's results equal lik_eval_batch on
+ * its own inputs.  Synchronous; allocates and frees its device memory.
+ *   reqs [n_req] host; all of one precision; at most 16 distinct networks;
+ *     at most 2^26 filters (theta x trajectory pairs) in all.
+ *   tuning: work partitioning and schedule (NULL: the defaults).
+ *   kernel: LIK_KERNEL_* (AUTO: specialised when the batch amortises the
+ *     compile).
+ *   loglik_out [sum of n_theta] host: request k's values at offset
+ *     sum_{j<k} reqs[j].n_theta, as lik_eval_batch writes them; status_out
+ *     likewise, or NULL.
+ *   done_ms [n_req] host or NULL: device-clock time from the admission
+ *     launch to the finish of the request's last filter (for completion
+ *     percentiles; 0 if none of its filters ran).
+ * Returns LIK_EINVAL for an invalid request (the message names it),
+ * LIK_EUNSUPPORTED for more than 16 networks.
+ */
+int lik_eval_requests(const lik_request *reqs, int32_t n_req, const lik_tuning *tuning,
+                      int32_t kernel, double *loglik_out, int32_t *status_out, double *done_ms);
+
+/*
+ * lik_precompile_requests -- compile the flow kernel lik_eval_requests uses
+ * for this set of networks into the on-disk kernel cache (no GPU needed).
+ * nets: the distinct networks in the order they first appear in the
+ * requests; 1 to 16.  LIK_EDEVICE with the compiler log if compilation fails.
+ */
+int lik_precompile_requests(const lik_network_t *nets, int32_t n_nets, int32_t precision);
+
+/*
+ * lik_autotune_requests -- times lik_eval_requests on these requests for
+ * the fixed set of candidate tunings (particles per wavefront, pool
+ * thresholds, schedule) and writes the fastest to *chosen.  Results of
+ * every candidate are identical; the timing includes the calls' copies.
+ */
+int lik_autotune_requests(const lik_request *reqs, int32_t n_req, int32_t kernel,
+                          lik_tuning *chosen);
+
 /* Creates a server on the current device.  LIK_ENOMEM if the arena cannot be allocated. */
 int lik_server_create(const lik_server_opts *opts, lik_server_t *out);
 

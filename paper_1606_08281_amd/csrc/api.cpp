@@ -76,6 +76,27 @@ hipEvent_t timing_mark(hipStream_t s) {
 
 }  // namespace
 
+hipEvent_t lik::timing_begin(hipStream_t s) { return g_timing.enabled ? timing_mark(s) : nullptr; }
+
+void lik::timing_end_propagate(hipEvent_t begin, hipStream_t s) {
+    if (g_timing.enabled && begin) g_timing.prop.push_back({begin, timing_mark(s)});
+}
+
+const lik_tuning *lik::autotune_candidates(int *n) {
+    static const lik_tuning cands[] = {
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30},  // default: flow schedule
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 32000, 30},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 0, 30},      // flow, first come first served
+        {1, 4, 1024, 1, 1, 0, 160, 0, 1, 16000, 30},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 0, 16000, 30},  // one launch sequence per interval
+        {1, 4, 1024, 1, 1, 0, 160, 0, 0, 16000, 30},
+        {2, 6, 2048, 1, 1, 0, 160, 0, 0, 16000, 30},
+        {1, 1, 0, 1, 1, 0, 0, 0, 0, 16000, 30},       // one group of 64 particles per wavefront
+        {1, 1, 0, 1, 1, 0, 0, 1, 0, 16000, 30},       // persistent wavefronts (R <= 16)
+    };
+    *n = (int)(sizeof(cands) / sizeof(cands[0]));
+    return cands;
+}
 
 template <int RMAX, int W>
 static void fill_net(const lik_network &src, NetArgs<RMAX, W> &dst) {
@@ -201,17 +222,8 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         double *loglik_out, int32_t *status_out, void *workspace,
                         size_t workspace_bytes, void *stream, lik_tuning *chosen) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
-    static const lik_tuning cands[] = {
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30},  // default: flow schedule
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 32000, 30},
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 0, 30},      // flow, first come first served
-        {1, 4, 1024, 1, 1, 0, 160, 0, 1, 16000, 30},
-        {1, 6, 1536, 1, 1, 0, 160, 0, 0, 16000, 30},  // one launch sequence per interval
-        {1, 4, 1024, 1, 1, 0, 160, 0, 0, 16000, 30},
-        {2, 6, 2048, 1, 1, 0, 160, 0, 0, 16000, 30},
-        {1, 1, 0, 1, 1, 0, 0, 0, 0, 16000, 30},       // one group of 64 particles per wavefront
-        {1, 1, 0, 1, 1, 0, 0, 1, 0, 16000, 30},       // persistent wavefronts (R <= 16)
-    };
+    int n_cands = 0;
+    const lik_tuning *cands = autotune_candidates(&n_cands);
     const lik_tuning saved = net->tuning;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a = nullptr, b = nullptr;
@@ -226,7 +238,8 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
     rc = lik_eval_batch_device(net, obs, &o, n_theta, theta, data, obs_offsets_host, n_particles,
                                seed, loglik_out, status_out, nullptr, workspace, workspace_bytes,
                                stream);
-    for (const lik_tuning &c : cands) {
+    for (int ci = 0; ci < n_cands; ++ci) {
+        const lik_tuning &c = cands[ci];
         if (rc != LIK_OK) break;
         net->tuning = c;
         (void)hipEventRecord(a, s);

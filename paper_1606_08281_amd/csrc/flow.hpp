@@ -446,9 +446,11 @@ __device__ __forceinline__ const EngineArgs &reload_engine_args() {
     return *(const EngineArgs *)p;
 }
 
-template <class NetT, int UMAX, int RMAX, int W, int PREC>
-__device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa,
-                                         const NetT &net) {
+// run(item) runs one work item (the propagation of its pool); a launch over
+// several networks picks the item's network inside it.
+template <class RunItem>
+__device__ __forceinline__ void flow_run_with(const EngineArgs &e, const FlowArgs &fa,
+                                              RunItem &&run) {
     __shared__ double logy[LIK_MAX_OBSERVED];
     // the wavefronts beyond the batch's last item start after it is done
     if ((int)__builtin_amdgcn_readfirstlane(ctl_load(fa, kCtlFinished)) >= fa.n_slots) return;
@@ -474,7 +476,7 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t item = __builtin_amdgcn_readfirstlane((uint32_t)ent);
     const int f = (int)(item >> 6);
-    run_item<NetT, UMAX, RMAX, W, PREC>(e, net, item);
+    run(item);
 
     // release: this item's results before the filter's count goes down
     __threadfence();
@@ -504,11 +506,21 @@ __device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa
     } else {
         __threadfence();
         __syncthreads();
-        if (lane_id() == 0)
+        if (lane_id() == 0) {
+            if (ec.fdone) ec.fdone[f] = wall_clock64();
             __hip_atomic_fetch_add(&fa.ctl[kCtlFinished], 1u, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
+        }
         flow_unpark_some(ec, fa, lane_id());
     }
+}
+
+template <class NetT, int UMAX, int RMAX, int W, int PREC>
+__device__ __forceinline__ void flow_run(const EngineArgs &e, const FlowArgs &fa,
+                                         const NetT &net) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[item_lds_words<UMAX, RMAX, PREC>()];
+    flow_run_with(e, fa,
+                  [&](uint32_t item) { run_item<NetT, UMAX, RMAX, W, PREC>(e, net, item, lds); });
 }
 
 }  // namespace lik

@@ -69,6 +69,14 @@ hipFunction_t specialized_kernel(lik_network &net, int precision, std::string *e
 // current device, else nullptr; never compiles or loads (no allocation).
 hipFunction_t loaded_specialized_kernel(lik_network &net, int precision, int kind = kSpecItem);
 
+// The flow kernel for filters of several networks (group g = nets[g]), each
+// item running its network's specialised body; compiled with hipRTC (cached on
+// disk) and loaded once per device for the life of the process.
+std::string specialized_multi_source(const std::vector<lik_network *> &nets, int precision);
+hipFunction_t specialized_multi_kernel(const std::vector<lik_network *> &nets, int precision,
+                                       std::string *err);
+bool precompile_multi(const std::vector<lik_network *> &nets, int precision, std::string *err);
+
 // Compile (or find in the disk cache) without loading: needs no device.
 bool precompile_specialized(const lik_network &net, int precision, std::string *err);
 
@@ -77,6 +85,14 @@ void release_graphs(lik_network &net);
 
 // Release every module loaded for this network.
 void release_specialized(lik_network &net);
+
+// Kernel timing (lik_timing_enable): an event opening a propagation launch
+// (null while timing is off), and the one closing it.
+hipEvent_t timing_begin(hipStream_t s);
+void timing_end_propagate(hipEvent_t begin, hipStream_t s);
+
+// The fixed candidate tunings the autotuners time.
+const lik_tuning *autotune_candidates(int *n);
 
 // Error reporting (thread-local message for lik_last_error).
 int fail(int code, const std::string &msg);

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 #endif
 
 #include "devmath.hpp"
@@ -37,10 +39,9 @@ namespace lik {
 // round to infinity, and infinity times a zero mass-action factor is NaN) --
 // mark every slot of that theta BAD_THETA before any simulation.
 // ---------------------------------------------------------------------------
-__global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
-    const int F = r.n_theta * r.M;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= F) return;
+// Filter k of request r (theta k / M against trajectory k % M) into its slot.
+__device__ __forceinline__ void admit_one(FilterDesc *desc, const EngineArgs &e,
+                                          const RequestArgs &r, int k) {
     const int i = k / r.M;
     const int m = k - i * r.M;
     const int f = r.base + k;
@@ -82,6 +83,7 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
         if (r.precision == LIK_FP32_MIXED && isinf((float)c)) bad = true;
     }
     e.tcur[f] = 0;
+    if (e.fdone) e.fdone[f] = 0;
     e.fll[f] = bad ? __builtin_nan("") : 0.0;
     e.fstatus[f] = bad ? LIK_STATUS_BAD_THETA : LIK_STATUS_OK;
     e.fflags[f] = bad ? kFlagStopped : 0u;
@@ -106,6 +108,28 @@ __global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
     }
     const double expect = (double)r.H * a0 * (d.t_obs[0] - d.t0);
     e.cost[f] = !(expect > 0.0) ? 0u : expect >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)expect;
+}
+
+__global__ void k_admit(FilterDesc *desc, EngineArgs e, RequestArgs r) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < r.n_theta * r.M) admit_one(desc, e, r, k);
+}
+
+// Every request of a multi-request batch: thread g admits the g-th filter
+// overall, of the request q with fstart[q] <= g < fstart[q + 1] (its first
+// slot is fstart[q]); thread 0 also records the batch's start time.
+__global__ void k_admit_requests(FilterDesc *desc, EngineArgs e, const RequestArgs *reqs,
+                                 const int32_t *fstart, int32_t n_req, uint64_t *start_tick) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) *start_tick = wall_clock64();
+    if (g >= fstart[n_req]) return;
+    int lo = 0, hi = n_req - 1;  // the last q with fstart[q] <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (fstart[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    admit_one(desc, e, reqs[lo], g - fstart[lo]);
 }
 
 void fill_reactant_tables(RequestArgs &r, const int32_t *kind, const int32_t *s1,
@@ -280,6 +304,31 @@ __global__ __launch_bounds__(kPropBlock) void k_flow(EngineArgs e, const FlowArg
     flow_run<NetArgs<RMAX, W>, UMAX, RMAX, W, PREC>(e, *fa, net);
 }
 
+// One flow launch over filters of several networks (generic tables): each
+// work item's network tables, nets[group of its filter], are read into
+// scalar registers before its pool runs.
+template <int UMAX, int RMAX, int W, int PREC>
+__global__ __launch_bounds__(kPropBlock) void k_flow_multi(EngineArgs e, const FlowArgs *fa,
+                                                           const NetArgs<RMAX, W> *nets) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[item_lds_words<UMAX, RMAX, PREC>()];
+    flow_run_with(e, *fa, [&](uint32_t item) {
+        const int g = __builtin_amdgcn_readfirstlane(e.desc[item >> 6].group);
+        const NetArgs<RMAX, W> &src = nets[g];
+        NetArgs<RMAX, W> net;
+        net.U = __builtin_amdgcn_readfirstlane(src.U);
+        net.R = __builtin_amdgcn_readfirstlane(src.R);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            net.kind[r] = __builtin_amdgcn_readfirstlane(src.kind[r]);
+            net.s1[r] = __builtin_amdgcn_readfirstlane(src.s1[r]);
+            net.s2[r] = __builtin_amdgcn_readfirstlane(src.s2[r]);
+#pragma unroll
+            for (int w = 0; w < W; ++w) net.nu[r][w] = __builtin_amdgcn_readfirstlane(src.nu[r][w]);
+        }
+        run_item<NetArgs<RMAX, W>, UMAX, RMAX, W, PREC>(e, net, item, lds);
+    });
+}
+
 __global__ void k_flow_check(EngineArgs e, FlowArgs fa) {
     if (fa.ctl[kCtlAbort] == 0u) return;
     const int f = e.f_lo + (int)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -328,6 +377,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
             e.tcur[f] = t + 1;
             e.fll[f] = __builtin_nan("");
             e.fflags[f] |= kFlagStopped;
+            if (e.fdone) e.fdone[f] = wall_clock64();
         }
         return;
     }
@@ -363,6 +413,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
             e.tcur[f] = t + 1;
             e.fll[f] = -__builtin_inf();
             e.fflags[f] |= kFlagStopped;
+            if (e.fdone) e.fdone[f] = wall_clock64();
         }
         return;
     }
@@ -404,6 +455,7 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
         e.fll[f] = e.fll[f] + loglik_increment(d, mx, S, yt);
         e.tcur[f] = t + 1;
         if (t + 1 < T) bcast_u = resample_word(d, t);
+        else if (e.fdone) e.fdone[f] = wall_clock64();
     }
     if (t + 1 >= T) return;
     __syncthreads();
@@ -460,6 +512,24 @@ __global__ void k_finish(EngineArgs e, int32_t base, int32_t n_theta, int32_t M,
     if (status) status[i] = st;
 }
 
+// Per-theta results of every request of a multi-request batch: block q sums
+// request q's filters over its trajectories, in trajectory order.
+__global__ void k_finish_requests(EngineArgs e, const ReqSpan *spans, double *loglik,
+                                  int32_t *status) {
+    const ReqSpan sp = spans[blockIdx.x];
+    for (int i = threadIdx.x; i < sp.n_theta; i += blockDim.x) {
+        double s = 0.0;
+        int32_t st = LIK_STATUS_OK;
+        for (int m = 0; m < sp.M; ++m) {
+            const int f = sp.base + i * sp.M + m;
+            if (st == LIK_STATUS_OK && e.fstatus[f] != LIK_STATUS_OK) st = e.fstatus[f];
+            s = s + e.fll[f];
+        }
+        loglik[sp.out + i] = st == LIK_STATUS_OK ? s : __builtin_nan("");
+        if (status) status[sp.out + i] = st;
+    }
+}
+
 __global__ void k_aux_filters(EngineArgs e, int32_t base, int32_t F, uint64_t *events,
                               double *fll) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -501,6 +571,23 @@ hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs
 }
 
 const void *admit_kernel() { return (const void *)k_admit; }
+
+hipError_t launch_admit_requests(FilterDesc *desc, const EngineArgs &e, const RequestArgs *reqs,
+                                 const int32_t *fstart, int32_t n_req, int32_t n_filters,
+                                 uint64_t *start_tick, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::max(1, (n_filters + 255) / 256);
+    hipLaunchKernelGGL(k_admit_requests, dim3(blocks), dim3(256), 0, s, desc, e, reqs, fstart,
+                       n_req, start_tick);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_requests(const EngineArgs &e, const ReqSpan *spans, int32_t n_req,
+                                  double *loglik, int32_t *status, hipStream_t s) {
+    if (n_req > 0)
+        hipLaunchKernelGGL(k_finish_requests, dim3((unsigned)n_req), dim3(64), 0, s, e, spans,
+                           loglik, status);
+    return hipGetLastError();
+}
 
 hipError_t launch_stop(const EngineArgs &e, int32_t base, int32_t F, hipStream_t s) {
     if (F <= 0) return hipSuccess;
@@ -590,6 +677,40 @@ static const void *flow_kernel(int umax, int rmax, int precision) {
     if (umax == 8 && rmax == 16) return flow_fn<8, 16, 1>(precision);
     if (umax == 32 && rmax == 64) return flow_fn<32, 64, 4>(precision);
     return nullptr;
+}
+
+template <int UMAX, int RMAX, int W>
+static const void *flow_multi_fn(int precision) {
+    return precision == LIK_FP32_MIXED ? (const void *)k_flow_multi<UMAX, RMAX, W, LIK_FP32_MIXED>
+                                       : (const void *)k_flow_multi<UMAX, RMAX, W, LIK_FP64>;
+}
+
+// the multi-network flow kernel exists for the small buckets (networks whose
+// tables fit scalar registers)
+static const void *flow_multi_kernel(int umax, int rmax, int precision) {
+    if (umax == 4 && rmax == 8) return flow_multi_fn<4, 8, 1>(precision);
+    if (umax == 8 && rmax == 16) return flow_multi_fn<8, 16, 1>(precision);
+    return nullptr;
+}
+
+int flow_multi_blocks_per_cu(int umax, int rmax, int precision) {
+    const void *fn = flow_multi_kernel(umax, rmax, precision);
+    int n = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kPropBlock, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+hipError_t launch_flow_multi(const EngineArgs &e, const FlowArgs &fa, unsigned n_waves,
+                             const void *nets_dev, int umax, int rmax, int precision,
+                             hipStream_t s) {
+    const void *fn = flow_multi_kernel(umax, rmax, precision);
+    if (!fn || n_waves == 0) return hipErrorInvalidValue;
+    EngineArgs ea = e;
+    const FlowArgs *fb = flow_args_copy(fa.ctl);  // written by k_flow_init
+    const void *nd = nets_dev;
+    void *args[] = {(void *)&ea, (void *)&fb, (void *)&nd};
+    return hipLaunchKernel(fn, dim3(n_waves), dim3(kPropBlock), args, 0, s);
 }
 
 int flow_blocks_per_cu(int umax, int rmax, int precision) {

@@ -96,6 +96,8 @@ struct EngineArgs {
     uint32_t *order_ctl;      // [2]: most expected events per particle of any slot (zero
                               // between iterations), and its copy for the placing pass
     uint32_t pool_chunks;     // groups of 64 particles over the slots that may be active
+    uint64_t *fdone;          // [slots] device wall clock when the slot's filter finished, or
+                              // null (not recorded)
     int32_t f_lo, f_hi;       // slot range that may hold active filters
     // Pool size G per slot: G = clamp(pool_events / (events per particle in
     // the last interval), pool_min, pool_max); pool_first for the first one.
@@ -204,6 +206,22 @@ struct RequestArgs {
 void fill_reactant_tables(RequestArgs &r, const int32_t *kind, const int32_t *s1,
                           const int32_t *s2, int R);
 size_t request_state_bytes(int64_t F, int32_t U, int32_t Hp);
+// A request's place in a multi-request batch: first slot, sizes, and the
+// offset of its per-theta results.
+struct ReqSpan {
+    int32_t base, n_theta, M, out;
+};
+hipError_t launch_admit_requests(FilterDesc *desc, const EngineArgs &e, const RequestArgs *reqs,
+                                 const int32_t *fstart, int32_t n_req, int32_t n_filters,
+                                 uint64_t *start_tick, hipStream_t s);
+hipError_t launch_finish_requests(const EngineArgs &e, const ReqSpan *spans, int32_t n_req,
+                                  double *loglik, int32_t *status, hipStream_t s);
+// Flow launch over filters of several networks with the generic tables
+// nets_dev[group] (NetArgs of the umax x rmax bucket, in device memory).
+hipError_t launch_flow_multi(const EngineArgs &e, const FlowArgs &fa, unsigned n_waves,
+                             const void *nets_dev, int umax, int rmax, int precision,
+                             hipStream_t s);
+int flow_multi_blocks_per_cu(int umax, int rmax, int precision);
 hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs &r,
                         hipStream_t s);
 const void *admit_kernel();  // k_admit, for updating captured graph nodes

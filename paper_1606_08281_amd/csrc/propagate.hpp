@@ -81,6 +81,17 @@ __host__ __device__ constexpr int nu_row_words() {
     return ((UMAX + 3) / 4 + 3) / 4 * 4;
 }
 
+// LDS words a work item uses (the caller's buffer, 16-byte aligned): the
+// pool's staged counts and processing order, the pool sort's buckets, and
+// for a large network its rates and net-change table.
+template <int UMAX, int RMAX, int PREC>
+__host__ __device__ constexpr int item_lds_words() {
+    return kPoolLdsWords + kSortBuckets +
+           (LdsNet<RMAX>::on ? ((PREC == LIK_FP32_MIXED ? RMAX : 2 * RMAX) + 3) / 4 * 4 +
+                                   RMAX * nu_row_words<UMAX>()
+                             : 0);
+}
+
 // Index of the reaction that fires, r* = min{r : S_r > target}, else R - 1
 // (no sum above a NaN or infinite target), as select_reaction picks it.
 template <class NetT, int RMAX, class Real>
@@ -286,8 +297,12 @@ __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x
 // data (generic kernels) or as compile-time constants (network-specialised
 // kernels).
 // ---------------------------------------------------------------------------
+// lds: the workgroup's buffer of at least item_lds_words<UMAX, RMAX, PREC>()
+// words, 16-byte aligned (declared by the kernel, so that a kernel running
+// the items of several networks holds one buffer for all of them).
 template <class NetT, int UMAX, int RMAX, int W, int PREC>
-__device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, uint32_t item) {
+__device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, uint32_t item,
+                                         uint32_t *lds) {
     // Every value of the item's context is the same on all lanes: moved to
     // scalar registers (a persistent caller loads them with vector loads,
     // after stores of earlier items, and would otherwise keep them in
@@ -328,8 +343,11 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     // or for a large network in LDS with its net-change table.
     constexpr bool kLds = LdsNet<RMAX>::on;
     constexpr int kRow = nu_row_words<UMAX>();
-    __shared__ __attribute__((aligned(16))) Real c_lds[kLds ? RMAX : 1];
-    __shared__ __attribute__((aligned(16))) uint32_t nu_lds[kLds ? RMAX * kRow : 1];
+    int32_t *pool_x = reinterpret_cast<int32_t *>(lds);  // [U][npool], then order[npool] (uint16)
+    uint32_t *bucket = lds + kPoolLdsWords;              // [kSortBuckets]
+    Real *c_lds = reinterpret_cast<Real *>(lds + kPoolLdsWords + kSortBuckets);
+    uint32_t *nu_lds = lds + kPoolLdsWords + kSortBuckets +
+                       ((PREC == LIK_FP32_MIXED ? RMAX : 2 * RMAX) + 3) / 4 * 4;
     Real c_reg[kLds ? 1 : RMAX];
     if (kLds) {
         for (int r = lane; r < R; r += kPropBlock) c_lds[r] = (Real)d.theta[r];
@@ -372,8 +390,6 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     // interval length), bucketed by half octave below the pool's heaviest;
     // order[s] is the pool offset of the s-th particle taken.
     // Which lane runs a particle, and when, never changes its result.
-    __shared__ __attribute__((aligned(16))) int32_t pool_x[kPoolLdsWords];  // [U][npool], then order[npool] (uint16)
-    __shared__ uint32_t bucket[kSortBuckets];
     const int npool = p1 - p0;
     const bool staged = npool > kPropBlock;
     const bool ordered = staged && t > 0 && npool <= kSortPerLane * kPropBlock &&
@@ -592,8 +608,9 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
 // One wavefront per work item of the iteration's list.
 template <class NetT, int UMAX, int RMAX, int W, int PREC>
 __device__ __forceinline__ void propagate_item(const EngineArgs &e, const NetT &net, int group) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[item_lds_words<UMAX, RMAX, PREC>()];
     if (blockIdx.x >= e.item_count[group]) return;
-    run_item<NetT, UMAX, RMAX, W, PREC>(e, net, e.items[e.group_off[group] + blockIdx.x]);
+    run_item<NetT, UMAX, RMAX, W, PREC>(e, net, e.items[e.group_off[group] + blockIdx.x], lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,6 +16,8 @@
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -112,6 +114,82 @@ bool compile(const std::string &src, std::vector<char> *code, std::string *err) 
 
 }  // namespace
 
+namespace {
+
+// A network's tables as compile-time constants: struct `name` in namespace lik.
+void emit_spec_net(std::ostringstream &o, const lik_network &net, const char *name) {
+    const int U = net.U, R = net.R, W = (U + 7) / 8;
+    o << "struct " << name << " {\n  static constexpr int U = " << U << ", R = " << R << ";\n";
+    auto arr = [&](const char *field, const int32_t *v) {
+        o << "  static constexpr int " << field << "[" << R << "] = {";
+        for (int r = 0; r < R; ++r) o << (r ? "," : "") << v[r];
+        o << "};\n";
+    };
+    arr("kind", net.kind);
+    arr("s1", net.s1);
+    arr("s2", net.s2);
+    o << "  static constexpr unsigned nu[" << R << "][" << W << "] = {";
+    for (int r = 0; r < R; ++r) {
+        o << (r ? "," : "") << "{";
+        for (int w = 0; w < W; ++w) o << (w ? "," : "") << net.nu[r][w] << "u";
+        o << "}";
+    }
+    o << "};\n};\n";
+}
+
+void emit_prelude(std::ostringstream &o) {
+    o << "typedef __hip_internal::uint32_t uint32_t;\n"
+         "typedef __hip_internal::uint64_t uint64_t;\n"
+         "typedef __hip_internal::int32_t int32_t;\n"
+         "typedef __hip_internal::int64_t int64_t;\n"
+         "typedef __hip_internal::uint8_t uint8_t;\n"
+         "typedef __hip_internal::uint16_t uint16_t;\n"
+         "#include \"flow.hpp\"\n"
+         "namespace lik {\n"
+         "static_assert(sizeof(EngineArgs) == "
+      << sizeof(EngineArgs) << ", \"EngineArgs layout\");\n"
+         "static_assert(sizeof(FilterDesc) == "
+      << sizeof(FilterDesc) << ", \"FilterDesc layout\");\n"
+         "static_assert(sizeof(FlowArgs) == "
+      << sizeof(FlowArgs) << ", \"FlowArgs layout\");\n";
+}
+
+}  // namespace
+
+// One flow kernel for filters of several networks: each work item runs the
+// specialised body of its filter's network (group g = index in nets; the
+// branch is wave-uniform), with one LDS buffer for all of them.
+std::string specialized_multi_source(const std::vector<lik_network *> &nets, int precision) {
+    std::ostringstream o;
+    emit_prelude(o);
+    for (size_t g = 0; g < nets.size(); ++g)
+        emit_spec_net(o, *nets[g], ("SpecNet" + std::to_string(g)).c_str());
+    o << "constexpr int cmax(int a, int b) { return a > b ? a : b; }\n"
+         "constexpr int kMultiLds = 0";
+    for (size_t g = 0; g < nets.size(); ++g) {
+        const int U = nets[g]->U, R = nets[g]->R;
+        o << ";\nconstexpr int kMultiLds" << g << " = cmax(kMultiLds"
+          << (g ? std::to_string(g - 1) : std::string("")) << ", item_lds_words<" << U << ", "
+          << R << ", " << precision << ">())";
+    }
+    o << ";\n}  // namespace lik\n";
+    o << "extern \"C\" __global__ __launch_bounds__(64) void lik_flow_spec_multi("
+         "lik::EngineArgs e, const lik::FlowArgs *fa) {\n"
+         "  __shared__ __attribute__((aligned(16))) uint32_t lds[lik::kMultiLds"
+      << nets.size() - 1 << "];\n"
+         "  lik::flow_run_with(e, *fa, [&](uint32_t item) {\n"
+         "    const int g = __builtin_amdgcn_readfirstlane(e.desc[item >> 6].group);\n"
+         "    switch (g) {\n";
+    for (size_t g = 0; g < nets.size(); ++g) {
+        const int U = nets[g]->U, R = nets[g]->R, W = (U + 7) / 8;
+        o << "    case " << g << ": { const lik::SpecNet" << g << " n{}; lik::run_item<lik::SpecNet"
+          << g << ", " << U << ", " << R << ", " << W << ", " << precision
+          << ">(e, n, item, lds); break; }\n";
+    }
+    o << "    default: break;\n    }\n  });\n}\n";
+    return o.str();
+}
+
 std::string specialized_source(const lik_network &net, int precision) {
     const int U = net.U, R = net.R, W = (U + 7) / 8;
     std::ostringstream o;
@@ -168,10 +246,20 @@ std::string specialized_source(const lik_network &net, int precision) {
 
 namespace {
 
+// Code object of a generated source: from the disk cache or compiled now.
+bool code_for_source(const std::string &src, std::vector<char> *code, std::string *path_out,
+                     std::string *err);
+
 // Code object for (network, precision): from the disk cache or compiled now.
 bool specialized_code(const lik_network &net, int precision, std::vector<char> *code,
                       std::string *src_out, std::string *path_out, std::string *err) {
     const std::string src = specialized_source(net, precision);
+    *src_out = src;
+    return code_for_source(src, code, path_out, err);
+}
+
+bool code_for_source(const std::string &src, std::vector<char> *code, std::string *path_out,
+                     std::string *err) {
     // the key covers everything the code object depends on: the generated
     // source, the embedded kernel headers, the options and the compiler
     std::string key = src;
@@ -188,7 +276,6 @@ bool specialized_code(const lik_network &net, int precision, std::vector<char> *
     const std::string dir = cache_dir();
     const std::string path = dir + "/prop_" + hex + ".co";
 
-    *src_out = src;
     *path_out = path;
     if (read_file(path, code)) return true;
     if (!compile(src, code, err)) return false;
@@ -259,6 +346,50 @@ hipFunction_t loaded_specialized_kernel(lik_network &net, int precision, int kin
     if (it == net.spec.end()) return nullptr;
     const lik_network::SpecKernels &k = it->second;
     return kind == kSpecPersistent ? k.persistent : kind == kSpecFlow ? k.flow : k.item;
+}
+
+namespace {
+// Multi-network flow kernels, per (device, source): loaded once and kept for
+// the life of the process (a set of networks has no handle that owns them).
+std::mutex g_multi_mu;
+std::map<std::pair<int, std::string>, std::pair<hipModule_t, hipFunction_t>> g_multi;
+}  // namespace
+
+bool precompile_multi(const std::vector<lik_network *> &nets, int precision, std::string *err) {
+    std::vector<char> code;
+    std::string path;
+    return code_for_source(specialized_multi_source(nets, precision), &code, &path, err);
+}
+
+hipFunction_t specialized_multi_kernel(const std::vector<lik_network *> &nets, int precision,
+                                       std::string *err) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return nullptr;
+    }
+    const std::string src = specialized_multi_source(nets, precision);
+    std::lock_guard<std::mutex> g(g_multi_mu);
+    auto it = g_multi.find({dev, src});
+    if (it != g_multi.end()) return it->second.second;
+    std::vector<char> code;
+    std::string path;
+    if (!code_for_source(src, &code, &path, err)) return nullptr;
+    hipModule_t mod = nullptr;
+    hipError_t e = hipModuleLoadData(&mod, code.data());
+    if (e != hipSuccess) {
+        *err = std::string("hipModuleLoadData: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    hipFunction_t fn = nullptr;
+    e = hipModuleGetFunction(&fn, mod, "lik_flow_spec_multi");
+    if (e != hipSuccess) {
+        *err = std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
+        (void)hipModuleUnload(mod);
+        return nullptr;
+    }
+    g_multi[{dev, src}] = {mod, fn};
+    return fn;
 }
 
 void release_specialized(lik_network &net) {

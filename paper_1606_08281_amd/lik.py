@@ -27,7 +27,8 @@ EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile
             "lik_server_submit", "lik_server_wait", "lik_server_cancel", "lik_server_stats_get",
             "lik_server_destroy",
             "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version",
-            "lik_network_set_tuning", "lik_network_get_tuning", "lik_autotune_device"]
+            "lik_network_set_tuning", "lik_network_get_tuning", "lik_autotune_device",
+            "lik_eval_requests", "lik_precompile_requests", "lik_autotune_requests"]
 
 
 class LikError(RuntimeError):
@@ -146,6 +147,12 @@ def lib():
         L.lik_server_stats_get.restype = ctypes.c_int
         L.lik_server_destroy.argtypes = [vp]
         L.lik_server_destroy.restype = ctypes.c_int
+        L.lik_eval_requests.argtypes = [vp, i32, vp, i32, vp, vp, vp]
+        L.lik_eval_requests.restype = ctypes.c_int
+        L.lik_precompile_requests.argtypes = [vp, i32, i32]
+        L.lik_precompile_requests.restype = ctypes.c_int
+        L.lik_autotune_requests.argtypes = [vp, i32, i32, vp]
+        L.lik_autotune_requests.restype = ctypes.c_int
         L.lik_timing_enable.argtypes = [ctypes.c_int]
         L.lik_timing_enable.restype = ctypes.c_int
         L.lik_timing_read.argtypes = [vp]
@@ -402,6 +409,81 @@ class DeviceBatch:
             self.workspace.data_ptr(), self.ws_bytes + 256, ctypes.c_void_p(s.cuda_stream),
             ctypes.byref(t)))
         return _tuning_dict(t)
+
+
+def _request(net, obs_kind, observed, sigma, theta, trajectories, n_particles, seed,
+             precision=FP64, event_cap=0, theta_ids=None, timeout_s=None, keep=None):
+    """A Request struct over numpy copies (appended to `keep`, which must
+    outlive the struct's use)."""
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, net.R))
+    P = len(observed)
+    d = pack_trajectories(trajectories, P)
+    ids = None if theta_ids is None else np.ascontiguousarray(theta_ids, dtype=np.uint32)
+    if keep is not None:
+        keep.append((theta, d, ids))
+    q = Request()
+    q.net = net.handle.value
+    q.obs = obs_model(obs_kind, observed, sigma)
+    q.precision = int(precision)
+    q.n_theta = theta.shape[0]
+    q.theta = theta.ctypes.data
+    q.theta_ids = _ptr(ids)
+    q.data = Data(len(trajectories), _ptr(d["obs_offsets"]), _ptr(d["t_obs"]), _ptr(d["y"]),
+                  _ptr(d["t0"]), _ptr(d["x0"]))
+    q.n_particles = int(n_particles)
+    q.reserved = 0
+    q.seed = int(seed) & (2**64 - 1)
+    q.event_cap = int(event_cap)
+    q.timeout_us = 0 if timeout_s is None else max(1, int(timeout_s * 1e6))
+    return q
+
+
+def _request_array(requests, keep):
+    arr = (Request * len(requests))()
+    for k, r in enumerate(requests):
+        arr[k] = _request(keep=keep, **r)
+    return arr
+
+
+def eval_requests(requests, tuning=None, kernel=KERNEL_AUTO):
+    """lik_eval_requests over a list of request dicts (keys: net, obs_kind,
+    observed, sigma, theta, trajectories, n_particles, seed and optionally
+    precision, event_cap, theta_ids).  Returns (list of loglik arrays, list
+    of status arrays, done_ms array)."""
+    keep = []
+    arr = _request_array(requests, keep)
+    n = [arr[k].n_theta for k in range(len(requests))]
+    ll = np.zeros(max(sum(n), 1), dtype=np.float64)
+    st = np.zeros(max(sum(n), 1), dtype=np.int32)
+    done = np.zeros(max(len(requests), 1), dtype=np.float64)
+    tp = None
+    if tuning is not None:
+        t = dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1,
+                 priority=0, items_per_cu=160, persistent=0, schedule=1, urgent_events=16000,
+                 backlog_per_cu=30)
+        t.update(tuning)
+        tp = Tuning(**{k: int(v) for k, v in t.items()})
+    _check(lib().lik_eval_requests(arr, len(requests), None if tp is None else ctypes.byref(tp),
+                                   int(kernel), ll.ctypes.data, st.ctypes.data, done.ctypes.data))
+    offs = np.cumsum([0] + n)
+    return ([ll[offs[k]:offs[k + 1]].copy() for k in range(len(requests))],
+            [st[offs[k]:offs[k + 1]].copy() for k in range(len(requests))], done[:len(requests)])
+
+
+def precompile_requests(nets, precision=FP64):
+    """Compile the multi-network flow kernel for these networks (in the order
+    they first appear in the requests) into the disk cache (no GPU)."""
+    arr = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
+    _check(lib().lik_precompile_requests(arr, len(nets), int(precision)))
+
+
+def autotune_requests(requests, kernel=KERNEL_AUTO):
+    """The fastest candidate tuning for lik_eval_requests on these requests."""
+    keep = []
+    arr = _request_array(requests, keep)
+    t = Tuning()
+    _check(lib().lik_autotune_requests(arr, len(requests), int(kernel), ctypes.byref(t)))
+    return _tuning_dict(t)
 
 
 class Server:

@@ -141,3 +141,23 @@ def test_tuning_set_get_and_bounds():
             net.set_tuning(**bad)
     assert net.tuning()["pool_max"] == 16  # a rejected call changes nothing
     assert net.set_tuning(default=True) == default
+
+
+def test_eval_requests_rejects_on_the_host():
+    # every check runs before any device work
+    imm = W.immigration_death_workload(n_theta=4, n_particles=16)
+    net = lik.Network(imm.net.orders, imm.net.stoich)
+    base = dict(net=net, obs_kind=imm.obs_kind, observed=imm.observed, sigma=imm.sigma,
+                theta=imm.theta[:2], trajectories=imm.trajectories, n_particles=16, seed=1)
+    with pytest.raises(lik.LikError) as e:   # mixed precisions
+        lik.eval_requests([base, dict(base, precision=lik.FP32_MIXED)])
+    assert e.value.code == lik.LIK_EINVAL
+    with pytest.raises(lik.LikError) as e:   # an invalid request is named
+        lik.eval_requests([base, dict(base, n_particles=0)])
+    assert e.value.code == lik.LIK_EINVAL and "request 1" in str(e.value)
+    nets = [lik.Network(imm.net.orders, imm.net.stoich) for _ in range(17)]
+    with pytest.raises(lik.LikError) as e:   # more than 16 networks
+        lik.eval_requests([dict(base, net=n) for n in nets])
+    assert e.value.code == lik.LIK_EUNSUPPORTED
+    with pytest.raises(lik.LikError):
+        lik.precompile_requests(nets)
