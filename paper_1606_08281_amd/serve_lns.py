@@ -272,6 +272,20 @@ def replay(recs, nets, n_total, loads=(0.5, 0.8), log=None, arena_bytes=8 << 30)
            "saturated": {"evals_per_s": sat, "wall_s": wall,
                          "p50_ms": st["p50_latency_us"] / 1e3, "p99_ms": st["p99_latency_us"] / 1e3},
            "at_load": []}
+    # the same requests in one lik_eval_requests call: one persistent flow
+    # launch over every interval of every filter, the upper bound for a
+    # server that fed the flow kernel
+    rq = [dict(net=nets[r["wl"].name], obs_kind=r["wl"].obs_kind, observed=r["wl"].observed,
+               sigma=r["wl"].sigma, theta=r["theta"], trajectories=r["trajs"], n_particles=r["H"],
+               seed=r["seed"], theta_ids=r["ids"]) for r in reqs]
+    lik.eval_requests(rq[:64])
+    t0 = time.perf_counter()
+    lik.eval_requests(rq)
+    flow_wall = time.perf_counter() - t0
+    out["one_flow_launch"] = {"evals_per_s": n_evals / flow_wall, "wall_s": flow_wall,
+                              "path": "every request at once through lik_eval_requests "
+                                      "(synchronous; copies and allocation included)"}
+    say(f"one flow launch {n_evals / flow_wall:.0f} evals/s")
     mean_evals = n_evals / len(reqs)
     for load in loads:
         rate = load * sat / mean_evals
