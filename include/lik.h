@@ -69,6 +69,9 @@ extern "C" {
 /* observation noise models (Sec. "General Task": Y ~ p(. | X, theta)) */
 #define LIK_OBS_GAUSSIAN 0  /* y = x_s + N(0, sigma^2) per observed species s */
 #define LIK_OBS_LOGNORMAL 1 /* log y = log x_s + N(0, sigma^2); y > 0 required */
+#define LIK_OBS_FLUORESCENCE 2 /* y = N(gain x_s, sigma^2 x_s) + B, B ~ N(bg_mean, bg_sd^2):
+                                  each molecule adds an independent normal signal,
+                                  background added (Supplementary "LacGfp example") */
 
 /* arithmetic of the SSA step */
 #define LIK_FP64 0       /* binary64 propensities, event times and clock */
@@ -172,12 +175,21 @@ int lik_destroy_network(lik_network_t net);
  */
 int lik_network_precompile(lik_network_t net, int32_t precision);
 
-/* Observation model: kind, observed species (in order) and noise scale sigma > 0. */
+/*
+ * Observation model (Sec. "General Task": Y ~ p(. | X, theta)): kind, observed
+ * species (in order) and noise parameters.
+ *   LIK_OBS_GAUSSIAN, LIK_OBS_LOGNORMAL: sigma > 0; gain, bg_mean, bg_sd unused.
+ *   LIK_OBS_FLUORESCENCE: the density of y is normal with mean gain * x + bg_mean
+ *     and variance sigma^2 * x + bg_sd^2 (x: the observed count), so a count of
+ *     zero still has density through the background.  gain, bg_mean finite;
+ *     sigma >= 0 finite; bg_sd > 0 finite.
+ */
 typedef struct lik_obs_model {
     int32_t kind;
     int32_t n_observed;                 /* P in [1, LIK_MAX_OBSERVED] */
     int32_t species[LIK_MAX_OBSERVED];  /* species index of observed component k */
     double sigma;
+    double gain, bg_mean, bg_sd;        /* LIK_OBS_FLUORESCENCE only */
 } lik_obs_model;
 
 /*
@@ -189,6 +201,13 @@ typedef struct lik_obs_model {
  *   y [total * P] binary64 observed values, component k of observation n at
  *     y[n*P + k];
  *   t0 [M] start times; x0 [M*U] int32 known initial counts (>= 0, <= 2^30).
+ *   x0_hi [M*U] int32 or NULL.  NULL: every particle starts at x0.  Otherwise
+ *     the initial counts are random (Supplementary I: the filter starts from
+ *     H draws of the initial distribution): particle j of trajectory m starts
+ *     with species u drawn uniformly from the integers x0 .. x0_hi
+ *     (x0 <= x0_hi <= 2^30), independently per species and particle, from
+ *     Philox block (u / 4, j, m << 16, theta id << 2 | 2), word u % 4:
+ *     x0 + floor(word * (x0_hi - x0 + 1) / 2^32).
  * Whether these are host or device pointers is fixed by the entry point.
  */
 typedef struct lik_data {
@@ -198,6 +217,7 @@ typedef struct lik_data {
     const double *y;
     const double *t0;
     const int32_t *x0;
+    const int32_t *x0_hi;
 } lik_data;
 
 /* Evaluation options; a NULL pointer means all defaults. */

@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "pf_oracle.c")
 
 OK, EVENT_CAP, COUNT_OVERFLOW, BAD_THETA = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
-OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
+OBS_GAUSSIAN, OBS_LOGNORMAL, OBS_FLUORESCENCE = 0, 1, 2
 
 
 def build():
@@ -50,6 +50,10 @@ class _Problem(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int32),
         ("event_cap", ctypes.c_uint64),
+        ("gain", ctypes.c_double),
+        ("bg_mean", ctypes.c_double),
+        ("bg_sd", ctypes.c_double),
+        ("x0_hi", ctypes.c_void_p),
     ]
 
 
@@ -105,27 +109,34 @@ class Problem:
                           else np.ascontiguousarray(theta_ids, dtype=np.uint32))
         P = len(self.observed)
         offs = [0]
-        t_obs, ys, t0, x0 = [], [], [], []
+        t_obs, ys, t0, x0, x0_hi = [], [], [], [], []
         for tr in trajectories:
             t_obs.append(np.asarray(tr["t_obs"], dtype=np.float64))
             ys.append(np.asarray(tr["y"], dtype=np.float64).reshape(-1, P))
             t0.append(float(tr.get("t0", 0.0)))
             x0.append(np.asarray(tr["x0"], dtype=np.int32))
+            x0_hi.append(np.asarray(tr.get("x0_hi", tr["x0"]), dtype=np.int32))
             offs.append(offs[-1] + len(t_obs[-1]))
+        random_start = any("x0_hi" in tr for tr in trajectories)
         self.offsets = np.array(offs, dtype=np.int32)
         self.t_obs = np.ascontiguousarray(np.concatenate(t_obs))
         self.y = np.ascontiguousarray(np.concatenate(ys))
         self.t0 = np.array(t0, dtype=np.float64)
         self.x0 = np.ascontiguousarray(np.stack(x0))
+        self.x0_hi = np.ascontiguousarray(np.stack(x0_hi)) if random_start else None
+        # sigma: the noise scale, or (sigma, gain, bg_mean, bg_sd) for the
+        # fluorescence model
+        sig = tuple(sigma) if isinstance(sigma, (tuple, list)) else (sigma, 0.0, 0.0, 0.0)
         self.H = int(n_particles)
         self.M = len(trajectories)
         self.n_theta = self.theta.shape[0]
         self.c = _Problem(
             U, R, _ptr(self.orders), _ptr(self.stoich), int(obs_kind), P,
-            _ptr(self.observed), float(sigma), self.n_theta, _ptr(self.theta),
+            _ptr(self.observed), float(sig[0]), self.n_theta, _ptr(self.theta),
             _ptr(self.theta_ids), self.M, _ptr(self.offsets), _ptr(self.t_obs),
             _ptr(self.y), _ptr(self.t0), _ptr(self.x0), self.H, int(seed) & (2**64 - 1),
-            int(precision), int(event_cap))
+            int(precision), int(event_cap), float(sig[1]), float(sig[2]), float(sig[3]),
+            _ptr(self.x0_hi))
 
 
 def philox(ctr, key):

@@ -10,7 +10,13 @@
  *     reactions with consumed counts p_ru and produced counts q_ru, propensities
  *     depending on theta; mass-action kinetics as stated for the Lac-Gfp example
  *     in the Supplementary "Examples used"),
- *   - the observation model Y ~ p(. | X, theta) of Sec. "General Task",
+ *   - the observation model Y ~ p(. | X, theta) of Sec. "General Task", with
+ *     the Gaussian and log-normal noise used by the workloads and the
+ *     fluorescence model of the Supplementary "LacGfp example" (each molecule
+ *     contributes an independent normal signal, plus a background),
+ *   - a random initial state: the filter starts from H draws of the initial
+ *     distribution (Supplementary I), here independent uniform integers per
+ *     species as in the Lac-Gfp initial-distribution table,
  *   - the likelihood factorisation over trajectories and time points and the
  *     recursive estimate of Supplementary I ("Computing the Likelihood"),
  *   - the particle filter of Supplementary I, Algorithm "Likelihood
@@ -48,6 +54,7 @@
 
 #define ORC_OBS_GAUSSIAN 0
 #define ORC_OBS_LOGNORMAL 1
+#define ORC_OBS_FLUORESCENCE 2
 
 /* Counts above this at the end of an interval flag COUNT_OVERFLOW. */
 #define ORC_COUNT_LIMIT (1 << 30)
@@ -74,6 +81,10 @@ typedef struct orc_problem {
     uint64_t seed;
     int32_t precision;            /* ORC_FP64 | ORC_FP32_MIXED */
     uint64_t event_cap;           /* max events per particle per interval */
+    /* fluorescence model: y ~ N(gain x + bg_mean, sigma^2 x + bg_sd^2) */
+    double gain, bg_mean, bg_sd;
+    /* [M*U] or NULL: initial counts uniform on the integers x0 .. x0_hi */
+    const int32_t *x0_hi;
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -353,6 +364,19 @@ static double obs_logweight(const orc_problem *P, const int32_t *x, const double
     for (int k = 0; k < P->n_observed; ++k) {
         int32_t cnt = x[P->observed[k]];
         double z;
+        if (P->obs_kind == ORC_OBS_FLUORESCENCE) {
+            /* the sum of cnt independent N(gain, sigma^2) signals plus a
+             * N(bg_mean, bg_sd^2) background: normal, with mean and variance
+             * linear in the count; its variance term depends on the
+             * particle, so log v stays in the weight */
+            double xc = (double)cnt;
+            double mean = P->gain * xc + P->bg_mean;
+            double var = (P->sigma * P->sigma) * xc + P->bg_sd * P->bg_sd;
+            double r = yt[k] - mean;
+            lw = lw - 0.5 * ((r * r) / var);
+            lw = lw - 0.5 * orc_log(var);
+            continue;
+        }
         if (P->obs_kind == ORC_OBS_LOGNORMAL) {
             if (cnt <= 0) return -INFINITY;
             z = (orc_log(yt[k]) - orc_log((double)cnt)) / P->sigma;
@@ -368,7 +392,9 @@ static double obs_logweight(const orc_problem *P, const int32_t *x, const double
  * of the noise density (and the Jacobian -log y of the log-normal). */
 static double obs_logconst(const orc_problem *P, const double *yt)
 {
-    double per = orc_log(P->sigma) + 0.5 * orc_log(2.0 * 3.141592653589793);
+    double half_log_2pi = 0.5 * orc_log(2.0 * 3.141592653589793);
+    double per = P->obs_kind == ORC_OBS_FLUORESCENCE ? half_log_2pi
+                                                     : orc_log(P->sigma) + half_log_2pi;
     double c = -((double)P->n_observed * per);
     if (P->obs_kind == ORC_OBS_LOGNORMAL)
         for (int k = 0; k < P->n_observed; ++k) c = c - orc_log(yt[k]);
@@ -477,8 +503,23 @@ static int run_filter(const orc_problem *P, int i, int m, double *ll_out,
     double *lw = (double *)malloc(sizeof(double) * (size_t)H);
     double *e = (double *)malloc(sizeof(double) * (size_t)H);
     int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * (size_t)H);
-    for (int j = 0; j < H; ++j)
-        for (int u = 0; u < U; ++u) x[(size_t)j * U + u] = P->x0[(size_t)m * U + u];
+    const int32_t *lo = P->x0 + (size_t)m * U;
+    for (int j = 0; j < H; ++j) {
+        for (int u = 0; u < U; ++u) {
+            int32_t v = lo[u];
+            if (P->x0_hi) {
+                /* draw X_0 of particle j: species u from word u % 4 of the
+                 * Philox block (u / 4, j, m << 16, theta id << 2 | 2), mapped
+                 * to lo + floor(word * (hi - lo + 1) / 2^32) */
+                uint32_t w[4];
+                philox_block(P->seed, (uint32_t)(u / 4), (uint32_t)j, (uint32_t)m << 16,
+                             (theta_id << 2) | 2u, w);
+                uint64_t span = (uint64_t)(P->x0_hi[(size_t)m * U + u] - lo[u]) + 1u;
+                v = lo[u] + (int32_t)(((uint64_t)w[u % 4] * span) >> 32);
+            }
+            x[(size_t)j * U + u] = v;
+        }
+    }
 
     int first = P->obs_offsets[m], T = P->obs_offsets[m + 1] - first;
     double ll = 0.0;

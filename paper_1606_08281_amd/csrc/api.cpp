@@ -305,6 +305,10 @@ int lik::check_host_data(const lik_network *net, const lik_obs_model *obs, const
         for (int u = 0; u < U; ++u) {
             const int32_t v = data->x0[(size_t)m * U + u];
             if (v < 0 || v > kCountLimit) return fail(LIK_EINVAL, "x0 out of [0, 2^30]");
+            if (data->x0_hi) {
+                const int32_t h = data->x0_hi[(size_t)m * U + u];
+                if (h < v || h > kCountLimit) return fail(LIK_EINVAL, "x0_hi out of [x0, 2^30]");
+            }
         }
     }
     if (theta_ids)
@@ -318,14 +322,24 @@ int lik::check_common(lik_network_t net, const lik_obs_model *obs, const lik_eva
                         int32_t n_theta, int32_t n_traj, int32_t n_particles) {
     if (!net) return fail(LIK_EINVAL, "network is NULL");
     if (!obs) return fail(LIK_EINVAL, "observation model is NULL");
-    if (obs->kind != LIK_OBS_GAUSSIAN && obs->kind != LIK_OBS_LOGNORMAL)
+    if (obs->kind != LIK_OBS_GAUSSIAN && obs->kind != LIK_OBS_LOGNORMAL &&
+        obs->kind != LIK_OBS_FLUORESCENCE)
         return fail(LIK_EINVAL, "unknown observation kind");
     if (obs->n_observed < 1 || obs->n_observed > LIK_MAX_OBSERVED)
         return fail(LIK_EINVAL, "n_observed must be in [1, 8]");
     for (int k = 0; k < obs->n_observed; ++k)
         if (obs->species[k] < 0 || obs->species[k] >= net->U)
             return fail(LIK_EINVAL, "observed species out of range");
-    if (!(obs->sigma > 0.0) || isinf(obs->sigma)) return fail(LIK_EINVAL, "sigma must be > 0");
+    if (obs->kind == LIK_OBS_FLUORESCENCE) {
+        if (!(obs->sigma >= 0.0) || isinf(obs->sigma))
+            return fail(LIK_EINVAL, "fluorescence: sigma must be finite and >= 0");
+        if (!isfinite(obs->gain) || !isfinite(obs->bg_mean))
+            return fail(LIK_EINVAL, "fluorescence: gain and bg_mean must be finite");
+        if (!(obs->bg_sd > 0.0) || isinf(obs->bg_sd))
+            return fail(LIK_EINVAL, "fluorescence: bg_sd must be finite and > 0");
+    } else if (!(obs->sigma > 0.0) || isinf(obs->sigma)) {
+        return fail(LIK_EINVAL, "sigma must be > 0");
+    }
     if (n_theta < 0) return fail(LIK_EINVAL, "n_theta < 0");
     if (n_theta >= (1 << 30)) return fail(LIK_EINVAL, "n_theta too large");
     if (n_traj < 1 || n_traj > LIK_MAX_TRAJ) return fail(LIK_EINVAL, "n_traj out of range");
@@ -643,6 +657,7 @@ int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts
     r.y = data->y;
     r.t0 = data->t0;
     r.x0 = data->x0;
+    r.x0_hi = data->x0_hi;
     r.state = L.state;
     r.n_theta = n_theta;
     r.M = M;
@@ -656,6 +671,9 @@ int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts
     r.precision = precision;
     for (int k = 0; k < LIK_MAX_OBSERVED; ++k) r.obs_species[k] = k < r.P ? obs->species[k] : 0;
     r.sigma = obs->sigma;
+    r.gain = obs->gain;
+    r.bg_mean = obs->bg_mean;
+    r.bg_sd = obs->bg_sd;
     r.seed = seed;
     r.event_cap = (uint32_t)((opts && opts->event_cap) ? opts->event_cap : LIK_DEFAULT_EVENT_CAP);
     r.base = 0;
@@ -665,6 +683,8 @@ int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts
     auto enqueue = [&](hipStream_t st) -> int {
         hipError_t e = launch_admit(L.desc, L.e, r, st);
         if (e != hipSuccess) return hip_fail(e, "admit launch");
+        if (r.x0_hi && (e = launch_init_start(L.desc, 0, (int32_t)F, st)) != hipSuccess)
+            return hip_fail(e, "initial-count launch");
         if (flow) {
             e = launch_flow_setup(L.e, L.fa, st);
             if (e != hipSuccess) return hip_fail(e, "flow setup launch");
@@ -700,7 +720,8 @@ int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts
     std::string key;
     auto add = [&](const void *v, size_t n) { key.append((const char *)v, n); };
     const void *ptrs[] = {theta, r.theta_ids, data->obs_offsets, data->t_obs, data->y, data->t0,
-                          data->x0, loglik_out, status_out, aux ? aux->filter_events : nullptr,
+                          data->x0, data->x0_hi, loglik_out, status_out,
+                          aux ? aux->filter_events : nullptr,
                           aux ? aux->filter_loglik : nullptr, aux ? aux->final_state : nullptr,
                           workspace, (const void *)G.spec};
     add(ptrs, sizeof(ptrs));
@@ -709,6 +730,9 @@ int eval_device(lik_network_t net, const lik_obs_model *obs, const lik_eval_opts
     add(obs_offsets_host, (size_t)(M + 1) * 4);
     add(r.obs_species, sizeof(r.obs_species));
     add(&r.sigma, 8);
+    add(&r.gain, 8);
+    add(&r.bg_mean, 8);
+    add(&r.bg_sd, 8);
     add(&r.event_cap, 4);
     add(&net->tuning, sizeof(lik_tuning));
     int dev = 0;
@@ -840,11 +864,12 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
     const size_t sz_ids = (opts && opts->theta_ids) ? (size_t)n_theta * 4 : 0;
     const size_t sz_off = (size_t)(M + 1) * 4, sz_t = (size_t)total * 8;
     const size_t sz_y = (size_t)total * P * 8, sz_t0 = (size_t)M * 8, sz_x0 = (size_t)M * U * 4;
+    const size_t sz_x0h = data->x0_hi ? sz_x0 : 0;
     const size_t sz_ll = (size_t)n_theta * 8, sz_st = (size_t)n_theta * 4;
     const size_t sz_ev = (aux && aux->filter_events) ? F * 8 : 0;
     const size_t sz_fl = (aux && aux->filter_loglik) ? F * 8 : 0;
     const size_t sz_fs = (aux && aux->final_state) ? F * U * n_particles * 4 : 0;
-    const size_t sizes[] = {sz_theta, sz_ids, sz_off, sz_t, sz_y, sz_t0, sz_x0,
+    const size_t sizes[] = {sz_theta, sz_ids, sz_off, sz_t, sz_y, sz_t0, sz_x0, sz_x0h,
                             sz_ll, sz_st, sz_ev, sz_fl, sz_fs, ws};
     size_t total_bytes = 0;
     for (size_t v : sizes) total_bytes += align256(v);
@@ -864,6 +889,7 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
     double *d_y = (double *)take(sz_y);
     double *d_t0 = (double *)take(sz_t0);
     int32_t *d_x0 = (int32_t *)take(sz_x0);
+    int32_t *d_x0h = (int32_t *)take(sz_x0h);
     double *d_ll = (double *)take(sz_ll);
     int32_t *d_st = (int32_t *)take(sz_st);
     uint64_t *d_ev = (uint64_t *)take(sz_ev);
@@ -878,7 +904,7 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
         struct { void *d; const void *h; size_t n; } up[] = {
             {d_theta, theta, sz_theta}, {d_ids, opts ? opts->theta_ids : nullptr, sz_ids},
             {d_off, data->obs_offsets, sz_off}, {d_t, data->t_obs, sz_t}, {d_y, data->y, sz_y},
-            {d_t0, data->t0, sz_t0}, {d_x0, data->x0, sz_x0}};
+            {d_t0, data->t0, sz_t0}, {d_x0, data->x0, sz_x0}, {d_x0h, data->x0_hi, sz_x0h}};
         for (auto &u : up) {
             if (!u.n) continue;
             if ((e = hipMemcpyAsync(u.d, u.h, u.n, hipMemcpyHostToDevice, s)) != hipSuccess) break;
@@ -886,7 +912,7 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
         if (e != hipSuccess) { rc = hip_fail(e, "copy to device"); break; }
         lik_eval_opts o = opts ? *opts : lik_eval_opts{LIK_FP64, LIK_KERNEL_AUTO, 0, nullptr, 0, 0};
         o.theta_ids = sz_ids ? d_ids : nullptr;
-        lik_data dd = {M, d_off, d_t, d_y, d_t0, d_x0};
+        lik_data dd = {M, d_off, d_t, d_y, d_t0, d_x0, sz_x0h ? d_x0h : nullptr};
         lik_aux da = {sz_ev ? d_ev : nullptr, sz_fl ? d_fl : nullptr, sz_fs ? d_fs : nullptr};
         rc = lik_eval_batch_device(net, obs, &o, n_theta, d_theta, &dd, data->obs_offsets,
                                    n_particles, seed, d_ll, d_st, aux ? &da : nullptr, d_ws, ws, s);

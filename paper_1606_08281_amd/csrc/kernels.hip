@@ -51,6 +51,7 @@ __device__ __forceinline__ void admit_one(FilterDesc *desc, const EngineArgs &e,
     d.t_obs = r.t_obs + off;
     d.y = r.y + (size_t)off * r.P;
     d.x0 = r.x0 + (size_t)m * r.U;
+    d.x0_hi = r.x0_hi ? r.x0_hi + (size_t)m * r.U : nullptr;
     const size_t per = (size_t)r.U * r.Hp;
     int32_t *st = r.state + (size_t)k * (2 * per + 5 * (size_t)r.Hp);
     d.xa = st;
@@ -61,6 +62,10 @@ __device__ __forceinline__ void admit_one(FilterDesc *desc, const EngineArgs &e,
     d.pa0 = (float *)(st + 2 * per + 4 * (size_t)r.Hp);
     d.t0 = r.t0[m];
     d.sigma = r.sigma;
+    d.gain = r.gain;
+    d.bg_mean = r.bg_mean;
+    d.obs_s2 = r.sigma * r.sigma;
+    d.bg_s2 = r.bg_sd * r.bg_sd;
     d.seed = r.seed;
     d.theta_id = r.theta_ids ? r.theta_ids[i] : (uint32_t)i;
     d.traj = (uint32_t)m;
@@ -130,6 +135,29 @@ __global__ void k_admit_requests(FilterDesc *desc, EngineArgs e, const RequestAr
         else hi = mid - 1;
     }
     admit_one(desc, e, reqs[lo], g - fstart[lo]);
+}
+
+// Random initial counts (stream purpose 2): one workgroup per slot; particle
+// j of a slot with bounds draws species u from Philox block (u / 4, j,
+// traj << 16, theta id << 2 | 2), word u % 4, as x0 + floor(w (x0_hi - x0 + 1)
+// / 2^32), into the buffer the first interval reads, with ancestor j.
+__global__ void k_init_start(const FilterDesc *desc, int32_t base) {
+    const FilterDesc &d = desc[base + (int)blockIdx.x];
+    if (!d.x0_hi) return;
+    const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+    const uint32_t c2 = d.traj << 16, c3 = (d.theta_id << 2) | 2u;
+    for (int j = threadIdx.x; j < d.H; j += blockDim.x) {
+        for (int u4 = 0; u4 < d.U; u4 += 4) {
+            const Block4 b = philox4x32_10((uint32_t)(u4 >> 2), (uint32_t)j, c2, c3, k0, k1);
+            const uint32_t w[4] = {b.w0, b.w1, b.w2, b.w3};
+            for (int q = 0; q < 4 && u4 + q < d.U; ++q) {
+                const int u = u4 + q;
+                const uint64_t span = (uint64_t)(d.x0_hi[u] - d.x0[u]) + 1u;
+                d.xa[(size_t)u * d.Hp + j] = d.x0[u] + (int32_t)(((uint64_t)w[q] * span) >> 32);
+            }
+        }
+        d.anc[j] = j;
+    }
 }
 
 void fill_reactant_tables(RequestArgs &r, const int32_t *kind, const int32_t *s1,
@@ -551,7 +579,7 @@ __global__ void k_aux_state(EngineArgs e, int32_t base, int32_t F, int32_t *out)
         const int u = (int)(rem / d.H), j = (int)(rem % d.H);
         const int steps = e.tcur[f];
         const int32_t *src = (steps & 1) ? d.xb : d.xa;
-        out[k] = steps == 0 ? d.x0[u] : src[(size_t)u * d.Hp + j];
+        out[k] = (steps == 0 && !d.x0_hi) ? d.x0[u] : src[(size_t)u * d.Hp + j];
     }
 }
 
@@ -571,6 +599,12 @@ hipError_t launch_admit(FilterDesc *desc, const EngineArgs &e, const RequestArgs
 }
 
 const void *admit_kernel() { return (const void *)k_admit; }
+
+hipError_t launch_init_start(const FilterDesc *desc, int32_t base, int32_t F, hipStream_t s) {
+    if (F <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_start, dim3((unsigned)F), dim3(256), 0, s, desc, base);
+    return hipGetLastError();
+}
 
 hipError_t launch_admit_requests(FilterDesc *desc, const EngineArgs &e, const RequestArgs *reqs,
                                  const int32_t *fstart, int32_t n_req, int32_t n_filters,

@@ -54,7 +54,8 @@ struct FilterDesc {
     const double *theta;   // [R] rate constants
     const double *t_obs;   // [T] observation times
     const double *y;       // [T * P] observations
-    const int32_t *x0;     // [U] initial counts
+    const int32_t *x0;     // [U] initial counts (lower bounds when x0_hi is set)
+    const int32_t *x0_hi;  // [U] upper bounds of random initial counts, or null
     int32_t *xa;           // [U][Hp] counts after even-numbered intervals
     int32_t *xb;           // [U][Hp] counts after odd-numbered intervals
     double *lw;            // [Hp] particle log-weights (particle-dependent part)
@@ -64,6 +65,8 @@ struct FilterDesc {
                            //      last observation time (cost prediction)
     double t0;             // start time
     double sigma;          // observation noise scale
+    double gain, bg_mean;  // fluorescence model: mean gain * x + bg_mean ...
+    double obs_s2, bg_s2;  // ... variance obs_s2 * x + bg_s2 (sigma^2, bg_sd^2)
     uint64_t seed;         // Philox key
     uint32_t theta_id;     // random-stream id of the rate vector
     uint32_t traj;         // trajectory index within its request
@@ -191,11 +194,12 @@ struct RequestArgs {
     const double *y;
     const double *t0;           // [M]
     const int32_t *x0;          // [M * U]
+    const int32_t *x0_hi;       // [M * U] upper bounds of random initial counts, or null
     int32_t *state;             // particle state arena of the request
     int32_t n_theta, M, H, Hp, U, R, P, obs_kind, group;
     int32_t precision;          // LIK_FP64 or LIK_FP32_MIXED (rates checked for its range)
     int32_t obs_species[LIK_MAX_OBSERVED];
-    double sigma;
+    double sigma, gain, bg_mean, bg_sd;
     uint64_t seed;
     uint32_t event_cap;
     int32_t base;               // first slot
@@ -211,6 +215,10 @@ size_t request_state_bytes(int64_t F, int32_t U, int32_t Hp);
 struct ReqSpan {
     int32_t base, n_theta, M, out;
 };
+// Random initial counts of the slots [base, base + F) that have them (the
+// others are left alone): each particle's draw into the buffer its first
+// interval reads, and identity ancestors.
+hipError_t launch_init_start(const FilterDesc *desc, int32_t base, int32_t F, hipStream_t s);
 hipError_t launch_admit_requests(FilterDesc *desc, const EngineArgs &e, const RequestArgs *reqs,
                                  const int32_t *fstart, int32_t n_req, int32_t n_filters,
                                  uint64_t *start_tick, hipStream_t s);

@@ -336,6 +336,9 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     float *pa0_p = wave_uniform(d.pa0);
     const int32_t *anc_p = wave_uniform(d.anc);
     const int32_t *x0_p = wave_uniform(d.x0);
+    // every particle starts at x0 (fixed initial counts, first interval);
+    // random initial counts were drawn into src with identity ancestors
+    const bool fixed_start = t == 0 && wave_uniform(d.x0_hi) == nullptr;
     const int refill_min = e.refill_min;
 
     using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
@@ -392,7 +395,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     // Which lane runs a particle, and when, never changes its result.
     const int npool = p1 - p0;
     const bool staged = npool > kPropBlock;
-    const bool ordered = staged && t > 0 && npool <= kSortPerLane * kPropBlock &&
+    const bool ordered = staged && !fixed_start && npool <= kSortPerLane * kPropBlock &&
                          U * npool + (npool + 1) / 2 <= kPoolLdsWords;
     uint16_t *order = reinterpret_cast<uint16_t *>(pool_x + U * npool);
     if (ordered) {
@@ -452,7 +455,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     } else if (staged) {
 #pragma unroll 1
         for (int q = lane; q < npool; q += kPropBlock) {
-            if (t == 0) {
+            if (fixed_start) {
 #pragma unroll
                 for (int u = 0; u < UMAX; ++u)
                     if (u < U) pool_x[u * npool + q] = x0_p[u];
@@ -483,7 +486,7 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     if (have) {
         if (staged) {
             load_lds(lane);
-        } else if (t == 0) {
+        } else if (fixed_start) {
 #pragma unroll
             for (int u = 0; u < UMAX; ++u) x[u] = (u < U) ? x0_p[u] : 0;
         } else {
@@ -742,9 +745,10 @@ __device__ __forceinline__ void propagate_persistent(const EngineArgs &e, const 
                     // the previous pool's entries it needed)
                     const int32_t *anc = d.anc;
                     const int32_t *x0 = d.x0;
+                    const bool fixed0 = t == 0 && d.x0_hi == nullptr;
 #pragma unroll 1
                     for (int q = lane; q < npool; q += kPropBlock) {
-                        if (t == 0) {
+                        if (fixed0) {
 #pragma unroll
                             for (int u = 0; u < UMAX; ++u)
                                 if (u < U) pool_x[u * npool + q] = x0[u];

@@ -50,7 +50,7 @@ struct Carve {
 struct ReqPlan {
     int32_t M, H, Hp, t_max, total, group;
     int64_t F;
-    size_t in_theta, in_ids, in_offs, in_t, in_y, in_t0, in_x0, state;  // offsets
+    size_t in_theta, in_ids, in_offs, in_t, in_y, in_t0, in_x0, in_x0h, state;  // offsets
 };
 
 }  // namespace
@@ -146,6 +146,7 @@ int lik_eval_requests(const lik_request *reqs, int32_t n_req, const lik_tuning *
         p.in_y = c.take((size_t)p.total * q.obs.n_observed * 8);
         p.in_t0 = c.take((size_t)p.M * 8);
         p.in_x0 = c.take((size_t)p.M * q.net->U * 4);
+        p.in_x0h = c.take(q.data.x0_hi ? (size_t)p.M * q.net->U * 4 : 0);
     }
     const size_t stage_bytes = c.off - o_stage;
     for (int k = 0; k < n_req; ++k) {
@@ -170,6 +171,7 @@ int lik_eval_requests(const lik_request *reqs, int32_t n_req, const lik_tuning *
             nt[g] = nets[g]->n8;
     }
     put(o_fstart, fstart.data(), ((size_t)n_req + 1) * 4);
+    bool any_random_start = false;
     for (int k = 0; k < n_req; ++k) {
         const lik_request &q = reqs[k];
         const ReqPlan &p = plan[(size_t)k];
@@ -181,6 +183,7 @@ int lik_eval_requests(const lik_request *reqs, int32_t n_req, const lik_tuning *
         put(p.in_y, q.data.y, (size_t)p.total * P * 8);
         put(p.in_t0, q.data.t0, (size_t)p.M * 8);
         put(p.in_x0, q.data.x0, (size_t)p.M * U * 4);
+        if (q.data.x0_hi) put(p.in_x0h, q.data.x0_hi, (size_t)p.M * U * 4);
         RequestArgs a;
         memset(&a, 0, sizeof(a));
         a.theta = (const double *)(dev + p.in_theta);
@@ -190,6 +193,8 @@ int lik_eval_requests(const lik_request *reqs, int32_t n_req, const lik_tuning *
         a.y = (const double *)(dev + p.in_y);
         a.t0 = (const double *)(dev + p.in_t0);
         a.x0 = (const int32_t *)(dev + p.in_x0);
+        a.x0_hi = q.data.x0_hi ? (const int32_t *)(dev + p.in_x0h) : nullptr;
+        any_random_start = any_random_start || q.data.x0_hi != nullptr;
         a.state = (int32_t *)(dev + p.state);
         a.n_theta = q.n_theta;
         a.M = p.M;
@@ -203,6 +208,9 @@ int lik_eval_requests(const lik_request *reqs, int32_t n_req, const lik_tuning *
         a.precision = precision;
         for (int j = 0; j < LIK_MAX_OBSERVED; ++j) a.obs_species[j] = j < P ? q.obs.species[j] : 0;
         a.sigma = q.obs.sigma;
+        a.gain = q.obs.gain;
+        a.bg_mean = q.obs.bg_mean;
+        a.bg_sd = q.obs.bg_sd;
         a.seed = q.seed;
         a.event_cap = (uint32_t)(q.event_cap ? q.event_cap : LIK_DEFAULT_EVENT_CAP);
         a.base = fstart[(size_t)k];
@@ -324,6 +332,10 @@ int lik_eval_requests(const lik_request *reqs, int32_t n_req, const lik_tuning *
                                     (const int32_t *)(dev + o_fstart), n_req, (int32_t)F,
                                     (uint64_t *)(dev + o_start), s);
         if (err != hipSuccess) { rc = hip_fail(err, "admit launch"); break; }
+        if (any_random_start && (err = launch_init_start(desc, 0, (int32_t)F, s)) != hipSuccess) {
+            rc = hip_fail(err, "initial-count launch");
+            break;
+        }
         if (flow) {
             if ((err = launch_flow_setup(e, fa, s)) != hipSuccess) { rc = hip_fail(err, "flow setup"); break; }
             const unsigned waves = (unsigned)std::max<int64_t>(items_max, 1);

@@ -100,7 +100,7 @@ struct Request {
     uint64_t seed, event_cap;
     std::vector<double> theta, t_obs, y, t0;
     std::vector<uint32_t> ids;
-    std::vector<int32_t> offsets, x0;
+    std::vector<int32_t> offsets, x0, x0_hi;  // x0_hi empty: fixed initial counts
     Clock::time_point submitted;
     bool has_deadline = false;  // its own time limit (lik_request.timeout_us)
     Clock::time_point deadline;
@@ -122,7 +122,7 @@ struct Request {
     size_t input_bytes() const {
         return align256(theta.size() * 8) + align256(ids.size() * 4) +
                align256(offsets.size() * 4) + align256(t_obs.size() * 8) + align256(y.size() * 8) +
-               align256(t0.size() * 8) + align256(x0.size() * 4);
+               align256(t0.size() * 8) + align256(x0.size() * 4) + align256(x0_hi.size() * 4);
     }
     size_t device_bytes() const {
         return input_bytes() + align256(request_state_bytes((int64_t)F(), net->U, Hp));
@@ -218,6 +218,7 @@ hipError_t admit(lik_server *S, Request &r) {
     a.y = (const double *)put(r.y.data(), r.y.size() * 8);
     a.t0 = (const double *)put(r.t0.data(), r.t0.size() * 8);
     a.x0 = (const int32_t *)put(r.x0.data(), r.x0.size() * 4);
+    a.x0_hi = (const int32_t *)put(r.x0_hi.data(), r.x0_hi.size() * 4);
     hipError_t err = hipMemcpyAsync(dev, pin, off, hipMemcpyHostToDevice, S->stream);
     if (err != hipSuccess) return err;
     a.state = (int32_t *)(dev + off);
@@ -233,11 +234,17 @@ hipError_t admit(lik_server *S, Request &r) {
     a.precision = r.precision;
     for (int k = 0; k < LIK_MAX_OBSERVED; ++k) a.obs_species[k] = r.obs.species[k];
     a.sigma = r.obs.sigma;
+    a.gain = r.obs.gain;
+    a.bg_mean = r.obs.bg_mean;
+    a.bg_sd = r.obs.bg_sd;
     a.seed = r.seed;
     a.event_cap = (uint32_t)(r.event_cap ? r.event_cap : LIK_DEFAULT_EVENT_CAP);
     a.base = (int32_t)r.slot;
     fill_reactant_tables(a, r.net->kind, r.net->s1, r.net->s2, r.net->R);
-    return launch_admit(S->desc, S->e, a, S->stream);
+    err = launch_admit(S->desc, S->e, a, S->stream);
+    if (err == hipSuccess && a.x0_hi)
+        err = launch_init_start(S->desc, (int32_t)r.slot, (int32_t)r.F(), S->stream);
+    return err;
 }
 
 int find_group(lik_server *S, lik_network *net, int precision) {
@@ -587,6 +594,7 @@ int lik_server_submit(lik_server_t S, const lik_request *q, uint64_t *ticket) {
     r->y.assign(q->data.y, q->data.y + (size_t)total * P);
     r->t0.assign(q->data.t0, q->data.t0 + M);
     r->x0.assign(q->data.x0, q->data.x0 + (size_t)M * U);
+    if (q->data.x0_hi) r->x0_hi.assign(q->data.x0_hi, q->data.x0_hi + (size_t)M * U);
     r->t_max = 0;
     for (int m = 0; m < M; ++m) r->t_max = std::max(r->t_max, r->offsets[m + 1] - r->offsets[m]);
     if (r->device_bytes() > S->arena_bytes || r->input_bytes() > S->opts.staging_bytes)

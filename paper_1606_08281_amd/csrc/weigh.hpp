@@ -77,12 +77,20 @@ __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c,
 // log p(y_t | x_j) without its particle-independent part (the "Compute
 // l_t^i" step): a sum over the observed components of -z^2/2, with z the
 // standardised residual of y (Gaussian) or of log y (log-normal, where a
-// count <= 0 has density zero).  logy[k] = log y_k for the log-normal model.
+// count <= 0 has density zero); for the fluorescence model, whose variance
+// v = sigma^2 x + bg_sd^2 depends on the count, -r^2/(2v) - log(v)/2 with
+// r = y - (gain x + bg_mean).  logy[k] = log y_k for the log-normal model.
 // obs_term adds component k's term to l; false (l = -inf, later components
 // skipped) for a log-normal observation of a count <= 0.
 __device__ __forceinline__ bool obs_term(const FilterDesc &d, int k, int cnt, const double *logy,
                                          const double *yt, double &l) {
-    if (d.obs_kind == LIK_OBS_LOGNORMAL) {
+    if (d.obs_kind == LIK_OBS_FLUORESCENCE) {
+        const double x = (double)cnt;
+        const double v = d.obs_s2 * x + d.bg_s2;
+        const double r = yt[k] - (d.gain * x + d.bg_mean);
+        l = l - 0.5 * ((r * r) / v);
+        l = l - 0.5 * dlog(v);
+    } else if (d.obs_kind == LIK_OBS_LOGNORMAL) {
         if (cnt <= 0) {
             l = -__builtin_inf();
             return false;
@@ -109,7 +117,9 @@ __device__ __forceinline__ double obs_logweight(const FilterDesc &d, const int32
 // mx: largest log-weight, S: sum of exp(l_j - mx).
 __device__ __forceinline__ double loglik_increment(const FilterDesc &d, double mx, double S,
                                                    const double *yt) {
-    const double per_comp = dlog(d.sigma) + 0.5 * dlog(2.0 * 3.141592653589793);
+    const double half_log_2pi = 0.5 * dlog(2.0 * 3.141592653589793);
+    const double per_comp =
+        d.obs_kind == LIK_OBS_FLUORESCENCE ? half_log_2pi : dlog(d.sigma) + half_log_2pi;
     double cst = -((double)d.P * per_comp);
     if (d.obs_kind == LIK_OBS_LOGNORMAL)
         for (int k = 0; k < d.P; ++k) cst = cst - dlog(yt[k]);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "liblik.so")
 LIK_OK, LIK_EINVAL, LIK_ENOMEM, LIK_EDEVICE, LIK_EUNSUPPORTED, LIK_ETIMEOUT = 0, -1, -2, -3, -4, -5
 STATUS_OK, STATUS_EVENT_CAP, STATUS_COUNT_OVERFLOW, STATUS_BAD_THETA = 0, 1, 2, 3
 STATUS_SCHEDULER, STATUS_CANCELLED, STATUS_TIMED_OUT = 4, 5, 6
-OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
+OBS_GAUSSIAN, OBS_LOGNORMAL, OBS_FLUORESCENCE = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
 FLAG_GRAPH = 1
@@ -39,13 +39,15 @@ class LikError(RuntimeError):
 
 class ObsModel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_observed", ctypes.c_int32),
-                ("species", ctypes.c_int32 * MAX_OBSERVED), ("sigma", ctypes.c_double)]
+                ("species", ctypes.c_int32 * MAX_OBSERVED), ("sigma", ctypes.c_double),
+                ("gain", ctypes.c_double), ("bg_mean", ctypes.c_double),
+                ("bg_sd", ctypes.c_double)]
 
 
 class Data(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_int32), ("obs_offsets", ctypes.c_void_p),
                 ("t_obs", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t0", ctypes.c_void_p),
-                ("x0", ctypes.c_void_p)]
+                ("x0", ctypes.c_void_p), ("x0_hi", ctypes.c_void_p)]
 
 
 class EvalOpts(ctypes.Structure):
@@ -237,12 +239,17 @@ class Network:
 
 
 def obs_model(kind, observed, sigma):
+    """sigma: the noise scale, or for OBS_FLUORESCENCE the tuple
+    (sigma, gain, bg_mean, bg_sd)."""
     o = ObsModel()
     o.kind = int(kind)
     o.n_observed = len(observed)
     for k, s in enumerate(observed):
         o.species[k] = int(s)
-    o.sigma = float(sigma)
+    if isinstance(sigma, (tuple, list)):
+        o.sigma, o.gain, o.bg_mean, o.bg_sd = (float(v) for v in sigma)
+    else:
+        o.sigma = float(sigma)
     return o
 
 
@@ -259,7 +266,16 @@ def pack_trajectories(trajectories, P):
         "t0": np.array([float(tr.get("t0", 0.0)) for tr in trajectories], dtype=np.float64),
         "x0": np.ascontiguousarray(np.stack([np.asarray(tr["x0"], np.int32)
                                              for tr in trajectories])),
-    }
+    } | ({"x0_hi": np.ascontiguousarray(np.stack([np.asarray(tr.get("x0_hi", tr["x0"]), np.int32)
+                                                  for tr in trajectories]))}
+         if any("x0_hi" in tr for tr in trajectories) else {})
+
+
+def _data(M, d, ptr):
+    """Data struct over the arrays of a pack_trajectories dict d (ptr: the
+    address of one of its arrays)."""
+    return Data(M, ptr(d["obs_offsets"]), ptr(d["t_obs"]), ptr(d["y"]), ptr(d["t0"]),
+                ptr(d["x0"]), ptr(d["x0_hi"]) if "x0_hi" in d else None)
 
 
 def eval_batch(net, obs_kind, observed, sigma, theta, trajectories, n_particles, seed,
@@ -272,8 +288,7 @@ def eval_batch(net, obs_kind, observed, sigma, theta, trajectories, n_particles,
     P = len(observed)
     d = pack_trajectories(trajectories, P)
     M = len(trajectories)
-    data = Data(M, _ptr(d["obs_offsets"]), _ptr(d["t_obs"]), _ptr(d["y"]), _ptr(d["t0"]),
-                _ptr(d["x0"]))
+    data = _data(M, d, _ptr)
     ids = None if theta_ids is None else np.ascontiguousarray(theta_ids, dtype=np.uint32)
     opts = EvalOpts(int(precision), int(kernel), int(event_cap), _ptr(ids))
     om = obs_model(obs_kind, observed, sigma)
@@ -301,14 +316,13 @@ def eval_batch_device(net, obs_kind, observed, sigma, theta_dev, data_dev, offse
                       theta_ids_dev=None):
     """lik_eval_batch_device on caller-owned device tensors: theta_dev
     [n_theta * R] float64; data_dev a dict of device tensors obs_offsets,
-    t_obs, y, t0, x0 (as pack_trajectories lays them out); offsets_host the
-    host copy of obs_offsets; loglik_dev / status_dev outputs; workspace_dev
-    at least lik_workspace_size bytes; stream a torch stream.  Enqueues and
+    t_obs, y, t0, x0 and, for random initial counts, x0_hi (as
+    pack_trajectories lays them out); offsets_host the host copy of
+    obs_offsets; loglik_dev / status_dev outputs; workspace_dev at least
+    lik_workspace_size bytes; stream a torch stream.  Enqueues and
     returns."""
     n_theta = theta_dev.numel() // net.R
-    data = Data(len(offsets_host) - 1, data_dev["obs_offsets"].data_ptr(),
-                data_dev["t_obs"].data_ptr(), data_dev["y"].data_ptr(), data_dev["t0"].data_ptr(),
-                data_dev["x0"].data_ptr())
+    data = _data(len(offsets_host) - 1, data_dev, lambda t: t.data_ptr())
     opts = EvalOpts(int(precision), int(kernel), int(event_cap),
                     None if theta_ids_dev is None else theta_ids_dev.data_ptr(), 0, 0)
     om = obs_model(obs_kind, observed, sigma)
@@ -345,9 +359,7 @@ class DeviceBatch:
         self.event_cap = int(event_cap)
         self.kernel = int(kernel)
         self.flags = FLAG_GRAPH if graph else 0
-        self.data = Data(self.M, self.dev["obs_offsets"].data_ptr(), self.dev["t_obs"].data_ptr(),
-                         self.dev["y"].data_ptr(), self.dev["t0"].data_ptr(),
-                         self.dev["x0"].data_ptr())
+        self.data = _data(self.M, self.dev, lambda t: t.data_ptr())
         self.ws_bytes = int(lib().lik_workspace_size(net.handle, self.n_theta, self.M, self.H))
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         self.loglik = torch.empty(self.n_theta, dtype=torch.float64, device=device)
@@ -428,8 +440,7 @@ def _request(net, obs_kind, observed, sigma, theta, trajectories, n_particles, s
     q.n_theta = theta.shape[0]
     q.theta = theta.ctypes.data
     q.theta_ids = _ptr(ids)
-    q.data = Data(len(trajectories), _ptr(d["obs_offsets"]), _ptr(d["t_obs"]), _ptr(d["y"]),
-                  _ptr(d["t0"]), _ptr(d["x0"]))
+    q.data = _data(len(trajectories), d, _ptr)
     q.n_particles = int(n_particles)
     q.reserved = 0
     q.seed = int(seed) & (2**64 - 1)
@@ -524,8 +535,7 @@ class Server:
         q.n_theta = theta.shape[0]
         q.theta = theta.ctypes.data
         q.theta_ids = _ptr(ids)
-        q.data = Data(len(trajectories), _ptr(d["obs_offsets"]), _ptr(d["t_obs"]), _ptr(d["y"]),
-                      _ptr(d["t0"]), _ptr(d["x0"]))
+        q.data = _data(len(trajectories), d, _ptr)
         q.n_particles = int(n_particles)
         q.reserved = 0
         q.seed = int(seed) & (2**64 - 1)

@@ -17,12 +17,19 @@ Workloads:
     translation and protein decay): G_off <-> G_on, G_on -> G_on + M, M -> 0,
     M -> M + P, P -> 0; log y = log P + N(0, 0.1^2) at t = 2, 4, ..., 100.
   * a seeded random mass-action network with 20 species and 40 reactions.
+  * Lac-Gfp (Supplementary "LacGfp example"): 9 species, 18 mass-action
+    reactions, 18 parameters (the LACI degradation rate rises linearly with
+    the inducer, theta_4 + theta_5 [IPTG]; GFP and mature GFP share the
+    degradation rate theta_17), random initial counts, and fluorescence of
+    mature GFP observed with per-molecule normal signal plus background.
 """
+import functools
+
 import numpy as np
 
 SEED_NET, SEED_DATA, SEED_NOISE, SEED_THETA, SEED_FILTER = 1, 2, 3, 4, 5
 
-OBS_GAUSSIAN, OBS_LOGNORMAL = 0, 1
+OBS_GAUSSIAN, OBS_LOGNORMAL, OBS_FLUORESCENCE = 0, 1, 2
 
 
 class Network:
@@ -36,17 +43,38 @@ class Network:
         self.R, self.U = self.orders.shape
         self.reaction_names = reaction_names or [f"R{r}" for r in range(self.R)]
 
+    def propensity_factors(self, X):
+        """propensity_factor for every row of X [K, U]: [K, R]."""
+        self.propensity_factor(X[0])   # builds the index tables
+        X = np.asarray(X, dtype=np.float64)
+        a = X[:, self._first]
+        h = np.where(self._order == 0, 1.0, a)
+        h = np.where(self._homo, a * (a - 1.0) / 2.0, h)
+        return np.where(self._second >= 0, h * X[:, np.maximum(self._second, 0)], h)
+
     def propensity_factor(self, x):
-        """Mass-action combinatorial factors prod_u C(x_u, p_ru) (float64)."""
-        h = np.ones(self.R)
-        for r in range(self.R):
-            for u in range(self.U):
-                p = self.orders[r, u]
-                if p == 1:
-                    h[r] *= x[u]
-                elif p == 2:
-                    h[r] *= x[u] * (x[u] - 1) / 2.0
-        return h
+        """Mass-action combinatorial factors prod_u C(x_u, p_ru) (float64):
+        products of exact integers, so any evaluation order gives the same
+        values."""
+        if not hasattr(self, "_first"):
+            first = np.zeros(self.R, dtype=np.int64)
+            second = np.full(self.R, -1, dtype=np.int64)
+            homo = np.zeros(self.R, dtype=bool)
+            order = self.orders.sum(axis=1)
+            for r in range(self.R):
+                us = np.nonzero(self.orders[r])[0]
+                if len(us):
+                    first[r] = us[0]
+                if len(us) == 2:
+                    second[r] = us[1]
+                homo[r] = len(us) == 1 and self.orders[r, us[0]] == 2
+            self._first, self._second, self._homo, self._order = first, second, homo, order
+        x = np.asarray(x, dtype=np.float64)
+        a = x[self._first]
+        h = np.where(self._order == 0, 1.0, a)
+        h = np.where(self._homo, a * (a - 1.0) / 2.0, h)
+        two = self._second >= 0
+        return np.where(two, h * x[np.maximum(self._second, 0)], h)
 
 
 def immigration_death():
@@ -109,6 +137,43 @@ def first_reaction_path(net, c, x0, t_points, rng, max_events=50_000_000):
     return out
 
 
+def first_reaction_paths(net, c, x0s, t_points, rng, max_events=50_000_000):
+    """first_reaction_path for several paths at once (rows of x0s), stepped
+    together: every unfinished path fires its next reaction per step.
+    Returns int64 [K, len(t_points), U]."""
+    X = np.array(x0s, dtype=np.int64)
+    K = X.shape[0]
+    t = np.zeros(K)
+    k = np.zeros(K, dtype=np.int64)
+    T = len(t_points)
+    tp = np.append(np.asarray(t_points, dtype=np.float64), np.inf)
+    out = np.zeros((K, T, net.U), dtype=np.int64)
+    nu = net.stoich.astype(np.int64)
+    live = np.arange(K)
+    steps = 0
+    while len(live):
+        a = c * net.propensity_factors(X[live])
+        pos = a > 0
+        with np.errstate(divide="ignore"):
+            waits = np.where(pos, rng.exponential(1.0, a.shape) / np.where(pos, a, 1.0), np.inf)
+        r = np.argmin(waits, axis=1)
+        t_next = t[live] + waits[np.arange(len(live)), r]
+        # observations passed before the next event keep the current counts
+        for i in np.nonzero(tp[k[live]] < t_next)[0]:
+            p = live[i]
+            while tp[k[p]] < t_next[i]:
+                out[p, k[p]] = X[p]
+                k[p] += 1
+        fire = np.isfinite(t_next)
+        X[live[fire]] += nu[r[fire]]
+        t[live] = t_next
+        live = live[k[live] < T]
+        steps += 1
+        if steps > max_events:
+            raise RuntimeError("data simulation exceeded its event budget")
+    return out
+
+
 def log_uniform(rng, lo, hi, n):
     lo = np.broadcast_to(np.asarray(lo, dtype=np.float64), (len(np.atleast_1d(lo)),))
     hi = np.broadcast_to(np.asarray(hi, dtype=np.float64), lo.shape)
@@ -125,7 +190,9 @@ class Workload:
         self.net = net
         self.obs_kind = obs_kind
         self.observed = list(observed)
-        self.sigma = float(sigma)
+        # the noise scale, or (sigma, gain, bg_mean, bg_sd) for the fluorescence model
+        self.sigma = tuple(float(v) for v in sigma) if isinstance(sigma, (tuple, list)) \
+            else float(sigma)
         self.theta = np.ascontiguousarray(theta, dtype=np.float64)
         self.trajectories = trajectories
         self.n_particles = int(n_particles)
@@ -324,3 +391,102 @@ def random_network_workload(n_theta=4096, n_particles=512, n_obs=100, events_per
     traj = {"t_obs": t_obs, "y": y, "t0": 0.0, "x0": x0, "x_true": states}
     return Workload(name, net, OBS_GAUSSIAN, [0, 1], 10.0, theta, [traj],
                     n_particles, truth=truth)
+
+
+# ---------------------------------------------------------------------------
+# Lac-Gfp (Supplementary "LacGfp example": species and initial-distribution
+# table, reaction list, prior table, observation model)
+# ---------------------------------------------------------------------------
+LACGFP_SPECIES = ["lacI", "LACI", "LACI2", "PLac", "O2Lac", "O4Lac", "gfp", "GFP", "mGFP"]
+# theta* of the prior table
+LACGFP_TRUTH = np.array([1.215, 7.430, 1.439, 3.971, 1.173, 1716.683, 6.282, 0.433, 0.679,
+                         173.576, 0.623, 119.232, 0.120, 0.006, 1.673, 32.318, 1.196, 2.102])
+# prior intervals (log-uniform); theta_10's upper bound is read as 1600 (the
+# table prints 1.600 with theta* = 173.576 inside the interval)
+LACGFP_PRIOR_LO = np.array([1, 0.1, 1, 0.1, 1, 0.16, 0.1, 0.0016, 0.1, 0.16, 0.1, 1, 0.1, 1e-5,
+                            0.1, 1, 0.1, 0.1])
+LACGFP_PRIOR_HI = np.array([50, 30, 50, 20, 100, 3000, 20, 1.6, 20, 1600, 20, 150, 15, 1, 20, 50,
+                            20, 20], dtype=np.float64)
+LACGFP_IPTG = 10.0
+# initial counts uniform on the integers lo..hi (lacI, LACI, O4Lac random)
+LACGFP_X0_LO = np.array([0, 0, 0, 0, 0, 50, 0, 0, 0], dtype=np.int32)
+LACGFP_X0_HI = np.array([5, 10, 0, 0, 0, 70, 0, 0, 0], dtype=np.int32)
+# fluorescence: 22.85 per molecule, sd 5.72 per molecule; the background is
+# read as normal (the paper's is an empirical flow-cytometry distribution)
+LACGFP_GAIN, LACGFP_SD = 22.85, 5.72
+LACGFP_BG_MEAN, LACGFP_BG_SD = 400.0, 120.0
+
+
+def lacgfp():
+    """The 9-species, 18-reaction Lac-Gfp network, reactions in the paper's
+    order."""
+    lacI, LACI, LACI2, PLac, O2Lac, O4Lac, gfp, GFP, mGFP = range(9)
+    reac = [({}, {lacI: 1}), ({lacI: 1}, {}), ({lacI: 1}, {lacI: 1, LACI: 1}), ({LACI: 1}, {}),
+            ({LACI: 2}, {LACI2: 1}), ({LACI2: 1}, {LACI: 2}),
+            ({LACI2: 1, PLac: 1}, {O2Lac: 1}), ({O2Lac: 1}, {LACI2: 1, PLac: 1}),
+            ({O2Lac: 2}, {O4Lac: 1}), ({O4Lac: 1}, {O2Lac: 2}),
+            ({PLac: 1}, {PLac: 1, gfp: 1}), ({O2Lac: 1}, {O2Lac: 1, gfp: 1}),
+            ({O4Lac: 1}, {O4Lac: 1, gfp: 1}), ({gfp: 1}, {}), ({gfp: 1}, {gfp: 1, GFP: 1}),
+            ({GFP: 1}, {}), ({GFP: 1}, {mGFP: 1}), ({mGFP: 1}, {})]
+    U, R = 9, len(reac)
+    orders = np.zeros((R, U), dtype=np.int32)
+    stoich = np.zeros((R, U), dtype=np.int32)
+    for r, (cons, prod) in enumerate(reac):
+        for u, v in cons.items():
+            orders[r, u] = v
+            stoich[r, u] -= v
+        for u, v in prod.items():
+            stoich[r, u] += v
+    return Network("lac-gfp", LACGFP_SPECIES, orders, stoich, [f"R{r + 1}" for r in range(R)])
+
+
+def lacgfp_rates(theta, iptg=LACGFP_IPTG):
+    """Rate constants c [n, 18] of parameter vectors theta [n, 18]: reaction 4
+    degrades LACI at theta_4 + theta_5 [IPTG], reactions 5-17 take theta_6 ..
+    theta_18, and reaction 18 (mature GFP degradation) shares theta_17."""
+    th = np.atleast_2d(np.asarray(theta, dtype=np.float64))
+    return np.concatenate([th[:, 0:3], (th[:, 3] + iptg * th[:, 4])[:, None], th[:, 5:18],
+                           th[:, 16:17]], axis=1)
+
+
+@functools.lru_cache(maxsize=4)
+def _lacgfp_data(n_traj, n_obs, dt):
+    """The Lac-Gfp data paths (exact, ~1.5e5 events each: simulated once per
+    process and argument set)."""
+    net = lacgfp()
+    t_obs = dt * np.arange(1, n_obs + 1, dtype=np.float64)
+    rng = np.random.Generator(np.random.PCG64(SEED_DATA))
+    nrng = np.random.Generator(np.random.PCG64(SEED_NOISE))
+    c_true = lacgfp_rates(LACGFP_TRUTH)[0]
+    x0s = np.stack([rng.integers(LACGFP_X0_LO, LACGFP_X0_HI + 1) for _ in range(n_traj)])
+    paths = first_reaction_paths(net, c_true, x0s, t_obs, rng)
+    trajs = []
+    for x0, states in zip(x0s.astype(np.int32), paths):
+        x = states[:, 8].astype(np.float64)
+        y = (nrng.normal(LACGFP_GAIN * x, LACGFP_SD * np.sqrt(x))
+             + nrng.normal(LACGFP_BG_MEAN, LACGFP_BG_SD, n_obs))
+        trajs.append({"t_obs": t_obs, "y": y.reshape(-1, 1), "t0": 0.0,
+                      "x0": LACGFP_X0_LO.copy(), "x0_hi": LACGFP_X0_HI.copy(),
+                      "x_true": states, "x0_drawn": x0})
+    return trajs
+
+
+def lacgfp_workload(n_theta=256, n_traj=5, n_obs=29, dt=1.0, n_particles=200, theta=None):
+    """Lac-Gfp batch: rate vectors from parameters log-uniform on the prior
+    box (or the given parameters), n_traj paths simulated exactly (first-
+    reaction method) at theta* from random initial counts, mature GFP observed
+    at dt, 2dt, ..., n_obs dt through the fluorescence model.  w.params holds
+    the parameter vectors, w.theta their rate constants."""
+    net = lacgfp()
+    c_true = lacgfp_rates(LACGFP_TRUTH)[0]
+    trajs = [{k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in tr.items()}
+             for tr in _lacgfp_data(int(n_traj), int(n_obs), float(dt))]
+    if theta is None:
+        theta = log_uniform(np.random.Generator(np.random.PCG64(SEED_THETA)),
+                            LACGFP_PRIOR_LO, LACGFP_PRIOR_HI, n_theta)
+    params = np.atleast_2d(np.asarray(theta, dtype=np.float64))
+    w = Workload("lac-gfp", net, OBS_FLUORESCENCE, [8],
+                 (LACGFP_SD, LACGFP_GAIN, LACGFP_BG_MEAN, LACGFP_BG_SD), lacgfp_rates(params),
+                 trajs, n_particles, truth=c_true)
+    w.params = params
+    return w

@@ -74,6 +74,10 @@ def _args(**kw):
 @pytest.mark.parametrize("bad", [
     dict(sigma=0.0), dict(sigma=-1.0), dict(observed=[1]), dict(obs_kind=7),
     dict(n_particles=0), dict(n_particles=4097), dict(precision=5),
+    # fluorescence model: (sigma, gain, bg_mean, bg_sd)
+    dict(obs_kind=2, sigma=(1.0, 2.0, 0.0, 0.0)), dict(obs_kind=2, sigma=(-1.0, 2.0, 0.0, 1.0)),
+    dict(obs_kind=2, sigma=(1.0, float("inf"), 0.0, 1.0)),
+    dict(obs_kind=2, sigma=(1.0, 2.0, float("nan"), 1.0)),
 ])
 def test_host_validation_rejects_before_device_work(bad):
     wl, a = _args(**bad)
@@ -98,6 +102,10 @@ def test_observation_checks():
     tr["x0"] = np.array([-1], np.int32)
     with pytest.raises(lik.LikError):
         lik.eval_batch(net, **dict(a, trajectories=[tr]))
+    for hi in (-1, (1 << 30) + 1):     # random initial counts: x0 <= x0_hi <= 2^30
+        tr = dict(wl.trajectories[0], x0=np.array([0], np.int32), x0_hi=np.array([hi], np.int32))
+        with pytest.raises(lik.LikError):
+            lik.eval_batch(net, **dict(a, trajectories=[tr]))
 
 
 def test_empty_batch_is_ok_without_device():
