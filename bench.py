@@ -8,10 +8,13 @@ filter particles x 50 log-normal observations, binary64.  --workload random:
 the seeded 20-species, 40-reaction mass-action network, 4,096 rate vectors x
 1 trajectory x 512 particles x 100 Gaussian observations, at the observation
 interval where the median rate vector realises 1e4 SSA events per particle
-per interval (~2.4e12 events per batch).  Inputs are resident in device
+per interval (~2.4e12 events per batch).  --workload lacgfp: the Lac-Gfp
+model, 1,024 parameter vectors around theta* x 5 trajectories x 200
+particles x 29 fluorescence observations, random initial counts.  Inputs are
+resident in device
 memory before the timed region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload telegraph|random]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload telegraph|random|lacgfp]
                   [--precision 0|1] [--no-cpu-baseline] [--no-serving]
 
 The VALU roofline is priced with the lane-op issue slots per SSA event that
@@ -142,6 +145,12 @@ def workload(name):
                 "filter particles x 100 Gaussian observations (sigma 10, species 0 and 1) at the "
                 "interval where the median theta realises 1e4 SSA events per particle per "
                 "interval", "random20x40_4096x1x512x100")
+    if name == "lacgfp":
+        return (W.lacgfp_workload(theta=W.lacgfp_population(1024), n_traj=5, n_particles=200),
+                "Lac-Gfp, 9 species x 18 mass-action reactions, 18 parameters log-normal (sd 0.3) "
+                "around theta* (a late level of the sampler's population); 1024 theta x 5 "
+                "trajectories x 200 filter particles x 29 fluorescence observations of mature "
+                "GFP; initial counts uniform per particle", "lacgfp_1024x5x200x29")
     raise SystemExit(f"unknown workload {name!r}")
 
 
@@ -156,7 +165,7 @@ def main():
                          "kernels launched once per request)")
     ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--precision", type=int, default=0)
-    ap.add_argument("--workload", default="telegraph", choices=["telegraph", "random"])
+    ap.add_argument("--workload", default="telegraph", choices=["telegraph", "random", "lacgfp"])
     ap.add_argument("--graph", action="store_true",
                     help="replay the step's launch sequence as a captured HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -471,6 +471,13 @@ def _lacgfp_data(n_traj, n_obs, dt):
     return trajs
 
 
+def lacgfp_population(n_theta, spread=0.3):
+    """Parameter vectors log-normal around theta* (sd `spread` per log
+    parameter): the shape of a late level of the sampler's population."""
+    rng = np.random.Generator(np.random.PCG64(SEED_THETA))
+    return LACGFP_TRUTH * np.exp(rng.normal(0.0, spread, (n_theta, len(LACGFP_TRUTH))))
+
+
 def lacgfp_workload(n_theta=256, n_traj=5, n_obs=29, dt=1.0, n_particles=200, theta=None):
     """Lac-Gfp batch: rate vectors from parameters log-uniform on the prior
     box (or the given parameters), n_traj paths simulated exactly (first-
