@@ -14,7 +14,7 @@ particles x 29 fluorescence observations, random initial counts.  Inputs are
 resident in device
 memory before the timed region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload telegraph|random|lacgfp]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload telegraph|random|lacgfp|erk]
                   [--precision 0|1] [--no-cpu-baseline] [--no-serving]
 
 The VALU roofline is priced with the lane-op issue slots per SSA event that
@@ -154,6 +154,99 @@ def workload(name):
     raise SystemExit(f"unknown workload {name!r}")
 
 
+def ode_step_work(spec):
+    """(binary64 operations, lane-op issue slots) of one Dormand-Prince step
+    attempt of a term-list model, a model count: six right-hand sides (the
+    seventh stage is the next step's first) and, per species, the stage
+    combinations (2i - 1 operations for stage i = 2..6), the fifth-order
+    update (11), the error estimate (12) and its scaled norm (4, one of them a
+    divide).  Slots: one per operation, the IEEE divide sequence SLOTS_DIV_F64,
+    and the step-size factor's log and exp (~65)."""
+    ops = divs = 0
+    for T in spec["terms"]:
+        ops += 1 if T.get("rate_param", -1) >= 0 else 0
+        for kind, _, _ in T.get("factors", []):
+            ops += {0: 1, 1: 3, 2: 4, 3: 4, 4: 1}[kind]
+            divs += kind in (1, 2, 3)
+        ops += (T.get("frm", -1) >= 0) + (T.get("to", -1) >= 0)
+    ops, divs = 6 * ops, 6 * divs
+    ops += spec["U"] * ((3 + 5 + 7 + 9 + 11) + 11 + 12 + 4)
+    divs += spec["U"]
+    return ops, ops - divs + SLOTS_DIV_F64 * divs + 65
+
+
+def bench_erk(args):
+    """The deterministic (ODE) likelihood of the Egf-Ras-Raf-Mek-Erk model:
+    lik_ode_eval over a population of parameter vectors, six input patterns
+    each.  The call takes host pointers, so the step includes its input copies
+    and allocation; the roofline uses the solver kernel's own HIP-event time."""
+    import torch
+    from paper_1606_08281_amd import lik
+    from paper_1606_08281_amd import workloads as W
+    torch.cuda.set_device(0)
+    n = 65536
+    wl = W.erk_workload(n_theta=n, spread=0.3)
+    model = lik.OdeModel(wl["spec"])
+    trajs = wl["trajectories"]
+    kw = dict(rtol=1e-6, atol=1e-9, max_steps=100000)
+    say = lambda m: print("[bench]", m, flush=True, file=sys.stderr)  # noqa: E731
+    say(f"erk workload ready: {n} theta x {len(trajs)} input patterns x 60 FRET observations")
+    for w in range(args.warmup):
+        lik.ode_eval(model, wl["theta"], trajs, **kw)
+        say(f"warmup {w + 1}/{args.warmup} done")
+    lik.timing_read()
+    lik.timing_enable(True)
+    t0 = time.perf_counter()
+    steps_total = 0
+    for k in range(args.steps):
+        ll, st, steps = lik.ode_eval(model, wl["theta"], trajs, steps=True, **kw)
+        steps_total += int(steps.sum())
+        say(f"step {k + 1}/{args.steps} done")
+    elapsed = time.perf_counter() - t0
+    lik.timing_enable(False)
+    tm = lik.timing_read()
+    flops, slots = ode_step_work(wl["spec"])
+    kernel_s = tm["propagate_ms"] / 1e3
+    achieved = steps_total * slots / kernel_s / 1e12
+    out = {
+        "metric": "deterministic likelihood evals/s", "value": n * args.steps / elapsed,
+        "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Egf-Ras-Raf-Mek-Erk ODE model (14 species, 17 flux terms, 36 "
+                               "parameters log-normal sd 0.3 around a reference point), 6 "
+                               "piecewise-constant EGF input patterns x 60 FRET observations; "
+                               "Dormand-Prince 5(4), rtol 1e-6, atol 1e-9", "n_theta": n},
+        "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
+        "solver_steps_per_eval": steps_total / (n * args.steps),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                     "unit": "Tlane-op/s", "frac": achieved / (VALU_PEAK_LANE_OPS / 1e12),
+                     "traffic": None,
+                     "fp64_tflops": steps_total * flops / kernel_s / 1e12,
+                     "kernel": "lik_ode_spec (the model compiled with hipRTC): one lane per "
+                               "(theta, input pattern)",
+                     "basis": "lane-op slots of the step attempts (model count, "
+                              f"{slots} per attempt; {flops} binary64 operations) over the "
+                              "solver kernel's HIP-event time",
+                     "avg_launch_ms": tm["propagate_ms"] / max(tm["propagate_launches"], 1)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        usable, machine, model_name = host_cores()
+        nth = max(1, min(16, usable))
+        idx = np.random.default_rng(7).permutation(n)[:4096]
+        P = oracle.OdeProblem(wl["spec"], wl["theta"][idx], trajs, **kw)
+        c0 = time.perf_counter()
+        oracle.ode_eval(P, nthreads=nth)
+        ct = time.perf_counter() - c0
+        out["cpu_baseline"] = {"value": len(idx) / ct, "unit": "deterministic likelihood evals/s",
+                               "cores": nth, "kind": "oracle",
+                               "sample": f"4096 of the same theta (seeded pick), all 6 patterns; "
+                                         f"{ct:.1f} s wall on {nth} threads"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,7 +258,8 @@ def main():
                          "kernels launched once per request)")
     ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--precision", type=int, default=0)
-    ap.add_argument("--workload", default="telegraph", choices=["telegraph", "random", "lacgfp"])
+    ap.add_argument("--workload", default="telegraph",
+                    choices=["telegraph", "random", "lacgfp", "erk"])
     ap.add_argument("--graph", action="store_true",
                     help="replay the step's launch sequence as a captured HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -186,6 +280,9 @@ def main():
               "single MI355X (see the design notes for how it shards); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "erk":
+        bench_erk(args)
+        return
 
     import torch
     from paper_1606_08281_amd import lik

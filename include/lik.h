@@ -65,6 +65,8 @@ extern "C" {
                                        environment variable LIK_FLOW_STALL_US for tests) */
 #define LIK_STATUS_CANCELLED 5      /* server: the request was cancelled (lik_server_cancel) */
 #define LIK_STATUS_TIMED_OUT 6      /* server: the request's own time limit passed first */
+#define LIK_STATUS_STEP_LIMIT 7     /* deterministic model: the solver's step limit was reached */
+#define LIK_STATUS_NONFINITE 8      /* deterministic model: a state or observation mean not finite */
 
 /* observation noise models (Sec. "General Task": Y ~ p(. | X, theta)) */
 #define LIK_OBS_GAUSSIAN 0  /* y = x_s + N(0, sigma^2) per observed species s */
@@ -460,7 +462,8 @@ int lik_server_destroy(lik_server_t srv);
  * thread-safe: for single-threaded benchmark drivers.
  */
 typedef struct lik_timing {
-    double propagate_ms;        /* summed duration of SSA propagation launches */
+    double propagate_ms;        /* summed duration of SSA propagation launches (and of
+                                   lik_ode_eval's solver launches) */
     int64_t propagate_launches;
     double weigh_ms;            /* summed duration of weight/resampling launches */
     int64_t weigh_launches;
@@ -483,6 +486,128 @@ int lik_autotune_device(lik_network_t net, const lik_obs_model *obs, const lik_e
                         const int32_t *obs_offsets_host, int32_t n_particles, uint64_t seed,
                         double *loglik_out, int32_t *status_out, void *workspace,
                         size_t workspace_bytes, void *stream, lik_tuning *chosen);
+
+/* ------------------------------------------------------------------------ */
+/* Deterministic models                                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * The deterministic formulation (Sec. "Chemical Reaction Networks": the state
+ * follows dX/dt = f(X, t, theta)): no particle filter; the likelihood of a
+ * trajectory is the noise density of its observations around the ODE solution
+ * (Results, deterministic models; Supplementary "Egf-Ras-Raf-Mek-Erk model"),
+ * summed over trajectories per theta.
+ *
+ * f is a sum of fluxes ("terms").  Term k moves one unit from species `from`
+ * to species `to` (-1: none) at the rate
+ *   v_k = rate_scale * theta[rate_param] * prod_f phi_f   (rate_param -1: rate_scale alone)
+ * with factors phi of kind
+ *   LIK_ODE_SPECIES     x_u
+ *   LIK_ODE_SATURATING  x_u / (theta[param] + x_u)         (Michaelis-Menten)
+ *   LIK_ODE_HILL2       x_u^2 / (theta[param] + x_u^2)     (activating, Hill 2)
+ *   LIK_ODE_REPRESS2    theta[param] / (theta[param] + x_u^2) (repressing, Hill 2)
+ *   LIK_ODE_INPUT       u(t), the trajectory's piecewise-constant input
+ * (a Hill constant K enters as K^2 through the parameter map of the caller).
+ * dx_u/dt sums -v_k over the terms leaving u and +v_k over those entering it,
+ * in term order.
+ *
+ * Initial state of trajectory m: x_u(t0) = theta[x0_param[u]] where
+ * x0_param[u] >= 0, else the trajectory's x0[u].
+ *
+ * Observation (one value per time point): y ~ N(g(x), sd^2), sd =
+ * theta[sd_param] (or sd_const when sd_param is -1), with
+ *   LIK_ODE_OBS_SPECIES  g = x_{obs_species}
+ *   LIK_ODE_OBS_FRET     g = lambda (E fAA x_a / ((x_b + (1 - E) x_a) fDD) + bg),
+ *                        x_a = x_{obs_species} (active), x_b = x_{obs_species2},
+ *                        lambda, bg, E, fAA, fDD = theta[fret_param[0..4]]
+ *                        (the FRET ratio of the Egf-Ras-Raf-Mek-Erk example).
+ *
+ * Solver (the paper names none): the Dormand-Prince 5(4) pair with local
+ * extrapolation and first-same-as-last stages; a step is accepted when
+ * max_u |e_u| / (atol + rtol max(|x_u|, |x_u new|)) <= 1, and the next step is
+ * h * min(5, max(0.2, 0.9 err^(-1/5))) (err^(-1/5) from the library's log and
+ * exp); steps end exactly at every observation time and input breakpoint.
+ * LIK_STATUS_STEP_LIMIT if a trajectory needs more than max_steps steps or its
+ * step falls below 1e-12 of its time span; LIK_STATUS_NONFINITE if the state
+ * or g is not finite.  A theta with a non-finite entry, or a negative rate,
+ * Hill constant, sd or initial value, is LIK_STATUS_BAD_THETA.
+ */
+#define LIK_ODE_MAX_SPECIES 32
+#define LIK_ODE_MAX_TERMS 128
+#define LIK_ODE_MAX_PARAMS 128
+#define LIK_ODE_MAX_FACTORS 3
+
+#define LIK_ODE_SPECIES 0
+#define LIK_ODE_SATURATING 1
+#define LIK_ODE_HILL2 2
+#define LIK_ODE_REPRESS2 3
+#define LIK_ODE_INPUT 4
+
+#define LIK_ODE_OBS_SPECIES 0
+#define LIK_ODE_OBS_FRET 1
+
+typedef struct lik_ode_term {
+    int32_t from, to;        /* species indices, or -1 */
+    int32_t rate_param;      /* theta index, or -1 */
+    int32_t n_factors;       /* 0 .. LIK_ODE_MAX_FACTORS */
+    double rate_scale;       /* finite, >= 0 */
+    int32_t kind[LIK_ODE_MAX_FACTORS];
+    int32_t species[LIK_ODE_MAX_FACTORS];
+    int32_t param[LIK_ODE_MAX_FACTORS]; /* theta index of K (saturating, Hill, repressing) */
+} lik_ode_term;
+
+typedef struct lik_ode_model {
+    int32_t n_species;       /* U in [1, LIK_ODE_MAX_SPECIES] */
+    int32_t n_params;        /* theta length V in [1, LIK_ODE_MAX_PARAMS] */
+    int32_t n_terms;         /* in [1, LIK_ODE_MAX_TERMS] */
+    const lik_ode_term *terms;
+    const int32_t *x0_param; /* [U]: theta index or -1 */
+    int32_t obs_kind, obs_species, obs_species2, sd_param;
+    double sd_const;         /* > 0 when sd_param is -1 */
+    int32_t fret_param[5];   /* lambda, bg, E, fAA, fDD (LIK_ODE_OBS_FRET) */
+} lik_ode_model;
+
+typedef struct lik_ode_t_ *lik_ode_t;
+
+/* Validates and copies a model (host pointers).  LIK_EINVAL on a violated rule. */
+int lik_ode_create(const lik_ode_model *model, lik_ode_t *out);
+int lik_ode_destroy(lik_ode_t model);
+/* Compiles the model-specialised kernel into the on-disk kernel cache (no GPU
+ * needed); LIK_EDEVICE with the compiler log in lik_last_error() on failure. */
+int lik_ode_precompile(lik_ode_t model);
+
+/*
+ * Trajectories of a deterministic batch (host pointers):
+ *   obs_offsets [M+1], t_obs [total] (strictly increasing, > t0[m]), y [total];
+ *   t0 [M]; x0 [M*U] binary64 initial values of the species not set by theta;
+ *   in_offsets [M+1] (NULL: no input, u = 0), t_in [n_in] breakpoints, strictly
+ *   increasing per trajectory, u_in [n_in]: u(t) = u_in[k] on [t_in[k],
+ *   t_in[k+1]), 0 before the first breakpoint, u_in[last] after the last.
+ */
+typedef struct lik_ode_data {
+    int32_t n_traj;
+    const int32_t *obs_offsets;
+    const double *t_obs, *y, *t0, *x0;
+    const int32_t *in_offsets;
+    const double *t_in, *u_in;
+} lik_ode_data;
+
+/*
+ * lik_ode_eval -- log-likelihood of n_theta parameter vectors (theta
+ * [n_theta * V], host) against the trajectories: loglik_out[i] = sum over m
+ * of sum over t of log N(y_t; g(x(t_t)), sd^2) in trajectory and time order;
+ * status_out[i] (may be NULL) the first non-OK trajectory status, with NaN;
+ * steps_out[i * M + m] (may be NULL) the step attempts (accepted or rejected)
+ * of trajectory m.  rtol, atol > 0; max_steps in [1, 2^30] per trajectory.
+ * kernel: LIK_KERNEL_GENERIC (the terms read at run time),
+ * LIK_KERNEL_SPECIALIZED (the model compiled with hipRTC into code with
+ * constant indices, cached on disk like the networks' kernels; LIK_EDEVICE if
+ * that fails) or LIK_KERNEL_AUTO (specialised, else generic); every variant
+ * gives identical results.  One lane of the GPU integrates one (theta,
+ * trajectory) pair.  Synchronous; allocates its device memory.
+ */
+int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta,
+                 const lik_ode_data *data, double rtol, double atol, int32_t max_steps,
+                 int32_t kernel, double *loglik_out, int32_t *status_out, int32_t *steps_out);
 
 /* Thread-local description of the last error returned on this thread. */
 const char *lik_last_error(void);

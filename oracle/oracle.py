@@ -1,4 +1,5 @@
-"""TEST INFRASTRUCTURE ONLY: ctypes binding of the CPU oracle (pf_oracle.c).
+"""TEST INFRASTRUCTURE ONLY: ctypes binding of the CPU oracle (pf_oracle.c,
+and ode_oracle.c for deterministic models).
 
 The oracle is the plain CPU particle filter of Supplementary I (Algorithm
 "Likelihood Approximation using particle filter") with Gillespie direct-method
@@ -14,6 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "pf_oracle.c")
+_SRC_ODE = os.path.join(_HERE, "ode_oracle.c")
 
 OK, EVENT_CAP, COUNT_OVERFLOW, BAD_THETA = 0, 1, 2, 3
 FP64, FP32_MIXED = 0, 1
@@ -23,7 +25,7 @@ OBS_GAUSSIAN, OBS_LOGNORMAL, OBS_FLUORESCENCE = 0, 1, 2
 def build():
     """Compile the oracle: no fast-math, no FMA contraction (fma() explicit)."""
     cmd = ["gcc", "-O2", "-mfma", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-pthread", "-o", _LIB_PATH, _SRC, "-lm"]
+           "-shared", "-pthread", "-o", _LIB_PATH, _SRC, _SRC_ODE, "-lm"]
     subprocess.run(cmd, check=True)
 
 
@@ -63,7 +65,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+                os.path.getmtime(_SRC), os.path.getmtime(_SRC_ODE)):
             build()
         L = ctypes.CDLL(_LIB_PATH)
         vp, i32, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
@@ -85,6 +88,10 @@ def lib():
         L.orc_trace_filter.restype = ctypes.c_int
         L.orc_ssa_paths.argtypes = [vp, vp, u32, vp, dbl, dbl, i32, vp, vp]
         L.orc_ssa_paths.restype = ctypes.c_int
+        L.orc_ode_eval.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_ode_eval.restype = ctypes.c_int
+        L.orc_ode_solve.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.orc_ode_solve.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -228,3 +235,112 @@ def ssa_paths(prob, c, x0, t_start, t_end, n_paths, theta_id=0):
                              x0.ctypes.data, float(t_start), float(t_end), int(n_paths),
                              states.ctypes.data, ev.ctypes.data)
     return states, ev, st
+
+
+# -- deterministic models (ode_oracle.c) -------------------------------------
+
+STEP_LIMIT, NONFINITE = 7, 8
+ODE_SPECIES, ODE_SATURATING, ODE_HILL2, ODE_REPRESS2, ODE_INPUT = 0, 1, 2, 3, 4
+ODE_OBS_SPECIES, ODE_OBS_FRET = 0, 1
+
+
+class _OdeTerm(ctypes.Structure):
+    _fields_ = [("frm", ctypes.c_int32), ("to", ctypes.c_int32), ("rate_param", ctypes.c_int32),
+                ("n_factors", ctypes.c_int32), ("rate_scale", ctypes.c_double),
+                ("kind", ctypes.c_int32 * 3), ("species", ctypes.c_int32 * 3),
+                ("param", ctypes.c_int32 * 3)]
+
+
+class _OdeProblem(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_int32), ("V", ctypes.c_int32), ("n_terms", ctypes.c_int32),
+                ("terms", ctypes.c_void_p), ("x0_param", ctypes.c_void_p),
+                ("obs_kind", ctypes.c_int32), ("obs_species", ctypes.c_int32),
+                ("obs_species2", ctypes.c_int32), ("sd_param", ctypes.c_int32),
+                ("sd_const", ctypes.c_double), ("fret_param", ctypes.c_int32 * 5),
+                ("n_theta", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("n_traj", ctypes.c_int32), ("obs_offsets", ctypes.c_void_p),
+                ("t_obs", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t0", ctypes.c_void_p),
+                ("x0", ctypes.c_void_p), ("in_offsets", ctypes.c_void_p),
+                ("t_in", ctypes.c_void_p), ("u_in", ctypes.c_void_p),
+                ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("max_steps", ctypes.c_int32)]
+
+
+class OdeProblem:
+    """A deterministic batch.  model: dict with U, V, terms (list of dicts
+    frm, to, rate_param, rate_scale, factors [(kind, species, param)]),
+    x0_param [U], obs_kind, obs_species, obs_species2, sd_param, sd_const,
+    fret_param [5].  trajectories: dicts t_obs, y, t0, x0 and optionally
+    t_in, u_in (piecewise-constant input)."""
+
+    def __init__(self, model, theta, trajectories, rtol=1e-6, atol=1e-9, max_steps=100000):
+        U, V = int(model["U"]), int(model["V"])
+        terms = model["terms"]
+        self.terms = (_OdeTerm * len(terms))()
+        for k, t in enumerate(terms):
+            T = self.terms[k]
+            T.frm, T.to = int(t.get("frm", -1)), int(t.get("to", -1))
+            T.rate_param = int(t.get("rate_param", -1))
+            T.rate_scale = float(t.get("rate_scale", 1.0))
+            fs = t.get("factors", [])
+            T.n_factors = len(fs)
+            for j, (kind, sp, par) in enumerate(fs):
+                T.kind[j], T.species[j], T.param[j] = int(kind), int(sp), int(par)
+        self.x0_param = np.ascontiguousarray(model.get("x0_param", [-1] * U), dtype=np.int32)
+        self.theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, V))
+        offs, t_obs, ys, t0, x0, ioff, tin, uin = [0], [], [], [], [], [0], [], []
+        for tr in trajectories:
+            t_obs.append(np.asarray(tr["t_obs"], np.float64))
+            ys.append(np.asarray(tr["y"], np.float64).ravel())
+            t0.append(float(tr.get("t0", 0.0)))
+            x0.append(np.asarray(tr.get("x0", np.zeros(U)), np.float64))
+            offs.append(offs[-1] + len(t_obs[-1]))
+            tin.append(np.asarray(tr.get("t_in", []), np.float64))
+            uin.append(np.asarray(tr.get("u_in", []), np.float64))
+            ioff.append(ioff[-1] + len(tin[-1]))
+        self.offsets = np.array(offs, np.int32)
+        self.t_obs = np.ascontiguousarray(np.concatenate(t_obs))
+        self.y = np.ascontiguousarray(np.concatenate(ys))
+        self.t0 = np.array(t0, np.float64)
+        self.x0 = np.ascontiguousarray(np.stack(x0))
+        self.in_offsets = np.array(ioff, np.int32)
+        self.t_in = np.ascontiguousarray(np.concatenate(tin)) if ioff[-1] else np.zeros(1)
+        self.u_in = np.ascontiguousarray(np.concatenate(uin)) if ioff[-1] else np.zeros(1)
+        self.n_theta, self.M, self.U = self.theta.shape[0], len(trajectories), U
+        fret = (ctypes.c_int32 * 5)(*[int(v) for v in model.get("fret_param", [0] * 5)])
+        self.c = _OdeProblem(
+            U, V, len(terms), ctypes.addressof(self.terms), _ptr(self.x0_param),
+            int(model.get("obs_kind", 0)), int(model.get("obs_species", 0)),
+            int(model.get("obs_species2", 0)), int(model.get("sd_param", -1)),
+            float(model.get("sd_const", 1.0)), fret, self.n_theta, _ptr(self.theta), self.M,
+            _ptr(self.offsets), _ptr(self.t_obs), _ptr(self.y), _ptr(self.t0), _ptr(self.x0),
+            _ptr(self.in_offsets) if ioff[-1] else None, _ptr(self.t_in), _ptr(self.u_in),
+            float(rtol), float(atol), int(max_steps))
+
+
+def ode_eval(prob, nthreads=None):
+    """dict loglik [n_theta], status [n_theta], traj_ll [F], traj_status [F]."""
+    if nthreads is None:
+        nthreads = min(os.cpu_count() or 1, 16)
+    F = prob.n_theta * prob.M
+    ll = np.zeros(max(prob.n_theta, 1))
+    st = np.zeros(max(prob.n_theta, 1), np.int32)
+    tll = np.zeros(max(F, 1))
+    tst = np.zeros(max(F, 1), np.int32)
+    tsteps = np.zeros(max(F, 1), np.int32)
+    if lib().orc_ode_eval(ctypes.byref(prob.c), int(nthreads), ll.ctypes.data, st.ctypes.data,
+                          tll.ctypes.data, tst.ctypes.data, tsteps.ctypes.data) != 0:
+        raise ValueError("oracle rejected the problem")
+    return {"loglik": ll[:prob.n_theta], "status": st[:prob.n_theta], "traj_ll": tll[:F],
+            "traj_status": tst[:F], "traj_steps": tsteps[:F]}
+
+
+def ode_solve(prob, i, m):
+    """(states [T, U] at the observation times, step attempts, loglik, status)."""
+    T = int(prob.offsets[m + 1] - prob.offsets[m])
+    states = np.zeros((T, prob.U))
+    steps = ctypes.c_int32()
+    ll = ctypes.c_double()
+    st = lib().orc_ode_solve(ctypes.byref(prob.c), int(i), int(m), states.ctypes.data,
+                             ctypes.byref(steps), ctypes.byref(ll))
+    return states, steps.value, ll.value, st

@@ -77,6 +77,10 @@ hipFunction_t specialized_multi_kernel(const std::vector<lik_network *> &nets, i
                                        std::string *err);
 bool precompile_multi(const std::vector<lik_network *> &nets, int precision, std::string *err);
 
+// Code object of a generated kernel source (compiled with hipRTC, or read
+// from the on-disk kernel cache keyed by the source, headers and compiler).
+bool rtc_code(const std::string &src, std::vector<char> *code, std::string *err);
+
 // Compile (or find in the disk cache) without loading: needs no device.
 bool precompile_specialized(const lik_network &net, int precision, std::string *err);
 

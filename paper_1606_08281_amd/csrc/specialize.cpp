@@ -355,6 +355,11 @@ std::mutex g_multi_mu;
 std::map<std::pair<int, std::string>, std::pair<hipModule_t, hipFunction_t>> g_multi;
 }  // namespace
 
+bool rtc_code(const std::string &src, std::vector<char> *code, std::string *err) {
+    std::string path;
+    return code_for_source(src, code, &path, err);
+}
+
 bool precompile_multi(const std::vector<lik_network *> &nets, int precision, std::string *err) {
     std::vector<char> code;
     std::string path;

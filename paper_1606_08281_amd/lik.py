@@ -15,6 +15,9 @@ LIB_PATH = os.path.join(_HERE, "liblik.so")
 LIK_OK, LIK_EINVAL, LIK_ENOMEM, LIK_EDEVICE, LIK_EUNSUPPORTED, LIK_ETIMEOUT = 0, -1, -2, -3, -4, -5
 STATUS_OK, STATUS_EVENT_CAP, STATUS_COUNT_OVERFLOW, STATUS_BAD_THETA = 0, 1, 2, 3
 STATUS_SCHEDULER, STATUS_CANCELLED, STATUS_TIMED_OUT = 4, 5, 6
+STATUS_STEP_LIMIT, STATUS_NONFINITE = 7, 8
+ODE_SPECIES, ODE_SATURATING, ODE_HILL2, ODE_REPRESS2, ODE_INPUT = 0, 1, 2, 3, 4
+ODE_OBS_SPECIES, ODE_OBS_FRET = 0, 1
 OBS_GAUSSIAN, OBS_LOGNORMAL, OBS_FLUORESCENCE = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 KERNEL_AUTO, KERNEL_GENERIC, KERNEL_SPECIALIZED = 0, 1, 2
@@ -28,7 +31,8 @@ EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile
             "lik_server_destroy",
             "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version",
             "lik_network_set_tuning", "lik_network_get_tuning", "lik_autotune_device",
-            "lik_eval_requests", "lik_precompile_requests", "lik_autotune_requests"]
+            "lik_eval_requests", "lik_precompile_requests", "lik_autotune_requests",
+            "lik_ode_create", "lik_ode_destroy", "lik_ode_eval", "lik_ode_precompile"]
 
 
 class LikError(RuntimeError):
@@ -155,6 +159,15 @@ def lib():
         L.lik_precompile_requests.restype = ctypes.c_int
         L.lik_autotune_requests.argtypes = [vp, i32, i32, vp]
         L.lik_autotune_requests.restype = ctypes.c_int
+        L.lik_ode_create.argtypes = [vp, ctypes.POINTER(vp)]
+        L.lik_ode_create.restype = ctypes.c_int
+        L.lik_ode_precompile.argtypes = [vp]
+        L.lik_ode_precompile.restype = ctypes.c_int
+        L.lik_ode_destroy.argtypes = [vp]
+        L.lik_ode_destroy.restype = ctypes.c_int
+        L.lik_ode_eval.argtypes = [vp, i32, vp, vp, ctypes.c_double, ctypes.c_double, i32, i32,
+                                   vp, vp, vp]
+        L.lik_ode_eval.restype = ctypes.c_int
         L.lik_timing_enable.argtypes = [ctypes.c_int]
         L.lik_timing_enable.restype = ctypes.c_int
         L.lik_timing_read.argtypes = [vp]
@@ -578,3 +591,110 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# -- deterministic models (lik_ode_*) ----------------------------------------
+
+class OdeTerm(ctypes.Structure):
+    _fields_ = [("frm", ctypes.c_int32), ("to", ctypes.c_int32), ("rate_param", ctypes.c_int32),
+                ("n_factors", ctypes.c_int32), ("rate_scale", ctypes.c_double),
+                ("kind", ctypes.c_int32 * 3), ("species", ctypes.c_int32 * 3),
+                ("param", ctypes.c_int32 * 3)]
+
+
+class OdeModelC(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_params", ctypes.c_int32),
+                ("n_terms", ctypes.c_int32), ("terms", ctypes.c_void_p),
+                ("x0_param", ctypes.c_void_p), ("obs_kind", ctypes.c_int32),
+                ("obs_species", ctypes.c_int32), ("obs_species2", ctypes.c_int32),
+                ("sd_param", ctypes.c_int32), ("sd_const", ctypes.c_double),
+                ("fret_param", ctypes.c_int32 * 5)]
+
+
+class OdeData(ctypes.Structure):
+    _fields_ = [("n_traj", ctypes.c_int32), ("obs_offsets", ctypes.c_void_p),
+                ("t_obs", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t0", ctypes.c_void_p),
+                ("x0", ctypes.c_void_p), ("in_offsets", ctypes.c_void_p),
+                ("t_in", ctypes.c_void_p), ("u_in", ctypes.c_void_p)]
+
+
+class OdeModel:
+    """A deterministic model (lik_ode_create).  spec: dict with U, V, terms
+    (dicts frm, to, rate_param, rate_scale, factors [(kind, species,
+    param)]), x0_param [U], obs_kind, obs_species, obs_species2, sd_param,
+    sd_const, fret_param [5]."""
+
+    def __init__(self, spec):
+        U, V = int(spec["U"]), int(spec["V"])
+        terms = spec["terms"]
+        arr = (OdeTerm * len(terms))()
+        for k, t in enumerate(terms):
+            T = arr[k]
+            T.frm, T.to = int(t.get("frm", -1)), int(t.get("to", -1))
+            T.rate_param = int(t.get("rate_param", -1))
+            T.rate_scale = float(t.get("rate_scale", 1.0))
+            fs = t.get("factors", [])
+            T.n_factors = len(fs)
+            for j, (kind, sp, par) in enumerate(fs):
+                T.kind[j], T.species[j], T.param[j] = int(kind), int(sp), int(par)
+        x0p = np.ascontiguousarray(spec.get("x0_param", [-1] * U), dtype=np.int32)
+        m = OdeModelC(U, V, len(terms), ctypes.addressof(arr), x0p.ctypes.data,
+                      int(spec.get("obs_kind", 0)), int(spec.get("obs_species", 0)),
+                      int(spec.get("obs_species2", 0)), int(spec.get("sd_param", -1)),
+                      float(spec.get("sd_const", 1.0)),
+                      (ctypes.c_int32 * 5)(*[int(v) for v in spec.get("fret_param", [0] * 5)]))
+        h = ctypes.c_void_p()
+        _check(lib().lik_ode_create(ctypes.byref(m), ctypes.byref(h)))   # copies the arrays
+        self.handle = h
+        self.U, self.V = U, V
+
+    def precompile(self):
+        """Compile the model-specialised kernel into the disk cache (no GPU)."""
+        _check(lib().lik_ode_precompile(self.handle))
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().lik_ode_destroy(self.handle)
+            self.handle = None
+
+
+def ode_eval(model, theta, trajectories, rtol=1e-6, atol=1e-9, max_steps=100000, steps=False,
+             kernel=KERNEL_AUTO):
+    """lik_ode_eval: (loglik [n_theta], status [n_theta]) and, with steps,
+    the step attempts [n_theta, M].  trajectories:
+    dicts t_obs, y, t0, x0 [U] (the species not set by theta) and optionally
+    t_in, u_in (piecewise-constant input)."""
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, model.V))
+    offs, tin, ioff = [0], [], [0]
+    for tr in trajectories:
+        offs.append(offs[-1] + len(tr["t_obs"]))
+        tin.append(len(tr.get("t_in", [])))
+        ioff.append(ioff[-1] + tin[-1])
+    offs = np.array(offs, np.int32)
+    t_obs = np.ascontiguousarray(np.concatenate([np.asarray(tr["t_obs"], np.float64)
+                                                 for tr in trajectories]))
+    y = np.ascontiguousarray(np.concatenate([np.asarray(tr["y"], np.float64).ravel()
+                                             for tr in trajectories]))
+    t0 = np.array([float(tr.get("t0", 0.0)) for tr in trajectories], np.float64)
+    x0 = np.ascontiguousarray(np.stack([np.asarray(tr.get("x0", np.zeros(model.U)), np.float64)
+                                        for tr in trajectories]))
+    has_in = ioff[-1] > 0
+    ioff = np.array(ioff, np.int32)
+    t_in = np.ascontiguousarray(np.concatenate([np.asarray(tr.get("t_in", []), np.float64)
+                                                for tr in trajectories])) if has_in else None
+    u_in = np.ascontiguousarray(np.concatenate([np.asarray(tr.get("u_in", []), np.float64)
+                                                for tr in trajectories])) if has_in else None
+    d = OdeData(len(trajectories), offs.ctypes.data, t_obs.ctypes.data, y.ctypes.data,
+                t0.ctypes.data, x0.ctypes.data, ioff.ctypes.data if has_in else None,
+                _ptr(t_in), _ptr(u_in))
+    n = theta.shape[0]
+    ll = np.zeros(max(n, 1))
+    st = np.zeros(max(n, 1), np.int32)
+    ns = np.zeros(max(n * len(trajectories), 1), np.int32)
+    _check(lib().lik_ode_eval(model.handle, n, theta.ctypes.data, ctypes.byref(d), float(rtol),
+                              float(atol), int(max_steps), int(kernel), ll.ctypes.data,
+                              st.ctypes.data,
+                              ns.ctypes.data if steps else None))
+    if steps:
+        return ll[:n], st[:n], ns[:n * len(trajectories)].reshape(n, len(trajectories))
+    return ll[:n], st[:n]

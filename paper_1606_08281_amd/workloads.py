@@ -24,6 +24,7 @@ Workloads:
     mature GFP observed with per-molecule normal signal plus background.
 """
 import functools
+import math
 
 import numpy as np
 
@@ -497,3 +498,158 @@ def lacgfp_workload(n_theta=256, n_traj=5, n_obs=29, dt=1.0, n_particles=200, th
                  trajs, n_particles, truth=c_true)
     w.params = params
     return w
+
+
+# ---------------------------------------------------------------------------
+# Egf-Ras-Raf-Mek-Erk (Supplementary "Egf-Ras-Raf-Mek-Erk model": species and
+# initial-value table, reaction equations, parameter and FRET prior tables)
+# as a deterministic model: a term list for the ODE likelihood (the spec
+# format of lik.OdeModel and of the oracle's OdeProblem)
+# ---------------------------------------------------------------------------
+ERK_SPECIES = ["EGFR", "EGFR*", "Ras", "Ras*", "Raf", "Raf*", "MEK", "MEK*", "ERK", "ERK*",
+               "NFB", "NFB*", "dusp", "DUSP"]
+ERK_PARAMS = ["k1", "gamma1", "k2", "K2", "gamma2", "D2", "k3", "K3", "K_NFB", "gamma3", "D3",
+              "k4", "K4", "gamma4", "D4", "k5", "K5", "gamma5", "D5", "k6", "K6", "K6R", "gamma6",
+              "D6", "dusp_basal", "dusp_ind", "K_dusp", "EGFR0", "NFB0", "dusp0",
+              "bg", "lambda", "sigma", "E", "fAA", "fDD"]
+ERK_PRIOR_LO = np.exp(np.r_[np.full(27, -10.0), np.full(3, -8.0), -7.0, -7.0, -8.0, -4.0, -8.0,
+                            -8.0])
+ERK_PRIOR_HI = np.exp(np.r_[np.full(27, 5.0), np.full(3, 1.0), 6.0, 6.0, -3.0, -0.5, 5.0, 5.0])
+# a reference point inside the prior box (the paper's table leaves its theta
+# column empty): rates per minute, concentrations in the table's units
+ERK_REF = np.array([1.0, 0.5, 2.0, 0.1, 0.5, 0.1, 2.0, 0.5, 0.1, 0.5, 0.5, 2.0, 0.5, 0.5, 0.5,
+                    2.0, 0.3, 2.0, 0.3, 0.5, 0.1, 0.3, 0.05, 0.1, 0.01, 10.0, 0.01, 0.1, 0.05,
+                    0.001, 0.5, 1.0, 0.01, 0.3, 1.0, 1.0])
+ERK_T_HALF = 90.0   # minutes, dusp and DUSP (fixed in the table)
+
+
+def erk_model():
+    """The 14 reaction equations as 17 flux terms over the engine's 36
+    parameters (erk_engine_params): conversions between inactive and active
+    forms, dusp production (basal and ERK-induced) and decay, DUSP
+    translation and decay; observed through the FRET ratio of ERK* / ERK."""
+    SP, SAT, HILL, REP, INP = 0, 1, 2, 3, 4
+    (EGFR, EGFRa, Ras, Rasa, Raf, Rafa, MEK, MEKa, ERK, ERKa, NFB, NFBa, dusp, DUSP) = range(14)
+    P = {n: k for k, n in enumerate(ERK_PARAMS)}
+    dec = math.log10(2.0) / ERK_T_HALF   # the printed factor log10(2) / T
+    terms = [
+        dict(frm=EGFR, to=EGFRa, rate_param=P["k1"], factors=[(INP, 0, 0), (SP, EGFR, 0)]),
+        dict(frm=EGFRa, to=EGFR, rate_param=P["gamma1"], factors=[(SP, EGFRa, 0)]),
+        dict(frm=Ras, to=Rasa, rate_param=P["k2"], factors=[(SP, EGFRa, 0), (SAT, Ras, P["K2"])]),
+        dict(frm=Rasa, to=Ras, rate_param=P["gamma2"], factors=[(SAT, Rasa, P["D2"])]),
+        dict(frm=Raf, to=Rafa, rate_param=P["k3"],
+             factors=[(SP, Rasa, 0), (SAT, Raf, P["K3"]), (REP, NFBa, P["K_NFB"])]),
+        dict(frm=Rafa, to=Raf, rate_param=P["gamma3"], factors=[(SAT, Rafa, P["D3"])]),
+        dict(frm=MEK, to=MEKa, rate_param=P["k4"], factors=[(SP, Rafa, 0), (SAT, MEK, P["K4"])]),
+        dict(frm=MEKa, to=MEK, rate_param=P["gamma4"], factors=[(SAT, MEKa, P["D4"])]),
+        dict(frm=ERK, to=ERKa, rate_param=P["k5"], factors=[(SP, MEKa, 0), (SAT, ERK, P["K5"])]),
+        dict(frm=ERKa, to=ERK, rate_param=P["gamma5"], factors=[(SP, DUSP, 0), (SAT, ERKa, P["D5"])]),
+        dict(frm=NFB, to=NFBa, rate_param=P["k6"],
+             factors=[(SP, ERKa, 0), (SAT, NFB, P["K6"]), (HILL, EGFRa, P["K6R"])]),
+        dict(frm=NFBa, to=NFB, rate_param=P["gamma6"], factors=[(SAT, NFBa, P["D6"])]),
+        dict(to=dusp, rate_param=P["dusp_basal"], rate_scale=dec),
+        dict(to=dusp, rate_param=P["dusp_ind"], rate_scale=dec, factors=[(HILL, ERKa, P["K_dusp"])]),
+        dict(frm=dusp, rate_scale=dec, factors=[(SP, dusp, 0)]),
+        dict(to=DUSP, rate_scale=dec, factors=[(SP, dusp, 0)]),
+        dict(frm=DUSP, rate_scale=dec, factors=[(SP, DUSP, 0)]),
+    ]
+    x0_param = [-1] * 14
+    x0_param[EGFR], x0_param[NFB] = P["EGFR0"], P["NFB0"]
+    x0_param[dusp] = x0_param[DUSP] = P["dusp0"]
+    return {"U": 14, "V": len(ERK_PARAMS), "terms": terms, "x0_param": x0_param,
+            "obs_kind": 1, "obs_species": ERKa, "obs_species2": ERK, "sd_param": P["sigma"],
+            "sd_const": 1.0, "fret_param": [P["lambda"], P["bg"], P["E"], P["fAA"], P["fDD"]]}
+
+
+def erk_engine_params(theta):
+    """The model's parameters as the engine reads them: the two repression and
+    activation constants that enter squared (K_NFB, K6R) are squared, and the
+    induced dusp rate is dusp_basal * dusp_ind."""
+    th = np.array(np.atleast_2d(theta), dtype=np.float64)
+    P = {n: k for k, n in enumerate(ERK_PARAMS)}
+    th[:, P["K_NFB"]] = th[:, P["K_NFB"]] ** 2
+    th[:, P["K6R"]] = th[:, P["K6R"]] ** 2
+    th[:, P["dusp_ind"]] = th[:, P["dusp_basal"]] * th[:, P["dusp_ind"]]
+    return th
+
+
+ERK_X0 = np.array([0, 0, 0.1, 0, 0.7, 0, 0.68, 0, 0.26, 0, 0, 0, 0, 0], dtype=np.float64)
+
+
+def erk_inputs():
+    """Six EGF input patterns over 0-120 min (reading: a sustained step, a
+    single 10-min pulse, 3-min pulses every 10, 20 and 30 min, and a staircase),
+    as breakpoints and values of a piecewise-constant input."""
+    pats = [([0.0], [1.0]), ([0.0, 10.0], [1.0, 0.0])]
+    for period in (10.0, 20.0, 30.0):
+        t, u = [], []
+        for s in np.arange(0.0, 120.0, period):
+            t += [s, s + 3.0]
+            u += [1.0, 0.0]
+        pats.append((t, u))
+    pats.append(([0.0, 30.0, 60.0, 90.0], [0.25, 0.5, 0.75, 1.0]))
+    return pats
+
+
+def ode_spec_rhs(spec, th, u):
+    """numpy right-hand side of a term list (data generation only)."""
+    U = spec["U"]
+
+    def f(t, x):
+        dx = np.zeros(U)
+        for T in spec["terms"]:
+            v = T.get("rate_scale", 1.0) * (th[T["rate_param"]] if T.get("rate_param", -1) >= 0 else 1.0)
+            for kind, sp, par in T.get("factors", []):
+                xs = x[sp]
+                v *= (u if kind == 4 else xs if kind == 0 else xs / (th[par] + xs) if kind == 1
+                      else xs * xs / (th[par] + xs * xs) if kind == 2 else th[par] / (th[par] + xs * xs))
+            if T.get("frm", -1) >= 0:
+                dx[T["frm"]] -= v
+            if T.get("to", -1) >= 0:
+                dx[T["to"]] += v
+        return dx
+    return f
+
+
+def erk_workload(n_theta=256, spread=0.3, n_obs=60, dt=2.0, theta=None):
+    """ERK batch: engine parameter vectors log-normal (sd `spread`) around the
+    reference point, six input patterns, FRET observations every dt minutes
+    simulated from the reference point (scipy DOP853, piece by piece between
+    input breakpoints) plus normal noise of the reference sigma."""
+    from scipy.integrate import solve_ivp
+    spec = erk_model()
+    ref = erk_engine_params(ERK_REF)[0]
+    t_obs = dt * np.arange(1, n_obs + 1, dtype=np.float64)
+    nrng = np.random.Generator(np.random.PCG64(SEED_NOISE))
+    P = {n: k for k, n in enumerate(ERK_PARAMS)}
+    trajs = []
+    for t_in, u_in in erk_inputs():
+        x = ERK_X0.copy()
+        for s, p in enumerate(spec["x0_param"]):
+            if p >= 0:
+                x[s] = ref[p]
+        edges = list(t_in[1:]) + [t_obs[-1]]
+        states = []
+        tc = 0.0
+        for te, uu in zip(edges, u_in):
+            te = min(te, t_obs[-1])
+            if te <= tc:
+                continue
+            ts = [tt for tt in t_obs if tc < tt <= te]
+            sol = solve_ivp(ode_spec_rhs(spec, ref, uu), (tc, te), x, method="DOP853", rtol=1e-10,
+                            atol=1e-12, t_eval=ts, dense_output=True)
+            states += list(sol.y.T)
+            x, tc = sol.sol(te), te
+        states = np.array(states)
+        lam, bg, E, fAA, fDD = (ref[P[k]] for k in ("lambda", "bg", "E", "fAA", "fDD"))
+        a, b = states[:, 9], states[:, 8]
+        g = lam * (E * fAA * a / ((b + (1 - E) * a) * fDD) + bg)
+        y = g + nrng.normal(0.0, ref[P["sigma"]], len(g))
+        trajs.append({"t_obs": t_obs, "y": y, "t0": 0.0, "x0": ERK_X0.copy(),
+                      "t_in": np.asarray(t_in, np.float64), "u_in": np.asarray(u_in, np.float64),
+                      "x_true": states})
+    if theta is None:
+        rng = np.random.Generator(np.random.PCG64(SEED_THETA))
+        theta = ERK_REF * np.exp(rng.normal(0.0, spread, (n_theta, len(ERK_REF))))
+    params = np.atleast_2d(np.asarray(theta, dtype=np.float64))
+    return {"spec": spec, "params": params, "theta": erk_engine_params(params), "trajectories": trajs}

@@ -169,3 +169,37 @@ def test_eval_requests_rejects_on_the_host():
     assert e.value.code == lik.LIK_EUNSUPPORTED
     with pytest.raises(lik.LikError):
         lik.precompile_requests(nets)
+
+
+def test_ode_model_validation_and_empty_batch():
+    # every check runs on the host; an empty batch needs no device
+    good = {"U": 1, "V": 2, "terms": [{"to": 0, "rate_param": 0},
+                                      {"frm": 0, "rate_param": 1, "factors": [(0, 0, 0)]}],
+            "x0_param": [-1], "sd_const": 1.0}
+    m = lik.OdeModel(good)
+    ll, st = lik.ode_eval(m, np.zeros((0, 2)), [{"t_obs": [1.0], "y": [0.0], "x0": [0.0]}])
+    assert ll.shape == (0,)
+    for bad in (dict(good, U=0), dict(good, V=0), dict(good, sd_const=0.0),
+                dict(good, terms=[{"frm": 1, "rate_param": 0}]),
+                dict(good, terms=[{"to": 0, "rate_param": 2}]),
+                dict(good, terms=[{"to": 0, "rate_param": 0, "factors": [(1, 0, 5)]}]),
+                dict(good, terms=[{"to": 0, "rate_param": 0, "factors": [(9, 0, 0)]}]),
+                dict(good, x0_param=[3]), dict(good, obs_kind=1, fret_param=[0, 1, 2, 3, 4])):
+        with pytest.raises(lik.LikError) as e:
+            lik.OdeModel(bad)
+        assert e.value.code == lik.LIK_EINVAL
+    tr = {"t_obs": [1.0, 0.5], "y": [0.0, 0.0], "x0": [0.0]}
+    with pytest.raises(lik.LikError):          # times must increase
+        lik.ode_eval(m, np.ones((1, 2)), [tr])
+    with pytest.raises(lik.LikError):          # tolerances
+        lik.ode_eval(m, np.ones((1, 2)), [dict(tr, t_obs=[1.0, 2.0])], rtol=0.0)
+
+
+def test_ode_specialised_kernels_compile_without_gpu(tmp_path, monkeypatch):
+    monkeypatch.setenv("LIK_KERNEL_CACHE", str(tmp_path))
+    from paper_1606_08281_amd import workloads as W
+    lik.OdeModel(W.erk_model()).precompile()
+    from tests.test_oracle_ode import every_factor_model, imm_death_model
+    lik.OdeModel(every_factor_model()).precompile()
+    lik.OdeModel(imm_death_model()).precompile()
+    assert len(list(tmp_path.iterdir())) == 3

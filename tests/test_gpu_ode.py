@@ -1,0 +1,84 @@
+"""Deterministic-model likelihood on the GPU against the oracle (Sec.
+"Chemical Reaction Networks", deterministic formulation; Results,
+deterministic models; Supplementary "Egf-Ras-Raf-Mek-Erk model").
+
+Both sides take the same Dormand-Prince steps under the same step rule, with
+every operation in the same order and the same log and exp, so the
+log-likelihoods and statuses agree bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1606_08281_amd import workloads as W
+from tests.test_oracle_ode import every_factor_model, imm_death_model
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu case]", *a, flush=True)
+
+
+def both(orc, spec, theta, trajs, **kw):
+    """The generic and the model-specialised kernel against the oracle: both
+    must give the same results; returns the specialised one's."""
+    from paper_1606_08281_amd import lik
+    model = lik.OdeModel(spec)
+    ref = orc.ode_eval(orc.OdeProblem(spec, theta, trajs, **kw))
+    outs = []
+    for kernel in (lik.KERNEL_GENERIC, lik.KERNEL_SPECIALIZED):
+        ll, st, steps = lik.ode_eval(model, theta, trajs, steps=True, kernel=kernel, **kw)
+        # the same step sequence: equal step counts per trajectory
+        assert np.array_equal(steps.ravel(), ref["traj_steps"]), kernel
+        outs.append((ll, st))
+    assert np.array_equal(outs[0][0], outs[1][0], equal_nan=True)
+    assert np.array_equal(outs[0][1], outs[1][1])
+    return outs[1][0], outs[1][1], ref
+
+
+def assert_same(ll, st, ref):
+    assert np.array_equal(st, ref["status"]), (st, ref["status"])
+    bad = ~np.isfinite(ref["loglik"])
+    assert np.array_equal(np.isnan(ll), np.isnan(ref["loglik"]))
+    diff = np.abs(ll[~bad] - ref["loglik"][~bad])
+    assert np.all(ll[~bad] == ref["loglik"][~bad]), diff.max()
+
+
+def test_small_models_bit_exact(orc):
+    rng = np.random.default_rng(3)
+    _say("immigration-death rate equations, 200 theta, 3 trajectories")
+    t = np.linspace(0.5, 12.0, 24)
+    trajs = [{"t_obs": t + 0.1 * m, "y": rng.normal(10, 3, len(t)), "x0": [m * 2.0]} for m in range(3)]
+    theta = np.exp(rng.normal(0.0, 1.0, (200, 2)))
+    assert_same(*both(orc, imm_death_model(), theta, trajs, rtol=1e-7, atol=1e-10))
+    _say("every factor kind, inputs, FRET read-out, 300 theta")
+    tin, uin = np.array([0.0, 3.0, 5.0]), np.array([1.0, 0.2, 2.0])
+    t = np.linspace(0.4, 8.0, 20)
+    trajs = [{"t_obs": t, "y": rng.normal(1.0, 0.05, len(t)), "x0": [0, 0, 0.4, 0.1],
+              "t_in": tin, "u_in": uin},
+             {"t_obs": t[::2], "y": rng.normal(1.0, 0.05, 10), "x0": [0, 0.1, 0.2, 0.0]}]
+    base = np.array([1.3, 0.8, 0.4, 2.0, 0.3, 0.7, 1.1, 0.5, 0.2, 2.5])
+    theta = base * np.exp(rng.normal(0.0, 0.7, (300, 10)))
+    for rtol in (1e-4, 1e-8):
+        assert_same(*both(orc, every_factor_model(), theta, trajs, rtol=rtol, atol=rtol * 1e-3))
+
+
+def test_erk_batch_bit_exact(orc):
+    wl = W.erk_workload(n_theta=512, spread=0.5)
+    _say("ERK model, 512 theta x 6 input patterns x 60 FRET observations")
+    ll, st, ref = both(orc, wl["spec"], wl["theta"], wl["trajectories"], rtol=1e-6, atol=1e-9)
+    assert np.mean(st == 0) > 0.9
+    assert_same(ll, st, ref)
+
+
+def test_statuses_agree(orc):
+    wl = W.erk_workload(n_theta=64, spread=1.5)
+    th = wl["theta"].copy()
+    th[1, 3] = -1.0           # a negative Hill constant
+    th[2, 0] = np.nan
+    th[3, 32] = 0.0           # zero noise sd
+    _say("ERK statuses: bad parameters and a step limit")
+    ll, st, ref = both(orc, wl["spec"], th, wl["trajectories"], rtol=1e-6, atol=1e-9,
+                       max_steps=400)
+    assert list(st[1:4]) == [3, 3, 3]
+    assert np.any(st == 7)
+    assert_same(ll, st, ref)
