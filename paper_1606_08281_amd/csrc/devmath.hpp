@@ -242,4 +242,28 @@ __device__ __forceinline__ float flog_pos(float x) {
     return ef * kLn2HiF + (ef * kLn2LoF + lm);
 }
 
+// A value equal on every lane, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <class T>
+__device__ __forceinline__ T *wave_uniform(T *p) {
+    return reinterpret_cast<T *>(wave_uniform((uint64_t)reinterpret_cast<unsigned long long>(p)));
+}
+
 }  // namespace lik

@@ -260,6 +260,7 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
     if (lane < d.P) logy[lane] = d.obs_kind == LIK_OBS_LOGNORMAL ? dlog(yt[lane]) : 0.0;
     __syncthreads();
     double *w = d.lw;
+    const ObsParams op = obs_params(d);
 
     // Per-particle passes take kB particles per lane at a time, their loads
     // issued together (a load cannot move above an earlier iteration's store
@@ -273,6 +274,15 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
     int c0[kB];
 #pragma unroll
     for (int k = 0; k < kB; ++k) c0[k] = lane + 64 * k < H ? x0s[lane + 64 * k] : 0;
+    if (op.kind == LIK_OBS_FLUORESCENCE) {
+        // one particle at a time: its count-dependent variance makes the term
+        // longer, and pairs would raise the kernel's register count
+        for (int j = lane; j < H; j += 64) {
+            const double l = obs_logweight(d, op, xs, j, logy, yt);
+            w[j] = l;
+            mx = fmax(mx, l);
+        }
+    } else
     for (int base = lane; base < H; base += 64 * kB) {
         double l[kB];
         bool on[kB];
@@ -291,7 +301,7 @@ __device__ __forceinline__ bool flow_weigh(const EngineArgs &e, int f, double *l
             for (int k = 0; k < kB; ++k) cnt[k] = o == 0 ? c0[k] : on[k] ? xo[base + 64 * k] : 0;
 #pragma unroll
             for (int k = 0; k < kB; ++k)
-                if (on[k]) on[k] = obs_term(d, o, cnt[k], logy, yt, l[k]);
+                if (on[k]) on[k] = obs_term<false>(op, o, cnt[k], logy, yt, l[k]);
         }
 #pragma unroll
         for (int k = 0; k < kB; ++k) c0[k] = n0[k];

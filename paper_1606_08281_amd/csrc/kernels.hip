@@ -421,8 +421,9 @@ __global__ __launch_bounds__(kWeighBlock) void k_weigh(EngineArgs e) {
     // particle-dependent part of log p(y_t | x_j) (the "Compute l_t^i" step),
     // kept in lw for this thread's second pass; and the maximum
     double mx = -__builtin_inf();
+    const ObsParams op = obs_params(d);
     for (int j = j0; j < j1; ++j) {
-        const double l = obs_logweight(d, xs, j, logy, yt);
+        const double l = obs_logweight(d, op, xs, j, logy, yt);
         lw[j] = l;
         mx = fmax(mx, l);
     }

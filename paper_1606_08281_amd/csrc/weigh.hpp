@@ -82,33 +82,47 @@ __device__ __forceinline__ int pool_size(const EngineArgs &e, int f, uint32_t c,
 // r = y - (gain x + bg_mean).  logy[k] = log y_k for the log-normal model.
 // obs_term adds component k's term to l; false (l = -inf, later components
 // skipped) for a log-normal observation of a count <= 0.
-__device__ __forceinline__ bool obs_term(const FilterDesc &d, int k, int cnt, const double *logy,
+// The observation model's parameters of one filter, read once into scalar
+// registers (every lane of a wavefront weighs particles of the same filter).
+struct ObsParams {
+    int kind;
+    double sigma, gain, bg_mean, s2, b2;
+};
+__device__ __forceinline__ ObsParams obs_params(const FilterDesc &d) {
+    return ObsParams{wave_uniform(d.obs_kind), wave_uniform(d.sigma), wave_uniform(d.gain),
+                     wave_uniform(d.bg_mean), wave_uniform(d.obs_s2), wave_uniform(d.bg_s2)};
+}
+
+// FLUO false: the caller has excluded the fluorescence model (a shorter body).
+template <bool FLUO = true>
+__device__ __forceinline__ bool obs_term(const ObsParams &o, int k, int cnt, const double *logy,
                                          const double *yt, double &l) {
-    if (d.obs_kind == LIK_OBS_FLUORESCENCE) {
+    if (FLUO && o.kind == LIK_OBS_FLUORESCENCE) {
         const double x = (double)cnt;
-        const double v = d.obs_s2 * x + d.bg_s2;
-        const double r = yt[k] - (d.gain * x + d.bg_mean);
+        const double v = o.s2 * x + o.b2;
+        const double r = yt[k] - (o.gain * x + o.bg_mean);
         l = l - 0.5 * ((r * r) / v);
         l = l - 0.5 * dlog(v);
-    } else if (d.obs_kind == LIK_OBS_LOGNORMAL) {
+    } else if (o.kind == LIK_OBS_LOGNORMAL) {
         if (cnt <= 0) {
             l = -__builtin_inf();
             return false;
         }
-        const double z = (logy[k] - dlog((double)cnt)) / d.sigma;
+        const double z = (logy[k] - dlog((double)cnt)) / o.sigma;
         l = l - 0.5 * (z * z);
     } else {
-        const double z = (yt[k] - (double)cnt) / d.sigma;
+        const double z = (yt[k] - (double)cnt) / o.sigma;
         l = l - 0.5 * (z * z);
     }
     return true;
 }
 
-__device__ __forceinline__ double obs_logweight(const FilterDesc &d, const int32_t *xs, int j,
-                                                const double *logy, const double *yt) {
+__device__ __forceinline__ double obs_logweight(const FilterDesc &d, const ObsParams &o,
+                                                const int32_t *xs, int j, const double *logy,
+                                                const double *yt) {
     double l = 0.0;
     for (int k = 0; k < d.P; ++k)
-        if (!obs_term(d, k, xs[(size_t)d.obs_species[k] * d.Hp + j], logy, yt, l)) break;
+        if (!obs_term(o, k, xs[(size_t)d.obs_species[k] * d.Hp + j], logy, yt, l)) break;
     return l;
 }
 
