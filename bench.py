@@ -342,11 +342,13 @@ def main():
         # the same seed in binary64: both draw the same random blocks, so the
         # difference per result is the effect of binary32 arithmetic alone
         ll32 = db.loglik.cpu().numpy().copy()
+        ev32 = db.events.cpu().numpy().copy()
         db64 = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories,
                                wl.n_theta, wl.n_particles, precision=lik.FP64,
                                kernel=args.kernel)
         db64.run(theta, wl.seed + args.steps - 1, stream=stream)
         ll64 = db64.loglik.cpu().numpy().copy()
+        ev64 = db64.events.cpu().numpy().copy()
         # Monte Carlo scale: the binary64 estimate under another seed
         db64.run(theta, wl.seed + args.steps, stream=stream)
         ll64b = db64.loglik.cpu().numpy().copy()
@@ -356,12 +358,24 @@ def main():
             err = np.abs(a[ok] - b[ok])
             if not err.size:
                 return {"n": 0}
+            rel = err / np.abs(b[ok])
+            q = (10, 25, 50, 75, 90, 99)
             return {"n": int(ok.sum()), "abs_max": float(err.max()),
                     "abs_p50": float(np.median(err)), "abs_p99": float(np.percentile(err, 99)),
-                    "rel_max": float((err / np.abs(b[ok])).max()),
-                    "identical": int((err == 0).sum())}
+                    "rel_max": float(rel.max()),
+                    "identical": int((err == 0).sum()),
+                    "abs_quantiles": {f"p{k}": float(np.percentile(err, k)) for k in q},
+                    "rel_quantiles": {f"p{k}": float(np.percentile(rel, k)) for k in q}}
+        # filters whose SSA paths left their FP64 twins (a differing event
+        # total; equal totals with different paths are not counted)
         fp32_error = dict(diff(ll32, ll64), vs="f64 path, same seed",
+                          filters_diverged=float(np.mean(ev32 != ev64)),
+                          filters=int(ev32.size),
                           f64_seed_to_seed=diff(ll64b, ll64))
+        out_dir = os.path.join(ROOT, "gpurun_out")
+        if os.path.isdir(out_dir):   # every result: FP32-mixed, FP64, FP64 under another seed
+            np.save(os.path.join(out_dir, f"fp32_vs_fp64_{args.workload}.npy"),
+                    np.stack([ll32, ll64, ll64b]))
         del db64
 
     # HBM bytes per launch from the committed rocprofv3 counter summary of
