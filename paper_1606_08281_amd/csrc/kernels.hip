@@ -218,19 +218,24 @@ __global__ __launch_bounds__(kOrderBlock) void k_order_count(EngineArgs e) {
     if (threadIdx.x == 0 && max_per) atomicMax(&e.order_ctl[0], max_per);
 }
 
-// One block: exclusive scan per group in key order (longest first), from the
-// group's first item; leaves the counts zero for the next iteration.
-__global__ __launch_bounds__(64) void k_order_scan(EngineArgs e) {
-    const int g = threadIdx.x;
-    if (g < kMaxGroups) {
-        uint32_t run = e.group_off[g];
-        for (int k = 0; k < kCostKeys; ++k) {
-            const uint32_t h = e.order_count[g * kCostKeys + k];
-            e.order_pos[g * kCostKeys + k] = run;
+// One block, one wavefront per group: exclusive scan in key order (longest
+// first) from the group's first item, 64 keys at a time with the running
+// total carried; leaves the counts zero for the next iteration.
+__global__ __launch_bounds__(64 * kMaxGroups) void k_order_scan(EngineArgs e) {
+    const int g = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    uint64_t run = e.group_off[g];
+    for (int k0 = 0; k0 < kCostKeys; k0 += 64) {
+        const int k = k0 + lane;
+        const uint32_t h = k < kCostKeys ? e.order_count[g * kCostKeys + k] : 0u;
+        const uint64_t incl = wave_incl_scan_u64(h, lane);
+        if (k < kCostKeys) {
+            e.order_pos[g * kCostKeys + k] = (uint32_t)(run + incl - h);
             e.order_count[g * kCostKeys + k] = 0u;
-            run += h;
         }
-        e.item_count[g] = run - e.group_off[g];
+        run += lane_read(incl, 63);
+    }
+    if (lane == 0) {
+        e.item_count[g] = (uint32_t)(run - e.group_off[g]);
         e.item_cursor[g] = 0;
     }
     if (threadIdx.x == 0) {
@@ -239,15 +244,32 @@ __global__ __launch_bounds__(64) void k_order_scan(EngineArgs e) {
     }
 }
 
+// Positions are taken per block: the block's slots first reserve their items
+// within the block (LDS atomics), then one global atomic per (group, key)
+// reserves the block's share.
 __global__ __launch_bounds__(kOrderBlock) void k_order_place(EngineArgs e) {
+    __shared__ uint32_t lcount[kMaxGroups * kCostKeys];
+    for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x) lcount[k] = 0u;
+    __syncthreads();
     const int f = e.f_lo + (int)(blockIdx.x * kOrderBlock + threadIdx.x);
-    if (f >= e.f_hi || !slot_active(e, f)) return;
-    const uint32_t c = e.cost[f];
-    const int nchunk = e.desc[f].Hp >> 6;
-    const int g = pool_size(e, f, c, order_gpar(e));  // as in the counting pass
-    const int key = duration_key((uint64_t)(c / (uint32_t)e.desc[f].H) * (uint64_t)g);
-    const uint32_t n_items = (uint32_t)((nchunk + g - 1) / g);
-    const uint32_t pos = atomicAdd(&e.order_pos[e.desc[f].group * kCostKeys + key], n_items);
+    const bool on = f < e.f_hi && slot_active(e, f);
+    uint32_t c = 0, n_items = 0, local = 0;
+    int g = 1, gk = 0;
+    if (on) {
+        c = e.cost[f];
+        const int nchunk = e.desc[f].Hp >> 6;
+        g = pool_size(e, f, c, order_gpar(e));  // as in the counting pass
+        const int key = duration_key((uint64_t)(c / (uint32_t)e.desc[f].H) * (uint64_t)g);
+        gk = e.desc[f].group * kCostKeys + key;
+        n_items = (uint32_t)((nchunk + g - 1) / g);
+        local = atomicAdd(&lcount[gk], n_items);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kMaxGroups * kCostKeys; k += blockDim.x)
+        if (lcount[k]) lcount[k] = atomicAdd(&e.order_pos[k], lcount[k]);  // the block's base
+    __syncthreads();
+    if (!on) return;
+    const uint32_t pos = lcount[gk] + local;
     for (uint32_t q = 0; q < n_items; ++q) e.items[pos + q] = ((uint32_t)f << 6) | (q * g);
     // Wavefront priority: the slots whose particles are expected to need
     // the most events are the ones the iteration waits for; their
@@ -634,7 +656,7 @@ hipError_t launch_order(const EngineArgs &e, hipStream_t s) {
     const int F = e.f_hi - e.f_lo;
     const unsigned blocks = (unsigned)((F + kOrderBlock - 1) / kOrderBlock);
     if (blocks) hipLaunchKernelGGL(k_order_count, dim3(blocks), dim3(kOrderBlock), 0, s, e);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, e);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64 * kMaxGroups), 0, s, e);
     if (blocks) hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(kOrderBlock), 0, s, e);
     return hipGetLastError();
 }
