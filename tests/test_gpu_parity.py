@@ -516,9 +516,15 @@ def test_flow_schedule_graph_replays_and_random_network(orc):
         ll_e = eager.run(theta, wl.seed + k)[0].clone()
         junk = torch.randn(4096, device="cuda").sum()
         ll_g = graph.run(theta, wl.seed + k)[0].clone()
+        ev_g = graph.events.clone()
         torch.cuda.synchronize()
         assert float(junk) == float(junk)
         assert torch.equal(ll_e, ll_g), k
+    # the last replay against the oracle directly (same seed)
+    ref = _oracle(orc, wl, seed=wl.seed + 2)
+    assert np.array_equal(ev_g.cpu().numpy().astype(np.uint64), ref["events"])
+    got = ll_g.cpu().numpy()
+    assert np.all(np.abs(got - ref["loglik"]) <= REL * np.abs(ref["loglik"]))
     rw = W.random_network_workload(n_theta=64, n_particles=96, n_obs=3, events_per_interval=300)
     idx = np.arange(0, 64, 8)
     for kernel in KERNELS:
