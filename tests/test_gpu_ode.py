@@ -82,3 +82,18 @@ def test_statuses_agree(orc):
     assert list(st[1:4]) == [3, 3, 3]
     assert np.any(st == 7)
     assert_same(ll, st, ref)
+
+
+def test_erk_bench_batch_sampled(orc):
+    """The bench's ERK batch at full size (65,536 theta x 6 input patterns) on
+    the GPU; 256 theta of it recomputed by the oracle, step counts included."""
+    from paper_1606_08281_amd import lik
+    wl = W.erk_workload(n_theta=65536, spread=0.3)
+    _say("ERK bench batch 65536 x 6 on the GPU")
+    ll, st, steps = lik.ode_eval(lik.OdeModel(wl["spec"]), wl["theta"], wl["trajectories"],
+                                 steps=True)
+    pick = np.random.default_rng(9).choice(65536, 256, replace=False)
+    ref = orc.ode_eval(orc.OdeProblem(wl["spec"], wl["theta"][pick], wl["trajectories"]))
+    assert np.array_equal(st[pick], ref["status"])
+    assert np.array_equal(ll[pick], ref["loglik"])
+    assert np.array_equal(steps[pick].ravel(), ref["traj_steps"])

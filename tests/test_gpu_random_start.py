@@ -115,3 +115,30 @@ def test_random_start_graph_replays_equal_eager():
     # the seed reaches the initial draws too
     assert not np.array_equal(eager.run(theta, 3)[0].cpu().numpy(),
                               eager.run(theta, 4)[0].cpu().numpy())
+
+
+def test_lacgfp_bench_batch_sampled(orc):
+    """The bench's Lac-Gfp batch at full size (1024 theta x 5 trajectories x
+    200 particles x 29 observations) on the GPU, a sample recomputed by the
+    oracle: the cheapest, a middle and the two heaviest theta of an oracle
+    cost ranking (events of every theta at 8 particles on one trajectory)."""
+    import time
+    from paper_1606_08281_amd import lik
+    wl = W.lacgfp_workload(theta=W.lacgfp_population(1024), n_traj=5, n_particles=200)
+    P = orc.Problem(wl.net.orders, wl.net.stoich, wl.obs_kind, wl.observed, wl.sigma, wl.theta,
+                    wl.trajectories[:1], 8, wl.seed)
+    rank = np.argsort(-orc.evaluate(P)["events"])
+    pick = np.array([rank[-1], rank[512], rank[1], rank[0]])
+    _say("lac-gfp bench batch 1024 x 5 x 200 x 29 on the GPU")
+    net = lik.Network(wl.net.orders, wl.net.stoich)
+    got = lik.eval_batch(net, wl.obs_kind, wl.observed, wl.sigma, wl.theta, wl.trajectories,
+                         200, wl.seed, aux=True)
+    t0 = time.time()
+    ref = _oracle(orc, wl, theta=wl.theta[pick], theta_ids=pick.astype(np.uint32))
+    _say("oracle sample", pick, f"{time.time() - t0:.1f} s")
+    F = np.concatenate([np.arange(5 * i, 5 * i + 5) for i in pick])
+    sub = {"status": got["status"][pick], "loglik": got["loglik"][pick],
+           "filter_events": got["filter_events"][F], "filter_loglik": got["filter_loglik"][F],
+           "final_state": got["final_state"][F]}
+    assert np.all(ref["status"] == 0)
+    assert_parity(sub, ref)
