@@ -481,6 +481,17 @@ def main():
         out["uneven"] = SB.uneven_block(log=lambda m: print("[bench] uneven:", m, flush=True,
                                                             file=sys.stderr))
         out["uneven"]["wall_s"] = time.perf_counter() - t_u0
+        print("[bench] sampler-stream block: level-set sampler runs against one server",
+              flush=True, file=sys.stderr)
+        from paper_1606_08281_amd import serve_lns as SL
+        t_l0 = time.perf_counter()
+        say_l = lambda m: print("[bench] sampler:", m, flush=True, file=sys.stderr)  # noqa: E731
+        rep, recs, nets_l = SL.closed_loop(N=120, levels=4, check=16, log=say_l)
+        rep.pop("samplers", None)
+        rep["replay"] = SL.replay(recs, nets_l, 1500, log=say_l)
+        rep["workload"] = SL.WORKLOAD.replace("N 200", "N 120") + "; 4 levels"
+        rep["wall_s"] = time.perf_counter() - t_l0
+        out["sampler_stream"] = rep
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", flush=True, file=sys.stderr)
         out["cpu_baseline"] = (cpu_baseline(wl, per_call=1, t_sub=10) if args.workload == "random"
