@@ -42,8 +42,7 @@ using namespace lik;
 
 template <int UMAX>
 __global__ void __launch_bounds__(64) k_ode(OdeArgs a) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < a.n_theta * a.M) ode_lane<OdeGeneric<UMAX>>(a, f);
+    ode_run<OdeGeneric<UMAX>>(a);
 }
 
 // per theta: the sum over its trajectories in order; the first non-OK status
@@ -68,9 +67,18 @@ std::string hexd(double v) {
     return b;
 }
 
+// Stride (in doubles) of the lanes' parameter slots in LDS: odd, so that the
+// slots a wavefront reads at once fall in different banks, except at the
+// largest V, where 64 slots of 128 fill the 64 KiB a workgroup may take.
+int ode_par_stride(int V) { return V % 2 == 1 || V == LIK_ODE_MAX_PARAMS ? V : V + 1; }
+
+// LDS bytes of the specialised kernel's launch: one parameter slot per lane.
+size_t ode_par_lds(int V) { return (size_t)64 * ode_par_stride(V) * sizeof(double); }
+
 // The model as code: its flux terms with constant indices (the same
-// operations, in the same order, as OdeGeneric::rhs), the lane's parameters
-// copied into a local array, the observation mean with constant indices.
+// operations, in the same order, as OdeGeneric::rhs), the parameters of the
+// lane's current theta read from its slot in LDS (copied there when the lane
+// takes a pair), the observation mean with constant indices.
 std::string ode_spec_source(const lik_ode_model &m) {
     const int U = m.n_species, V = m.n_params;
     std::ostringstream o;
@@ -79,24 +87,33 @@ std::string ode_spec_source(const lik_ode_model &m) {
          "typedef __hip_internal::int32_t int32_t;\n"
          "typedef __hip_internal::int64_t int64_t;\n"
          "#include \"ode.hpp\"\n"
+         "extern __shared__ double lik_ode_par[];\n"
          "namespace lik {\n"
          "static_assert(sizeof(OdeArgs) == "
       << sizeof(OdeArgs) << ", \"OdeArgs layout\");\n"
       << "struct OdeSpec {\n  static constexpr int U = " << U << ";\n"
-      << "  struct Params { double v[" << V << "]; };\n"
-      << "  __device__ static Params load(const double *th) {\n    Params p;\n"
-      << "    for (int k = 0; k < " << V << "; ++k) p.v[k] = th[k];\n    return p;\n  }\n"
+      << "  struct Params { int off; };\n"
+      << "  __device__ static Params load(const OdeArgs &a, int i) {\n"
+      << "    const int o = (int)threadIdx.x * " << ode_par_stride(V) << ";\n"
+      << "    for (int k = 0; k < " << V << "; ++k) lik_ode_par[o + k] = a.theta[(size_t)i * "
+      << V << " + k];\n    return Params{o};\n  }\n"
+      // the offset passes through an empty asm so that every evaluation
+      // reads its parameters from LDS anew instead of the compiler keeping
+      // all of them in registers across the step loop
+      << "  __device__ static const double *row(const Params &p) {\n"
+      << "    int o = p.off;\n    asm volatile(\"\" : \"+v\"(o));\n"
+      << "    return lik_ode_par + o;\n  }\n"
       << "  __device__ static void rhs(const OdeArgs &, const Params &p, double u, const double *x,"
-         " double *dx) {\n";
+         " double *dx) {\n    const double *pv = row(p);\n";
     for (int s = 0; s < U; ++s) o << "    dx[" << s << "] = 0.0;\n";
     for (int k = 0; k < m.n_terms; ++k) {
         const lik_ode_term &T = m.terms[k];
         o << "    { double v = " << hexd(T.rate_scale);
-        if (T.rate_param >= 0) o << " * p.v[" << T.rate_param << "]";
+        if (T.rate_param >= 0) o << " * pv[" << T.rate_param << "]";
         o << ";\n";
         for (int f = 0; f < T.n_factors; ++f) {
             const std::string xs = "x[" + std::to_string(T.species[f]) + "]";
-            const std::string K = "p.v[" + std::to_string(T.param[f]) + "]";
+            const std::string K = "pv[" + std::to_string(T.param[f]) + "]";
             std::string phi;
             switch (T.kind[f]) {
                 case LIK_ODE_INPUT: phi = "u"; break;
@@ -113,11 +130,12 @@ std::string ode_spec_source(const lik_ode_model &m) {
         if (T.to >= 0) o << "      dx[" << T.to << "] = dx[" << T.to << "] + v;\n";
         o << "    }\n";
     }
-    o << "  }\n  __device__ static double obs(const OdeArgs &, const Params &p, const double *x) {\n";
+    o << "  }\n  __device__ static double obs(const OdeArgs &, const Params &p, const double *x) {\n"
+         "    const double *pv = row(p);\n    (void)pv;\n";
     if (m.obs_kind == LIK_ODE_OBS_SPECIES) {
         o << "    return x[" << m.obs_species << "];\n";
     } else {
-        auto P = [&](int k) { return "p.v[" + std::to_string(m.fret_param[k]) + "]"; };
+        auto P = [&](int k) { return "pv[" + std::to_string(m.fret_param[k]) + "]"; };
         o << "    const double xa = x[" << m.obs_species << "], xb = x[" << m.obs_species2 << "];\n"
           << "    const double num = (" << P(2) << " * " << P(3) << ") * xa;\n"
           << "    const double den = (xb + (1.0 - " << P(2) << ") * xa) * " << P(4) << ";\n"
@@ -125,8 +143,7 @@ std::string ode_spec_source(const lik_ode_model &m) {
     }
     o << "  }\n};\n}  // namespace lik\n"
          "extern \"C\" __global__ void __launch_bounds__(64) lik_ode_spec(lik::OdeArgs a) {\n"
-         "  const int f = blockIdx.x * blockDim.x + threadIdx.x;\n"
-         "  if (f < a.n_theta * a.M) lik::ode_lane<lik::OdeSpec>(a, f);\n}\n";
+         "  lik::ode_run<lik::OdeSpec>(a);\n}\n";
     return o.str();
 }
 
@@ -297,18 +314,18 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
                          (size_t)total * 8, (size_t)M * 8, (size_t)M * U * 8,
                          data->in_offsets ? (size_t)(M + 1) * 4 : 0, (size_t)n_in * 8,
                          (size_t)n_in * 8, F * 8, F * 4, (size_t)n_theta * 8, (size_t)n_theta * 4,
-                         F * 4};
+                         F * 4, 4};
     const void *src[] = {model->m.terms, model->m.x0_param, theta, data->obs_offsets, data->t_obs,
                          data->y, data->t0, data->x0, data->in_offsets, data->t_in, data->u_in,
-                         nullptr, nullptr, nullptr, nullptr, nullptr};
+                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     size_t bytes = 0;
     for (size_t v : sz) bytes += align256(v);
     char *dev = nullptr;
     hipError_t e = hipMalloc((void **)&dev, bytes + 256);
     if (e != hipSuccess) return fail(LIK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    void *ptr[16];
+    void *ptr[17];
     size_t off = 0;
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < 17; ++k) {
         ptr[k] = sz[k] ? dev + off : nullptr;
         off += align256(sz[k]);
     }
@@ -342,6 +359,7 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
     a.tll = (double *)ptr[11];
     a.tst = (int32_t *)ptr[12];
     a.tsteps = (int32_t *)ptr[15];
+    a.next = (unsigned int *)ptr[16];
     double *d_ll = (double *)ptr[13];
     int32_t *d_st = (int32_t *)ptr[14];
     hipFunction_t spec = nullptr;
@@ -360,11 +378,25 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
         for (int k = 0; k < 11 && e == hipSuccess; ++k)
             if (sz[k]) e = hipMemcpyAsync(ptr[k], src[k], sz[k], hipMemcpyHostToDevice, s);
         if (e != hipSuccess) { rc = hip_fail(e, "copy to device"); break; }
-        const unsigned blocks = (unsigned)((F + 63) / 64);
+        if ((e = hipMemsetAsync(a.next, 0, 4, s)) != hipSuccess) { rc = hip_fail(e, "memset"); break; }
+        // every lane takes pairs until none is left: as many workgroups as
+        // can be resident at once (more would only find the counter spent)
+        const unsigned lds = spec ? (unsigned)ode_par_lds(V) : 0u;
+        const void *gen = U <= 4 ? (const void *)k_ode<4> : U <= 8 ? (const void *)k_ode<8>
+                        : U <= 16 ? (const void *)k_ode<16> : (const void *)k_ode<32>;
+        unsigned blocks = (unsigned)((F + 63) / 64);
+        int per_cu = 0, cus = 0, dev_id = 0;
+        const hipError_t eo = spec ? hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(
+                                         &per_cu, spec, 64, lds)
+                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen, 64, 0);
+        if (eo == hipSuccess && per_cu > 0 && hipGetDevice(&dev_id) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess &&
+            cus > 0)
+            blocks = std::min(blocks, (unsigned)(per_cu * cus));
         hipEvent_t t0 = timing_begin(s);  // timed as a propagation launch
         if (spec) {
             void *params[] = {(void *)&a};
-            e = hipModuleLaunchKernel(spec, blocks, 1, 1, 64, 1, 1, 0, s, params, nullptr);
+            e = hipModuleLaunchKernel(spec, blocks, 1, 1, 64, 1, 1, lds, s, params, nullptr);
             if (e != hipSuccess) { rc = hip_fail(e, "ode launch"); break; }
         } else if (U <= 4) hipLaunchKernelGGL(k_ode<4>, dim3(blocks), dim3(64), 0, s, a);
         else if (U <= 8) hipLaunchKernelGGL(k_ode<8>, dim3(blocks), dim3(64), 0, s, a);
