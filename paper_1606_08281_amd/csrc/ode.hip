@@ -309,23 +309,35 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
             }
     }
     const size_t F = (size_t)n_theta * M;
+    // Pairs are taken trajectory by trajectory, the trajectories with the
+    // most stops (observations and input breakpoints, each a restart of the
+    // step size) first: their pairs tend to take the most steps, and a lane
+    // that ends the launch on a short pair leaves less of a tail.
+    std::vector<int32_t> m_order(M);
+    for (int m = 0; m < M; ++m) m_order[m] = m;
+    auto stops = [&](int m) {
+        return (data->obs_offsets[m + 1] - data->obs_offsets[m]) +
+               (data->in_offsets ? data->in_offsets[m + 1] - data->in_offsets[m] : 0);
+    };
+    std::stable_sort(m_order.begin(), m_order.end(),
+                     [&](int32_t x, int32_t y) { return stops(x) > stops(y); });
     const size_t sz[] = {(size_t)model->m.n_terms * sizeof(lik_ode_term), (size_t)U * 4,
                          (size_t)n_theta * V * 8, (size_t)(M + 1) * 4, (size_t)total * 8,
                          (size_t)total * 8, (size_t)M * 8, (size_t)M * U * 8,
                          data->in_offsets ? (size_t)(M + 1) * 4 : 0, (size_t)n_in * 8,
                          (size_t)n_in * 8, F * 8, F * 4, (size_t)n_theta * 8, (size_t)n_theta * 4,
-                         F * 4, 4};
+                         F * 4, 4, (size_t)M * 4};
     const void *src[] = {model->m.terms, model->m.x0_param, theta, data->obs_offsets, data->t_obs,
                          data->y, data->t0, data->x0, data->in_offsets, data->t_in, data->u_in,
-                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, m_order.data()};
     size_t bytes = 0;
     for (size_t v : sz) bytes += align256(v);
     char *dev = nullptr;
     hipError_t e = hipMalloc((void **)&dev, bytes + 256);
     if (e != hipSuccess) return fail(LIK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    void *ptr[17];
+    void *ptr[18];
     size_t off = 0;
-    for (int k = 0; k < 17; ++k) {
+    for (int k = 0; k < 18; ++k) {
         ptr[k] = sz[k] ? dev + off : nullptr;
         off += align256(sz[k]);
     }
@@ -360,6 +372,7 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
     a.tst = (int32_t *)ptr[12];
     a.tsteps = (int32_t *)ptr[15];
     a.next = (unsigned int *)ptr[16];
+    a.m_order = (const int32_t *)ptr[17];
     double *d_ll = (double *)ptr[13];
     int32_t *d_st = (int32_t *)ptr[14];
     hipFunction_t spec = nullptr;
@@ -375,8 +388,8 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
     rc = LIK_OK;
     do {
         if ((e = hipStreamCreate(&s)) != hipSuccess) { rc = hip_fail(e, "hipStreamCreate"); break; }
-        for (int k = 0; k < 11 && e == hipSuccess; ++k)
-            if (sz[k]) e = hipMemcpyAsync(ptr[k], src[k], sz[k], hipMemcpyHostToDevice, s);
+        for (int k = 0; k < 18 && e == hipSuccess; ++k)
+            if (sz[k] && src[k]) e = hipMemcpyAsync(ptr[k], src[k], sz[k], hipMemcpyHostToDevice, s);
         if (e != hipSuccess) { rc = hip_fail(e, "copy to device"); break; }
         if ((e = hipMemsetAsync(a.next, 0, 4, s)) != hipSuccess) { rc = hip_fail(e, "memset"); break; }
         // every lane takes pairs until none is left: as many workgroups as

@@ -34,6 +34,7 @@ struct OdeArgs {
     int32_t *tst;    // [F] per-trajectory status
     int32_t *tsteps; // [F] step attempts
     unsigned int *next;  // the next pair to take (zero at launch)
+    const int32_t *m_order;  // [M] trajectories in the order their pairs are taken
 };
 
 // The model interpreted at run time: terms from memory, every index
@@ -189,7 +190,8 @@ __device__ __forceinline__ double ode_step_factor(double err) {
 
 // Every lane of the launch runs this loop: it takes (theta, trajectory) pairs
 // f = i * M + m from the shared counter a.next until none is left, and solves
-// one at a time.  The loop is flat, one step attempt per pass: a lane that
+// one at a time; the counter runs over trajectories in the order m_order
+// (all theta of one trajectory, then the next).  The loop is flat, one step attempt per pass: a lane that
 // reaches an input breakpoint or an observation handles it at the top of its
 // next pass, and a lane whose trajectory ends writes its results and starts
 // the next pair there, so the lanes of a wavefront keep stepping side by side
@@ -220,13 +222,14 @@ __device__ __forceinline__ void ode_run(const OdeArgs &a) {
     int m = 0, o0 = 0, T = 0, q0 = 0, nq = 0, q = 0, k = 0, steps = 0;
     int status = LIK_STATUS_OK;
     bool live = false;  // a pair in progress
-    int f = (int)atomicAdd(a.next, 1u);
+    int idx = (int)atomicAdd(a.next, 1u), f = 0;
     for (;;) {
         if (!live) {
             // the next pair; one with bad parameters is finished at once
-            if (f >= F) break;
-            const int i = f / a.M;
-            m = f - i * a.M;
+            if (idx >= F) break;
+            const int r = idx / a.n_theta, i = idx - r * a.n_theta;
+            m = a.m_order[r];
+            f = i * a.M + m;
             const double *th = a.theta + (size_t)i * a.V;
             bool bad = false;
             for (int v = 0; v < a.V; ++v)
@@ -236,7 +239,7 @@ __device__ __forceinline__ void ode_run(const OdeArgs &a) {
                 a.tll[f] = __builtin_nan("");
                 a.tst[f] = LIK_STATUS_BAD_THETA;
                 a.tsteps[f] = 0;
-                f = (int)atomicAdd(a.next, 1u);
+                idx = (int)atomicAdd(a.next, 1u);
                 continue;
             }
             p = Model::load(a, i);
@@ -300,7 +303,7 @@ __device__ __forceinline__ void ode_run(const OdeArgs &a) {
             a.tst[f] = status;
             a.tsteps[f] = steps;
             live = false;
-            f = (int)atomicAdd(a.next, 1u);
+            idx = (int)atomicAdd(a.next, 1u);
             continue;
         }
         // one step attempt toward stop
