@@ -190,6 +190,12 @@ def bench_erk(args):
     trajs = wl["trajectories"]
     kw = dict(rtol=1e-6, atol=1e-9, max_steps=100000)
     say = lambda m: print("[bench]", m, flush=True, file=sys.stderr)  # noqa: E731
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     say(f"erk workload ready: {n} theta x {len(trajs)} input patterns x 60 FRET observations")
     for w in range(args.warmup):
         lik.ode_eval(model, wl["theta"], trajs, **kw)
@@ -208,6 +214,9 @@ def bench_erk(args):
     flops, slots = ode_step_work(wl["spec"])
     kernel_s = tm["propagate_ms"] / 1e3
     achieved = steps_total * slots / kernel_s / 1e12
+    from paper_1606_08281_amd import profsum_ode
+    rec = profsum_ode.read_record(os.path.join(
+        ROOT, "profiles", "lik_ode_spec_traffic_erk_65536x6x60_fp64.txt"))
     out = {
         "metric": "deterministic likelihood evals/s", "value": n * args.steps / elapsed,
         "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -221,7 +230,13 @@ def bench_erk(args):
         "solver_steps_per_eval": steps_total / (n * args.steps),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / (VALU_PEAK_LANE_OPS / 1e12),
-                     "traffic": None,
+                     "traffic": float(rec["hbm_bytes_per_launch"]) if rec else None,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated; null unless the committed counter "
+                                     "record matches the solver sources)",
+                     "measured_slots_per_attempt": (float(rec["lane_slots_per_attempt"])
+                                                    if rec else None),
+                     "lane_utilisation": float(rec["lane_utilisation"]) if rec else None,
                      "fp64_tflops": steps_total * flops / kernel_s / 1e12,
                      "kernel": "lik_ode_spec (the model compiled with hipRTC): one lane per "
                                "(theta, input pattern)",
