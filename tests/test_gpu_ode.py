@@ -97,3 +97,25 @@ def test_erk_bench_batch_sampled(orc):
     assert np.array_equal(st[pick], ref["status"])
     assert np.array_equal(ll[pick], ref["loglik"])
     assert np.array_equal(steps[pick].ravel(), ref["traj_steps"])
+
+
+@pytest.mark.parametrize("n_theta", [1, 7, 13, 300])
+def test_pair_queue_order_and_ragged_sizes(orc, n_theta):
+    """Lanes take (theta, trajectory) pairs from a shared counter, the
+    trajectories with the most stops first: trajectories whose stop counts
+    rise with their index (so the order is reversed), one with input
+    breakpoints, and pair counts that leave the last wavefront part-full or
+    take one lane; every result lands at its own (theta, trajectory)."""
+    rng = np.random.default_rng(31 + n_theta)
+    trajs = []
+    for m in range(5):
+        t = np.linspace(0.3, 10.0, 4 + 5 * m)
+        tr = {"t_obs": t, "y": rng.normal(20, 4, len(t)), "x0": [1.0 + m]}
+        if m == 3:
+            tr.update(t_in=np.array([0.0, 2.0, 6.5]), u_in=np.array([1.0, 0.0, 2.0]))
+        trajs.append(tr)
+    spec = dict(imm_death_model(), terms=[{"to": 0, "rate_param": 0, "factors": [(4, 0, 0)]},
+                                          {"frm": 0, "rate_param": 1, "factors": [(0, 0, 0)]}])
+    theta = np.exp(rng.normal(0.0, 1.0, (n_theta, 2))) * np.array([8.0, 0.5])
+    _say("pair queue: immigration-death with input, 5 trajectories,", n_theta, "theta")
+    assert_same(*both(orc, spec, theta, trajs, rtol=1e-7, atol=1e-10))
