@@ -602,8 +602,10 @@ typedef struct lik_ode_data {
  * LIK_KERNEL_SPECIALIZED (the model compiled with hipRTC into code with
  * constant indices, cached on disk like the networks' kernels; LIK_EDEVICE if
  * that fails) or LIK_KERNEL_AUTO (specialised, else generic); every variant
- * gives identical results.  One lane of the GPU integrates one (theta,
- * trajectory) pair.  Synchronous; allocates its device memory.
+ * gives identical results.  Each (theta, trajectory) pair is integrated by
+ * one GPU lane; the lanes take pairs from a shared counter, the trajectories
+ * with the most stops (observations plus input breakpoints) first, which
+ * changes only the speed.  Synchronous; allocates its device memory.
  */
 int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta,
                  const lik_ode_data *data, double rtol, double atol, int32_t max_steps,
