@@ -329,24 +329,36 @@ def main():
         tuning = db.autotune(theta, wl.seed, stream=stream)
         print(f"[bench] autotuned: {tuning}", flush=True, file=sys.stderr)
 
+    # per-step event totals and maxima accumulate on the device, in stream
+    # order, so the timed steps run back to back with no host round trip
+    ev_sum = torch.zeros((), dtype=torch.float64, device="cuda")
+    ev_max = torch.zeros((), dtype=torch.float64, device="cuda")
+
+    def count_events():
+        ev = db.events.to(torch.float64)
+        ev_sum.add_(ev.sum())
+        torch.maximum(ev_max, ev.max(), out=ev_max)
+
     for w in range(args.warmup):
         db.run(theta, wl.seed, stream=stream)
+        count_events()  # (the warmup also loads torch's reduction kernels)
         torch.cuda.synchronize()
         print(f"[bench] warmup {w + 1}/{args.warmup} done", flush=True, file=sys.stderr)
+    ev_sum.zero_()
+    ev_max.zero_()
 
     lik.timing_read()
     lik.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    events = 0
-    max_per_particle = 0.0
     for k in range(args.steps):
         db.run(theta, wl.seed + k, stream=stream)
-        events += int(db.events.sum().item())  # synchronises: counted per step
-        max_per_particle = max(max_per_particle, float(db.events.max().item()) / wl.n_particles)
-        print(f"[bench] step {k + 1}/{args.steps} done", flush=True, file=sys.stderr)
+        count_events()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    print(f"[bench] {args.steps} steps done", flush=True, file=sys.stderr)
+    events = int(ev_sum.item())
+    max_per_particle = float(ev_max.item()) / wl.n_particles
     lik.timing_enable(False)
     tm = lik.timing_read()
     status = db.status.cpu().numpy()
