@@ -611,6 +611,31 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta,
                  const lik_ode_data *data, double rtol, double atol, int32_t max_steps,
                  int32_t kernel, double *loglik_out, int32_t *status_out, int32_t *steps_out);
 
+/*
+ * lik_ode_workspace_size -- bytes of device workspace lik_ode_eval_device
+ * needs for n_theta parameter vectors and n_traj trajectories (0 on a bad
+ * argument).
+ *
+ * lik_ode_eval_device -- lik_ode_eval on device buffers, enqueued on `stream`
+ * (a hipStream_t; NULL: the null stream) without waiting: theta [n_theta * V],
+ * every array of `data`, loglik [n_theta], status [n_theta] (may be NULL) and
+ * steps [n_theta * M] (may be NULL) are device pointers; obs_offsets_host and
+ * in_offsets_host are host copies of data->obs_offsets and data->in_offsets
+ * (both NULL or both given), checked like lik_ode_eval's; the values of the
+ * device arrays are the caller's to keep valid (the rules of lik_ode_data),
+ * and the device offsets must equal the host copies.  workspace: device
+ * memory of lik_ode_workspace_size bytes, owned by the caller, not to be
+ * shared by calls in flight.  The first call on a device copies the model's
+ * terms there (synchronously); later calls copy nothing from the host.
+ * Results are identical to lik_ode_eval's.
+ */
+size_t lik_ode_workspace_size(lik_ode_t model, int32_t n_theta, int32_t n_traj);
+int lik_ode_eval_device(lik_ode_t model, int32_t n_theta, const double *theta,
+                        const lik_ode_data *data, const int32_t *obs_offsets_host,
+                        const int32_t *in_offsets_host, double rtol, double atol,
+                        int32_t max_steps, int32_t kernel, double *loglik, int32_t *status,
+                        int32_t *steps, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Thread-local description of the last error returned on this thread. */
 const char *lik_last_error(void);
 

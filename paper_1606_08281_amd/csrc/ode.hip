@@ -34,6 +34,8 @@ struct lik_ode_t_ {
     // the model-specialised kernel, per device
     std::mutex mu;
     std::map<int, std::pair<hipModule_t, hipFunction_t>> spec;
+    // the terms and x0_param in device memory, per device (made on first use)
+    std::map<int, char *> dev;
 };
 
 namespace {
@@ -43,6 +45,23 @@ using namespace lik;
 template <int UMAX>
 __global__ void __launch_bounds__(64) k_ode(OdeArgs a) {
     ode_run<OdeGeneric<UMAX>>(a);
+}
+
+// The order in which the lanes take trajectories: by stops (observations plus
+// input breakpoints) from most to fewest, ties in index order; thread m
+// places trajectory m at its rank.  Thread 0 also zeroes the pair counter.
+__global__ void k_ode_order(const int32_t *obs_off, const int32_t *in_off, int32_t M,
+                            int32_t *order, unsigned int *next) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m == 0) *next = 0u;
+    if (m >= M) return;
+    const int sm = (obs_off[m + 1] - obs_off[m]) + (in_off ? in_off[m + 1] - in_off[m] : 0);
+    int rank = 0;
+    for (int j = 0; j < M; ++j) {
+        const int sj = (obs_off[j + 1] - obs_off[j]) + (in_off ? in_off[j + 1] - in_off[j] : 0);
+        rank += (sj > sm || (sj == sm && j < m)) ? 1 : 0;
+    }
+    order[rank] = m;
 }
 
 // per theta: the sum over its trajectories in order; the first non-OK status
@@ -225,6 +244,147 @@ int check_model(const lik_ode_model *md) {
     return LIK_OK;
 }
 
+// The model's terms and x0_param in device memory on the current device
+// (copied on the first call there, kept until lik_ode_destroy).
+int model_on_device(lik_ode_t_ &md, const lik_ode_term **terms, const int32_t **x0p) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(md.mu);
+    const size_t tb = align256(md.terms.size() * sizeof(lik_ode_term));
+    auto it = md.dev.find(dev);
+    char *p = it != md.dev.end() ? it->second : nullptr;
+    if (!p) {
+        const size_t xb = md.x0_param.size() * sizeof(int32_t);
+        if ((e = hipMalloc((void **)&p, tb + xb)) != hipSuccess)
+            return fail(LIK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        if ((e = hipMemcpy(p, md.terms.data(), md.terms.size() * sizeof(lik_ode_term),
+                           hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p + tb, md.x0_param.data(), xb, hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(p);
+            return hip_fail(e, "copy of the model to the device");
+        }
+        md.dev[dev] = p;
+    }
+    *terms = (const lik_ode_term *)p;
+    *x0p = (const int32_t *)(p + tb);
+    return LIK_OK;
+}
+
+// Arguments common to both entry points.
+int check_call(lik_ode_t model, int32_t n_theta, const lik_ode_data *data, double rtol,
+               double atol, int32_t max_steps, int32_t kernel) {
+    if (!model) return fail(LIK_EINVAL, "model is NULL");
+    if (kernel < LIK_KERNEL_AUTO || kernel > LIK_KERNEL_SPECIALIZED)
+        return fail(LIK_EINVAL, "unknown kernel variant");
+    if (!data) return fail(LIK_EINVAL, "data is NULL");
+    if (n_theta < 0 || n_theta >= (1 << 26)) return fail(LIK_EINVAL, "n_theta out of range");
+    if (!(rtol > 0.0) || !(atol > 0.0) || isinf(rtol) || isinf(atol))
+        return fail(LIK_EINVAL, "rtol and atol must be finite and > 0");
+    if (max_steps < 1 || max_steps > (1 << 30)) return fail(LIK_EINVAL, "max_steps out of [1, 2^30]");
+    const int M = data->n_traj;
+    if (M < 1 || M > LIK_MAX_TRAJ) return fail(LIK_EINVAL, "n_traj out of range");
+    if ((int64_t)n_theta * M >= ((int64_t)1 << 30)) return fail(LIK_EINVAL, "too many trajectories");
+    return LIK_OK;
+}
+
+// Input offsets (host copy): in_offsets[0] = 0, never decreasing; their total.
+int check_in_offsets(const int32_t *in_offsets, int M, int64_t *n_in) {
+    *n_in = 0;
+    if (!in_offsets) return LIK_OK;
+    if (in_offsets[0] != 0) return fail(LIK_EINVAL, "in_offsets[0] must be 0");
+    for (int m = 0; m < M; ++m)
+        if (in_offsets[m + 1] < in_offsets[m]) return fail(LIK_EINVAL, "in_offsets must not decrease");
+    *n_in = in_offsets[M];
+    return LIK_OK;
+}
+
+// The model's fields of the kernel arguments.
+void model_args(const lik_ode_t_ &md, OdeArgs *a) {
+    a->U = md.m.n_species;
+    a->V = md.m.n_params;
+    a->n_terms = md.m.n_terms;
+    a->obs_kind = md.m.obs_kind;
+    a->obs_species = md.m.obs_species;
+    a->obs_species2 = md.m.obs_kind == LIK_ODE_OBS_FRET ? md.m.obs_species2 : -1;
+    a->sd_param = md.m.sd_param;
+    a->sd_const = md.m.sd_const;
+    for (int k = 0; k < 5; ++k) a->fret[k] = md.m.fret_param[k];
+}
+
+// The specialised kernel when asked for (or by default, where it compiles).
+int pick_kernel(lik_ode_t_ &md, int32_t kernel, hipFunction_t *spec) {
+    *spec = nullptr;
+    if (kernel == LIK_KERNEL_GENERIC) return LIK_OK;
+    std::string msg;
+    *spec = ode_spec_kernel(md, &msg);
+    if (!*spec && kernel == LIK_KERNEL_SPECIALIZED)
+        return fail(LIK_EDEVICE, "specialised ODE kernel unavailable: " + msg);
+    return LIK_OK;
+}
+
+// Enqueues on s: the trajectory order (and the zeroed pair counter), the
+// solver over every pair, and the per-theta sums.  Every pointer in a is a
+// device pointer.
+int ode_enqueue(const OdeArgs &a, hipFunction_t spec, double *loglik, int32_t *status,
+                hipStream_t s) {
+    const int U = a.U, V = a.V, M = a.M, n_theta = a.n_theta;
+    const size_t F = (size_t)n_theta * M;
+    hipLaunchKernelGGL(k_ode_order, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s,
+                       a.obs_offsets, a.in_offsets, M, const_cast<int32_t *>(a.m_order), a.next);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "ode order launch");
+    // every lane takes pairs until none is left: as many workgroups as can
+    // be resident at once (more would only find the counter spent)
+    const unsigned lds = spec ? (unsigned)ode_par_lds(V) : 0u;
+    const void *gen = U <= 4 ? (const void *)k_ode<4> : U <= 8 ? (const void *)k_ode<8>
+                    : U <= 16 ? (const void *)k_ode<16> : (const void *)k_ode<32>;
+    unsigned blocks = (unsigned)((F + 63) / 64);
+    int per_cu = 0, cus = 0, dev_id = 0;
+    const hipError_t eo = spec ? hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, spec,
+                                                                                    64, lds)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen, 64, 0);
+    if (eo == hipSuccess && per_cu > 0 && hipGetDevice(&dev_id) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess &&
+        cus > 0)
+        blocks = std::min(blocks, (unsigned)(per_cu * cus));
+    hipEvent_t t0 = timing_begin(s);  // timed as a propagation launch
+    if (spec) {
+        OdeArgs ac = a;
+        void *params[] = {(void *)&ac};
+        e = hipModuleLaunchKernel(spec, blocks, 1, 1, 64, 1, 1, lds, s, params, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "ode launch");
+    } else if (U <= 4) hipLaunchKernelGGL(k_ode<4>, dim3(blocks), dim3(64), 0, s, a);
+    else if (U <= 8) hipLaunchKernelGGL(k_ode<8>, dim3(blocks), dim3(64), 0, s, a);
+    else if (U <= 16) hipLaunchKernelGGL(k_ode<16>, dim3(blocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_ode<32>, dim3(blocks), dim3(64), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "ode launch");
+    timing_end_propagate(t0, s);
+    hipLaunchKernelGGL(k_ode_finish, dim3((unsigned)((n_theta + 255) / 256)), dim3(256), 0, s,
+                       a.tll, a.tst, n_theta, M, loglik, status);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "ode finish launch");
+    return LIK_OK;
+}
+
+// Per-call device scratch after the inputs: trajectory log-likelihoods and
+// statuses, step counts, the pair counter, the trajectory order.
+size_t scratch_bytes(size_t F, int M) {
+    return align256(F * 8) + align256(F * 4) + align256(F * 4) + align256(4) +
+           align256((size_t)M * 4);
+}
+
+void carve_scratch(char *p, size_t F, int M, OdeArgs *a, int32_t *steps) {
+    a->tll = (double *)p;
+    p += align256(F * 8);
+    a->tst = (int32_t *)p;
+    p += align256(F * 4);
+    a->tsteps = steps ? steps : (int32_t *)p;
+    p += align256(F * 4);
+    a->next = (unsigned int *)p;
+    p += align256(4);
+    a->m_order = (const int32_t *)p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -253,8 +413,10 @@ int lik_ode_precompile(lik_ode_t model) {
 }
 
 int lik_ode_destroy(lik_ode_t model) {
-    if (model)
+    if (model) {
         for (auto &kv : model->spec) (void)hipModuleUnload(kv.second.first);
+        for (auto &kv : model->dev) (void)hipFree(kv.second);
+    }
     delete model;
     return LIK_OK;
 }
@@ -262,34 +424,18 @@ int lik_ode_destroy(lik_ode_t model) {
 int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const lik_ode_data *data,
                  double rtol, double atol, int32_t max_steps, int32_t kernel,
                  double *loglik_out, int32_t *status_out, int32_t *steps_out) {
-    if (!model) return fail(LIK_EINVAL, "model is NULL");
-    if (kernel < LIK_KERNEL_AUTO || kernel > LIK_KERNEL_SPECIALIZED)
-        return fail(LIK_EINVAL, "unknown kernel variant");
-    if (!data) return fail(LIK_EINVAL, "data is NULL");
-    if (n_theta < 0 || n_theta >= (1 << 26)) return fail(LIK_EINVAL, "n_theta out of range");
-    if (!(rtol > 0.0) || !(atol > 0.0) || isinf(rtol) || isinf(atol))
-        return fail(LIK_EINVAL, "rtol and atol must be finite and > 0");
-    if (max_steps < 1 || max_steps > (1 << 30)) return fail(LIK_EINVAL, "max_steps out of [1, 2^30]");
+    int rc = check_call(model, n_theta, data, rtol, atol, max_steps, kernel);
+    if (rc) return rc;
     const int M = data->n_traj, U = model->m.n_species, V = model->m.n_params;
-    if (M < 1 || M > LIK_MAX_TRAJ) return fail(LIK_EINVAL, "n_traj out of range");
-    if ((int64_t)n_theta * M >= ((int64_t)1 << 30)) return fail(LIK_EINVAL, "too many trajectories");
     if (n_theta == 0) return LIK_OK;
     if (!theta || !loglik_out || !data->obs_offsets || !data->t_obs || !data->y || !data->t0 ||
         !data->x0)
         return fail(LIK_EINVAL, "NULL input or output pointer");
     int t_max = 0;
-    int64_t total = 0;
-    int rc = check_offsets(data->obs_offsets, M, &t_max, &total);
-    if (rc) return rc;
-    int64_t n_in = 0;
-    if (data->in_offsets) {
-        if (data->in_offsets[0] != 0) return fail(LIK_EINVAL, "in_offsets[0] must be 0");
-        for (int m = 0; m < M; ++m)
-            if (data->in_offsets[m + 1] < data->in_offsets[m])
-                return fail(LIK_EINVAL, "in_offsets must not decrease");
-        n_in = data->in_offsets[M];
-        if (n_in > 0 && (!data->t_in || !data->u_in)) return fail(LIK_EINVAL, "input arrays NULL");
-    }
+    int64_t total = 0, n_in = 0;
+    if ((rc = check_offsets(data->obs_offsets, M, &t_max, &total))) return rc;
+    if ((rc = check_in_offsets(data->in_offsets, M, &n_in))) return rc;
+    if (n_in > 0 && (!data->t_in || !data->u_in)) return fail(LIK_EINVAL, "input arrays NULL");
     for (int m = 0; m < M; ++m) {
         double prev = data->t0[m];
         if (!isfinite(prev)) return fail(LIK_EINVAL, "t0 must be finite");
@@ -308,118 +454,58 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
                     return fail(LIK_EINVAL, "input breakpoints must be finite and increase strictly");
             }
     }
+    hipFunction_t spec = nullptr;
+    if ((rc = pick_kernel(*model, kernel, &spec))) return rc;
+    OdeArgs a;
+    memset(&a, 0, sizeof(a));
+    if ((rc = model_on_device(*model, &a.terms, &a.x0_param))) return rc;
+    model_args(*model, &a);
+
     const size_t F = (size_t)n_theta * M;
-    // Pairs are taken trajectory by trajectory, the trajectories with the
-    // most stops (observations and input breakpoints, each a restart of the
-    // step size) first: their pairs tend to take the most steps, and a lane
-    // that ends the launch on a short pair leaves less of a tail.
-    std::vector<int32_t> m_order(M);
-    for (int m = 0; m < M; ++m) m_order[m] = m;
-    auto stops = [&](int m) {
-        return (data->obs_offsets[m + 1] - data->obs_offsets[m]) +
-               (data->in_offsets ? data->in_offsets[m + 1] - data->in_offsets[m] : 0);
-    };
-    std::stable_sort(m_order.begin(), m_order.end(),
-                     [&](int32_t x, int32_t y) { return stops(x) > stops(y); });
-    const size_t sz[] = {(size_t)model->m.n_terms * sizeof(lik_ode_term), (size_t)U * 4,
-                         (size_t)n_theta * V * 8, (size_t)(M + 1) * 4, (size_t)total * 8,
+    // inputs, the per-theta results, then the solver's scratch
+    const size_t sz[] = {(size_t)n_theta * V * 8, (size_t)(M + 1) * 4, (size_t)total * 8,
                          (size_t)total * 8, (size_t)M * 8, (size_t)M * U * 8,
                          data->in_offsets ? (size_t)(M + 1) * 4 : 0, (size_t)n_in * 8,
-                         (size_t)n_in * 8, F * 8, F * 4, (size_t)n_theta * 8, (size_t)n_theta * 4,
-                         F * 4, 4, (size_t)M * 4};
-    const void *src[] = {model->m.terms, model->m.x0_param, theta, data->obs_offsets, data->t_obs,
-                         data->y, data->t0, data->x0, data->in_offsets, data->t_in, data->u_in,
-                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, m_order.data()};
-    size_t bytes = 0;
+                         (size_t)n_in * 8, (size_t)n_theta * 8, (size_t)n_theta * 4};
+    const void *src[] = {theta, data->obs_offsets, data->t_obs, data->y, data->t0, data->x0,
+                         data->in_offsets, data->t_in, data->u_in, nullptr, nullptr};
+    constexpr int kN = (int)(sizeof(sz) / sizeof(sz[0]));
+    size_t bytes = scratch_bytes(F, M);
     for (size_t v : sz) bytes += align256(v);
     char *dev = nullptr;
     hipError_t e = hipMalloc((void **)&dev, bytes + 256);
     if (e != hipSuccess) return fail(LIK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    void *ptr[18];
+    void *ptr[kN];
     size_t off = 0;
-    for (int k = 0; k < 18; ++k) {
+    for (int k = 0; k < kN; ++k) {
         ptr[k] = sz[k] ? dev + off : nullptr;
         off += align256(sz[k]);
     }
-    OdeArgs a;
-    memset(&a, 0, sizeof(a));
-    a.terms = (const lik_ode_term *)ptr[0];
-    a.x0_param = (const int32_t *)ptr[1];
-    a.U = U;
-    a.V = V;
-    a.n_terms = model->m.n_terms;
-    a.obs_kind = model->m.obs_kind;
-    a.obs_species = model->m.obs_species;
-    a.obs_species2 = model->m.obs_kind == LIK_ODE_OBS_FRET ? model->m.obs_species2 : -1;
-    a.sd_param = model->m.sd_param;
-    a.sd_const = model->m.sd_const;
-    for (int k = 0; k < 5; ++k) a.fret[k] = model->m.fret_param[k];
-    a.theta = (const double *)ptr[2];
+    carve_scratch(dev + off, F, M, &a, nullptr);
+    a.theta = (const double *)ptr[0];
     a.n_theta = n_theta;
     a.M = M;
-    a.obs_offsets = (const int32_t *)ptr[3];
-    a.t_obs = (const double *)ptr[4];
-    a.y = (const double *)ptr[5];
-    a.t0 = (const double *)ptr[6];
-    a.x0 = (const double *)ptr[7];
-    a.in_offsets = (const int32_t *)ptr[8];
-    a.t_in = (const double *)ptr[9];
-    a.u_in = (const double *)ptr[10];
+    a.obs_offsets = (const int32_t *)ptr[1];
+    a.t_obs = (const double *)ptr[2];
+    a.y = (const double *)ptr[3];
+    a.t0 = (const double *)ptr[4];
+    a.x0 = (const double *)ptr[5];
+    a.in_offsets = (const int32_t *)ptr[6];
+    a.t_in = (const double *)ptr[7];
+    a.u_in = (const double *)ptr[8];
     a.rtol = rtol;
     a.atol = atol;
     a.max_steps = max_steps;
-    a.tll = (double *)ptr[11];
-    a.tst = (int32_t *)ptr[12];
-    a.tsteps = (int32_t *)ptr[15];
-    a.next = (unsigned int *)ptr[16];
-    a.m_order = (const int32_t *)ptr[17];
-    double *d_ll = (double *)ptr[13];
-    int32_t *d_st = (int32_t *)ptr[14];
-    hipFunction_t spec = nullptr;
-    if (kernel != LIK_KERNEL_GENERIC) {
-        std::string msg;
-        spec = ode_spec_kernel(*model, &msg);
-        if (!spec && kernel == LIK_KERNEL_SPECIALIZED) {
-            (void)hipFree(dev);
-            return fail(LIK_EDEVICE, "specialised ODE kernel unavailable: " + msg);
-        }
-    }
+    double *d_ll = (double *)ptr[9];
+    int32_t *d_st = (int32_t *)ptr[10];
     hipStream_t s = nullptr;
     rc = LIK_OK;
     do {
         if ((e = hipStreamCreate(&s)) != hipSuccess) { rc = hip_fail(e, "hipStreamCreate"); break; }
-        for (int k = 0; k < 18 && e == hipSuccess; ++k)
+        for (int k = 0; k < kN && e == hipSuccess; ++k)
             if (sz[k] && src[k]) e = hipMemcpyAsync(ptr[k], src[k], sz[k], hipMemcpyHostToDevice, s);
         if (e != hipSuccess) { rc = hip_fail(e, "copy to device"); break; }
-        if ((e = hipMemsetAsync(a.next, 0, 4, s)) != hipSuccess) { rc = hip_fail(e, "memset"); break; }
-        // every lane takes pairs until none is left: as many workgroups as
-        // can be resident at once (more would only find the counter spent)
-        const unsigned lds = spec ? (unsigned)ode_par_lds(V) : 0u;
-        const void *gen = U <= 4 ? (const void *)k_ode<4> : U <= 8 ? (const void *)k_ode<8>
-                        : U <= 16 ? (const void *)k_ode<16> : (const void *)k_ode<32>;
-        unsigned blocks = (unsigned)((F + 63) / 64);
-        int per_cu = 0, cus = 0, dev_id = 0;
-        const hipError_t eo = spec ? hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(
-                                         &per_cu, spec, 64, lds)
-                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen, 64, 0);
-        if (eo == hipSuccess && per_cu > 0 && hipGetDevice(&dev_id) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) == hipSuccess &&
-            cus > 0)
-            blocks = std::min(blocks, (unsigned)(per_cu * cus));
-        hipEvent_t t0 = timing_begin(s);  // timed as a propagation launch
-        if (spec) {
-            void *params[] = {(void *)&a};
-            e = hipModuleLaunchKernel(spec, blocks, 1, 1, 64, 1, 1, lds, s, params, nullptr);
-            if (e != hipSuccess) { rc = hip_fail(e, "ode launch"); break; }
-        } else if (U <= 4) hipLaunchKernelGGL(k_ode<4>, dim3(blocks), dim3(64), 0, s, a);
-        else if (U <= 8) hipLaunchKernelGGL(k_ode<8>, dim3(blocks), dim3(64), 0, s, a);
-        else if (U <= 16) hipLaunchKernelGGL(k_ode<16>, dim3(blocks), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL(k_ode<32>, dim3(blocks), dim3(64), 0, s, a);
-        if ((e = hipGetLastError()) != hipSuccess) { rc = hip_fail(e, "ode launch"); break; }
-        timing_end_propagate(t0, s);
-        hipLaunchKernelGGL(k_ode_finish, dim3((unsigned)((n_theta + 255) / 256)), dim3(256), 0, s,
-                           a.tll, a.tst, n_theta, M, d_ll, d_st);
-        if ((e = hipGetLastError()) != hipSuccess) { rc = hip_fail(e, "ode finish launch"); break; }
+        if ((rc = ode_enqueue(a, spec, d_ll, d_st, s))) break;
         if ((e = hipMemcpyAsync(loglik_out, d_ll, (size_t)n_theta * 8, hipMemcpyDeviceToHost, s)) !=
                 hipSuccess ||
             (status_out && (e = hipMemcpyAsync(status_out, d_st, (size_t)n_theta * 4,
@@ -434,6 +520,57 @@ int lik_ode_eval(lik_ode_t model, int32_t n_theta, const double *theta, const li
     if (s) (void)hipStreamDestroy(s);
     (void)hipFree(dev);
     return rc;
+}
+
+size_t lik_ode_workspace_size(lik_ode_t model, int32_t n_theta, int32_t n_traj) {
+    if (!model || n_theta < 0 || n_traj < 1) return 0;
+    return scratch_bytes((size_t)n_theta * n_traj, n_traj) + 256;
+}
+
+int lik_ode_eval_device(lik_ode_t model, int32_t n_theta, const double *theta,
+                        const lik_ode_data *data, const int32_t *obs_offsets_host,
+                        const int32_t *in_offsets_host, double rtol, double atol,
+                        int32_t max_steps, int32_t kernel, double *loglik, int32_t *status,
+                        int32_t *steps, void *workspace, size_t workspace_bytes, void *stream) {
+    int rc = check_call(model, n_theta, data, rtol, atol, max_steps, kernel);
+    if (rc) return rc;
+    const int M = data->n_traj;
+    if (n_theta == 0) return LIK_OK;
+    if (!theta || !loglik || !data->obs_offsets || !data->t_obs || !data->y || !data->t0 ||
+        !data->x0 || !obs_offsets_host)
+        return fail(LIK_EINVAL, "NULL input or output pointer");
+    if ((data->in_offsets == nullptr) != (in_offsets_host == nullptr))
+        return fail(LIK_EINVAL, "in_offsets and in_offsets_host must both be given or both NULL");
+    int t_max = 0;
+    int64_t total = 0, n_in = 0;
+    if ((rc = check_offsets(obs_offsets_host, M, &t_max, &total))) return rc;
+    if ((rc = check_in_offsets(in_offsets_host, M, &n_in))) return rc;
+    if (n_in > 0 && (!data->t_in || !data->u_in)) return fail(LIK_EINVAL, "input arrays NULL");
+    const size_t F = (size_t)n_theta * M;
+    if (!workspace || workspace_bytes < lik_ode_workspace_size(model, n_theta, M))
+        return fail(LIK_EINVAL, "workspace too small (see lik_ode_workspace_size)");
+    hipFunction_t spec = nullptr;
+    if ((rc = pick_kernel(*model, kernel, &spec))) return rc;
+    OdeArgs a;
+    memset(&a, 0, sizeof(a));
+    if ((rc = model_on_device(*model, &a.terms, &a.x0_param))) return rc;
+    model_args(*model, &a);
+    carve_scratch((char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255), F, M, &a, steps);
+    a.theta = theta;
+    a.n_theta = n_theta;
+    a.M = M;
+    a.obs_offsets = data->obs_offsets;
+    a.t_obs = data->t_obs;
+    a.y = data->y;
+    a.t0 = data->t0;
+    a.x0 = data->x0;
+    a.in_offsets = data->in_offsets;
+    a.t_in = data->t_in;
+    a.u_in = data->u_in;
+    a.rtol = rtol;
+    a.atol = atol;
+    a.max_steps = max_steps;
+    return ode_enqueue(a, spec, loglik, status, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -32,7 +32,8 @@ EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile
             "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version",
             "lik_network_set_tuning", "lik_network_get_tuning", "lik_autotune_device",
             "lik_eval_requests", "lik_precompile_requests", "lik_autotune_requests",
-            "lik_ode_create", "lik_ode_destroy", "lik_ode_eval", "lik_ode_precompile"]
+            "lik_ode_create", "lik_ode_destroy", "lik_ode_eval", "lik_ode_precompile",
+            "lik_ode_workspace_size", "lik_ode_eval_device"]
 
 
 class LikError(RuntimeError):
@@ -168,6 +169,12 @@ def lib():
         L.lik_ode_eval.argtypes = [vp, i32, vp, vp, ctypes.c_double, ctypes.c_double, i32, i32,
                                    vp, vp, vp]
         L.lik_ode_eval.restype = ctypes.c_int
+        L.lik_ode_workspace_size.argtypes = [vp, i32, i32]
+        L.lik_ode_workspace_size.restype = ctypes.c_size_t
+        L.lik_ode_eval_device.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.c_double,
+                                          ctypes.c_double, i32, i32, vp, vp, vp, vp,
+                                          ctypes.c_size_t, vp]
+        L.lik_ode_eval_device.restype = ctypes.c_int
         L.lik_timing_enable.argtypes = [ctypes.c_int]
         L.lik_timing_enable.restype = ctypes.c_int
         L.lik_timing_read.argtypes = [vp]
@@ -658,13 +665,9 @@ class OdeModel:
             self.handle = None
 
 
-def ode_eval(model, theta, trajectories, rtol=1e-6, atol=1e-9, max_steps=100000, steps=False,
-             kernel=KERNEL_AUTO):
-    """lik_ode_eval: (loglik [n_theta], status [n_theta]) and, with steps,
-    the step attempts [n_theta, M].  trajectories:
-    dicts t_obs, y, t0, x0 [U] (the species not set by theta) and optionally
-    t_in, u_in (piecewise-constant input)."""
-    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, model.V))
+def _ode_arrays(model, trajectories):
+    """The trajectories as lik_ode_data's arrays (numpy): offs, t_obs, y, t0,
+    x0, and ioff, t_in, u_in (None without inputs)."""
     offs, tin, ioff = [0], [], [0]
     for tr in trajectories:
         offs.append(offs[-1] + len(tr["t_obs"]))
@@ -684,9 +687,19 @@ def ode_eval(model, theta, trajectories, rtol=1e-6, atol=1e-9, max_steps=100000,
                                                 for tr in trajectories])) if has_in else None
     u_in = np.ascontiguousarray(np.concatenate([np.asarray(tr.get("u_in", []), np.float64)
                                                 for tr in trajectories])) if has_in else None
+    return offs, t_obs, y, t0, x0, (ioff if has_in else None), t_in, u_in
+
+
+def ode_eval(model, theta, trajectories, rtol=1e-6, atol=1e-9, max_steps=100000, steps=False,
+             kernel=KERNEL_AUTO):
+    """lik_ode_eval: (loglik [n_theta], status [n_theta]) and, with steps,
+    the step attempts [n_theta, M].  trajectories:
+    dicts t_obs, y, t0, x0 [U] (the species not set by theta) and optionally
+    t_in, u_in (piecewise-constant input)."""
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1, model.V))
+    offs, t_obs, y, t0, x0, ioff, t_in, u_in = _ode_arrays(model, trajectories)
     d = OdeData(len(trajectories), offs.ctypes.data, t_obs.ctypes.data, y.ctypes.data,
-                t0.ctypes.data, x0.ctypes.data, ioff.ctypes.data if has_in else None,
-                _ptr(t_in), _ptr(u_in))
+                t0.ctypes.data, x0.ctypes.data, _ptr(ioff), _ptr(t_in), _ptr(u_in))
     n = theta.shape[0]
     ll = np.zeros(max(n, 1))
     st = np.zeros(max(n, 1), np.int32)
@@ -698,3 +711,42 @@ def ode_eval(model, theta, trajectories, rtol=1e-6, atol=1e-9, max_steps=100000,
     if steps:
         return ll[:n], st[:n], ns[:n * len(trajectories)].reshape(n, len(trajectories))
     return ll[:n], st[:n]
+
+
+class OdeDeviceBatch:
+    """Trajectories and workspace resident on the device for repeated
+    lik_ode_eval_device calls (torch tensors, torch's current stream): the
+    deterministic counterpart of DeviceBatch."""
+
+    def __init__(self, model, trajectories, n_theta, steps=False, kernel=KERNEL_AUTO):
+        import torch
+        self.torch, self.model, self.n_theta, self.kernel = torch, model, int(n_theta), kernel
+        self.M = len(trajectories)
+        offs, t_obs, y, t0, x0, ioff, t_in, u_in = _ode_arrays(model, trajectories)
+        self.offs_host, self.ioff_host = offs, ioff
+        dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+        self.arrays = [dev(a) for a in (offs, t_obs, y, t0, x0, ioff, t_in, u_in)]
+        p = [None if a is None else a.data_ptr() for a in self.arrays]
+        self.data = OdeData(self.M, *p)
+        ws = lib().lik_ode_workspace_size(model.handle, self.n_theta, self.M)
+        if ws == 0:
+            raise LikError(-1, "lik_ode_workspace_size: bad arguments")
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device="cuda")
+        self.loglik = torch.empty(max(self.n_theta, 1), dtype=torch.float64, device="cuda")
+        self.status = torch.empty(max(self.n_theta, 1), dtype=torch.int32, device="cuda")
+        self.steps = (torch.empty(max(self.n_theta * self.M, 1), dtype=torch.int32, device="cuda")
+                      if steps else None)
+
+    def run(self, theta_dev, rtol=1e-6, atol=1e-9, max_steps=100000, stream=None):
+        """Enqueue one evaluation of theta_dev [n_theta, V] (float64, device)."""
+        torch = self.torch
+        assert theta_dev.dtype == torch.float64 and theta_dev.is_contiguous()
+        assert theta_dev.numel() == self.n_theta * self.model.V
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().lik_ode_eval_device(
+            self.model.handle, self.n_theta, theta_dev.data_ptr(), ctypes.byref(self.data),
+            self.offs_host.ctypes.data, _ptr(self.ioff_host), float(rtol), float(atol),
+            int(max_steps), int(self.kernel), self.loglik.data_ptr(), self.status.data_ptr(),
+            None if self.steps is None else self.steps.data_ptr(), self.workspace.data_ptr(),
+            self.workspace.numel(), ctypes.c_void_p(s.cuda_stream)))
+        return self.loglik[:self.n_theta], self.status[:self.n_theta]

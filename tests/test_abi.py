@@ -195,6 +195,35 @@ def test_ode_model_validation_and_empty_batch():
         lik.ode_eval(m, np.ones((1, 2)), [dict(tr, t_obs=[1.0, 2.0])], rtol=0.0)
 
 
+def test_ode_device_entry_point_checks_on_the_host():
+    # lik_ode_eval_device: argument checks that run before any device work
+    m = lik.OdeModel({"U": 1, "V": 2, "terms": [{"to": 0, "rate_param": 0},
+                                                {"frm": 0, "rate_param": 1,
+                                                 "factors": [(0, 0, 0)]}],
+                      "x0_param": [-1], "sd_const": 1.0})
+    L = lik.lib()
+    assert L.lik_ode_workspace_size(m.handle, 100, 3) >= 100 * 3 * 16
+    assert L.lik_ode_workspace_size(None, 100, 3) == 0
+    assert L.lik_ode_workspace_size(m.handle, 100, 0) == 0
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails its checks
+    offs = np.array([0, 2], np.int32)
+    d = lik.OdeData(1, fake, fake, fake, fake, fake, None, None, None)
+
+    def call(data=d, offs_host=offs, ioff_host=None, ws=None, wsb=0, n=4, rtol=1e-6):
+        return L.lik_ode_eval_device(m.handle, n, fake, ctypes.byref(data),
+                                     None if offs_host is None else offs_host.ctypes.data,
+                                     None if ioff_host is None else ioff_host.ctypes.data,
+                                     rtol, 1e-9, 1000, lik.KERNEL_AUTO, fake, None, None,
+                                     ws, wsb, None)
+    assert call() == lik.LIK_EINVAL                       # no workspace
+    assert call(wsb=1 << 30) == lik.LIK_EINVAL            # workspace NULL
+    assert call(offs_host=None, ws=fake, wsb=1 << 30) == lik.LIK_EINVAL
+    assert call(offs_host=np.array([1, 2], np.int32), ws=fake, wsb=1 << 30) == lik.LIK_EINVAL
+    assert call(ioff_host=np.array([0, 1], np.int32), ws=fake, wsb=1 << 30) == lik.LIK_EINVAL
+    assert call(rtol=0.0, ws=fake, wsb=1 << 30) == lik.LIK_EINVAL
+    assert call(n=0) == lik.LIK_OK                        # an empty batch does nothing
+
+
 def test_ode_specialised_kernels_compile_without_gpu(tmp_path, monkeypatch):
     monkeypatch.setenv("LIK_KERNEL_CACHE", str(tmp_path))
     from paper_1606_08281_amd import workloads as W

@@ -119,3 +119,38 @@ def test_pair_queue_order_and_ragged_sizes(orc, n_theta):
     theta = np.exp(rng.normal(0.0, 1.0, (n_theta, 2))) * np.array([8.0, 0.5])
     _say("pair queue: immigration-death with input, 5 trajectories,", n_theta, "theta")
     assert_same(*both(orc, spec, theta, trajs, rtol=1e-7, atol=1e-10))
+
+
+def test_device_entry_point_equals_host_entry_point(orc):
+    """lik_ode_eval_device on resident buffers (torch tensors, the current
+    stream, one workspace reused by consecutive calls) gives lik_ode_eval's
+    results bit for bit, with and without inputs, for both kernels; the
+    oracle agrees."""
+    import torch
+    from paper_1606_08281_amd import lik
+    wl = W.erk_workload(n_theta=200, spread=0.5)
+    model = lik.OdeModel(wl["spec"])
+    for kernel in (lik.KERNEL_GENERIC, lik.KERNEL_SPECIALIZED):
+        db = lik.OdeDeviceBatch(model, wl["trajectories"], 200, steps=True, kernel=kernel)
+        for rep in range(2):
+            theta = wl["theta"] * (1.0 + 0.1 * rep)
+            _say("ODE device entry point, kernel", kernel, "call", rep)
+            ll_d, st_d = db.run(torch.from_numpy(np.ascontiguousarray(theta)).cuda())
+            torch.cuda.synchronize()
+            ll, st, steps = lik.ode_eval(model, theta, wl["trajectories"], steps=True,
+                                         kernel=kernel)
+            assert np.array_equal(ll_d.cpu().numpy(), ll, equal_nan=True)
+            assert np.array_equal(st_d.cpu().numpy(), st)
+            assert np.array_equal(db.steps[:200 * 6].cpu().numpy().reshape(200, 6), steps)
+    ref = orc.ode_eval(orc.OdeProblem(wl["spec"], theta[:16], wl["trajectories"]))
+    assert np.array_equal(ll[:16], ref["loglik"], equal_nan=True)
+    _say("ODE device entry point without inputs")
+    t = np.linspace(0.5, 12.0, 24)
+    trajs = [{"t_obs": t, "y": np.full(24, 10.0), "x0": [1.0]}, {"t_obs": t[:5], "y": np.ones(5),
+                                                               "x0": [3.0]}]
+    m2 = lik.OdeModel(imm_death_model())
+    th2 = np.exp(np.random.default_rng(4).normal(0.0, 1.0, (70, 2)))
+    db2 = lik.OdeDeviceBatch(m2, trajs, 70)
+    ll_d, st_d = db2.run(torch.from_numpy(th2).cuda())
+    ll, st = lik.ode_eval(m2, th2, trajs)
+    assert np.array_equal(ll_d.cpu().numpy(), ll) and np.array_equal(st_d.cpu().numpy(), st)
