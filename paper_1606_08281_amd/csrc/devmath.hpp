@@ -139,6 +139,37 @@ __device__ __forceinline__ double fma_f64_s(double a, double k) {
     return r;
 }
 
+// n / d correctly rounded, for operands the division sequence needs neither
+// to scale nor to fix up: d normal in [1, 4], n zero or with |n| in
+// [2^-60, 4] (the log's f / (2 + f)).  These are the steps of the IEEE
+// division sequence -- reciprocal estimate, two Newton steps, one residual
+// correction -- whose range scaling and special-case fix-up are the identity
+// on such operands: the same quotient, bit for bit, in three fewer
+// instructions.
+__device__ __forceinline__ double div_inrange(double n, double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-d, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double q = n * y;
+    const double r = __builtin_fma(-d, q, n);
+    return __builtin_fma(r, y, q);
+}
+
+// The binary32 counterpart (one Newton step, two residual corrections, as
+// the binary32 division sequence takes them).
+__device__ __forceinline__ float divf_inrange(float n, float d) {
+    float y = __builtin_amdgcn_rcpf(d);
+    const float e = __builtin_fmaf(-d, y, 1.0f);
+    y = __builtin_fmaf(e, y, y);
+    float q = n * y;
+    float r = __builtin_fmaf(-d, q, n);
+    q = __builtin_fmaf(r, y, q);
+    r = __builtin_fmaf(-d, q, n);
+    return __builtin_fmaf(r, y, q);
+}
+
 // Natural logarithm of x > 0 (x = 0 -> -inf).  Reduction x = 2^e m,
 // m in [sqrt(1/2), sqrt(2)]; with f = m - 1 and s = f / (2 + f),
 // log m = 2 atanh s = t + t z Q(z), t = 2s, z = s^2,
@@ -161,7 +192,7 @@ __device__ __forceinline__ double dlog_pos(double x) {
         e = e - 1;
     }
     const double f = m - 1.0;
-    const double s = f / (2.0 + f);
+    const double s = div_inrange(f, 2.0 + f);  // f in [-0.293, 0.415]
     const double z = s * s;
     double q = 1.0 / 21.0;
     q = fma_f64(q, z, 1.0 / 19.0);
@@ -228,7 +259,7 @@ __device__ __forceinline__ float flog_pos(float x) {
         e = e - 1;
     }
     const float f = m - 1.0f;
-    const float s = f / (2.0f + f);
+    const float s = divf_inrange(f, 2.0f + f);
     const float z = s * s;
     float q = 1.0f / 11.0f;
     q = __builtin_fmaf(q, z, 1.0f / 9.0f);
