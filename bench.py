@@ -43,10 +43,14 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # microbench/isa_cost.hip (four wavefronts per SIMD, 4.3-4.5 cycles for a
 # full-rate instruction; the table is in the profile summaries): a
 # 32 x 32 -> 64 multiply-add takes one slot, the IEEE-correct binary64 divide
-# sequence fifteen (58 cycles), the binary32 one ten (42 cycles).
+# sequence fifteen (58 cycles), the binary32 one ten (42 cycles); the log's
+# in-range division (the same sequence less its two scalings and its fix-up)
+# three slots less.
 SLOTS_MAD_U64 = 1
 SLOTS_DIV_F64 = 15
 SLOTS_DIV_F32 = 10
+SLOTS_DIV_INRANGE_F64 = SLOTS_DIV_F64 - 3
+SLOTS_DIV_INRANGE_F32 = SLOTS_DIV_F32 - 3
 
 
 def ops_per_event(R, U, precision):
@@ -57,12 +61,12 @@ def ops_per_event(R, U, precision):
     if precision == 0:
         philox = 10 * (2 * SLOTS_MAD_U64 + 2)   # 10 rounds: two 32x32->64 products, two 3-way xors
         uniforms = 2 * 6                # 53-bit assembly, int->binary64, scale (two uniforms)
-        log = 7 + SLOTS_DIV_F64 + 3 + 10 + 5   # reduction, divide, squares, series, recombination
+        log = 7 + SLOTS_DIV_INRANGE_F64 + 3 + 10 + 5   # reduction, divide, squares, series, sum
         tau = SLOTS_DIV_F64             # IEEE binary64 divide
     else:
         philox = 10 * (2 * SLOTS_MAD_U64 + 2)   # the binary64 path's block (same stream)
         uniforms = 2 * 3                # 24-bit shift, int->binary32, scale (two uniforms)
-        log = 7 + SLOTS_DIV_F32 + 3 + 6 + 5
+        log = 7 + SLOTS_DIV_INRANGE_F32 + 3 + 6 + 5
         tau = SLOTS_DIV_F32
     propensity = 3 * R                  # count -> float, times rate, running sum
     select = 1 + 2 * (R - 1)            # target, compare + select per reaction
