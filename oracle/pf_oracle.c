@@ -310,11 +310,13 @@ static uint64_t ssa_interval(const orc_problem *P, const double *c, int32_t *x,
             total = (double)sf;
             if (!(sf > 0.0f)) break;
             if (n >= P->event_cap) { *status = ORC_EVENT_CAP; break; }
-            /* event n draws the same block as in binary64 and keeps the
-             * leading 24 bits of the words that lead its two uniforms */
-            philox_block(P->seed, (uint32_t)n, slot, c2, theta_id << 2, w);
-            float u1 = (float)((w[1] >> 8) + 1u) * 0x1p-24f;   /* (0, 1] */
-            float u2 = (float)(w[3] >> 8) * 0x1p-24f;          /* [0, 1) */
+            /* half a block per event: events 2p and 2p + 1 share block p,
+             * the first taking words 0 and 1, the second words 2 and 3,
+             * each word's leading 24 bits */
+            philox_block(P->seed, (uint32_t)(n >> 1), slot, c2, theta_id << 2, w);
+            const int h = (int)(n & 1u) * 2;
+            float u1 = (float)((w[h] >> 8) + 1u) * 0x1p-24f;     /* (0, 1] */
+            float u2 = (float)(w[h + 1] >> 8) * 0x1p-24f;        /* [0, 1) */
             float tau = -orc_logf(u1) / sf;
             if (clock + (double)tau > t_end) break;
             float target = u2 * sf;

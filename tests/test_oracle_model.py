@@ -137,28 +137,37 @@ def test_ssa_immigration_death_poisson(orc, k1, k2, t, precision):
     assert p > 1e-4, (chi2, p)
 
 
-@pytest.mark.parametrize("net_case", ["immigration-death", "telegraph"])
-def test_fp32_mixed_follows_the_fp64_path(orc, net_case):
-    # Both modes draw event n from the same Philox block, the binary32 mode
-    # taking the leading 24 bits of the very words behind the binary64
-    # uniforms; so a path differs from its binary64 twin only where binary32
-    # rounding flips a decision (which reaction fires, or whether the event
-    # falls before the end), which is rare over a few hundred events.
-    if net_case == "immigration-death":
-        orders, stoich, c, x0, t = [[0], [1]], [[1], [-1]], [10.0, 0.1], [0], 20.0
-    else:
-        from paper_1606_08281_amd.workloads import telegraph
-        net = telegraph()
-        orders, stoich = net.orders, net.stoich
-        c, x0, t = [0.5, 0.5, 10.0, 1.0, 2.0, 0.1], [1, 0, 10, 100], 4.0
-    n = 4000
-    p64 = _problem(orc, orders, stoich, precision=0)
-    p32 = _problem(orc, orders, stoich, precision=1)
-    s64, e64, _ = orc.ssa_paths(p64, c, x0, 0.0, t, n, theta_id=3)
-    s32, e32, _ = orc.ssa_paths(p32, c, x0, 0.0, t, n, theta_id=3)
-    same = np.all(s64 == s32, axis=1) & (e64 == e32)
-    assert e64.mean() > 100
-    assert same.mean() > 0.97, same.mean()
+def test_fp32_mixed_takes_half_a_block_per_event(orc):
+    # The FP32-mixed stream layout, recomputed here from Philox blocks (pinned
+    # to rocRAND) and the binary32 log (pinned to mpmath): events 2p and
+    # 2p + 1 of a path share block p = (p, path, 0, theta_id << 2) under key
+    # (seed), the first taking u1, u2 from words 0, 1 and the second from
+    # words 2, 3, the leading 24 bits of each.  Two birth reactions, so that
+    # both the waiting times (u1) and the choice of reaction (u2) are checked.
+    rates, t_end, n_paths, theta_id, seed = (2.0, 1.0), 3.0, 150, 7, 5
+    P = _problem(orc, [[0, 0], [0, 0]], [[1, 0], [0, 1]], precision=1, seed=seed)
+    states, ev, st = orc.ssa_paths(P, list(rates), [0, 0], 0.0, t_end, n_paths,
+                                   theta_id=theta_id)
+    assert st == 0
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    a = [np.float32(r) for r in rates]          # float(c) * float(1) for order 0
+    sf = np.float32(a[0] + a[1])
+    for j in range(n_paths):
+        clock, n, x = 0.0, 0, [0, 0]
+        while True:
+            w = orc.philox([n >> 1, j, 0, theta_id << 2], key)
+            h = 2 * (n & 1)
+            u1 = np.float32(((int(w[h]) >> 8) + 1) * 2.0**-24)
+            u2 = np.float32((int(w[h + 1]) >> 8) * 2.0**-24)
+            tau = np.float32(-np.float32(orc.logf(u1))) / sf
+            if clock + float(tau) > t_end:
+                break
+            r = 0 if a[0] > np.float32(u2 * sf) else 1
+            x[r] += 1
+            clock += float(tau)
+            n += 1
+        assert int(ev[j]) == n and list(states[j]) == x, (j, n, x)
+    assert ev.mean() > 5
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
