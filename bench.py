@@ -64,7 +64,7 @@ def ops_per_event(R, U, precision):
         log = 7 + SLOTS_DIV_INRANGE_F64 + 3 + 10 + 5   # reduction, divide, squares, series, sum
         tau = SLOTS_DIV_F64             # IEEE binary64 divide
     else:
-        philox = 10 * (2 * SLOTS_MAD_U64 + 2)   # the binary64 path's block (same stream)
+        philox = 10 * (2 * SLOTS_MAD_U64 + 2) // 2   # half a block per event
         uniforms = 2 * 3                # 24-bit shift, int->binary32, scale (two uniforms)
         log = 7 + SLOTS_DIV_INRANGE_F32 + 3 + 6 + 5
         tau = SLOTS_DIV_F32
@@ -416,8 +416,8 @@ def main():
                     "identical": int((err == 0).sum()),
                     "abs_quantiles": {f"p{k}": float(np.percentile(err, k)) for k in q},
                     "rel_quantiles": {f"p{k}": float(np.percentile(rel, k)) for k in q}}
-        # filters whose SSA paths left their FP64 twins (a differing event
-        # total; equal totals with different paths are not counted)
+        # (the two precisions draw different random numbers, so this is a
+        # Monte-Carlo difference; filters_diverged: event totals that differ)
         fp32_error = dict(diff(ll32, ll64), vs="f64 path, same seed",
                           filters_diverged=float(np.mean(ev32 != ev64)),
                           filters=int(ev32.size),

@@ -157,11 +157,18 @@ struct pick_type<false, T, F> {
 // "Simulate" step): nl = -log u1 (the waiting time times the total
 // propensity) and u2 (the reaction's share of the total), in the precision of
 // the event arithmetic.  A function of the event's stream counter (n, j)
-// alone, so any lane may compute it for any particle.
+// alone, so any lane may compute it for any particle.  FP32-mixed draws two
+// events at once from one Philox block (events n and n + 1, n even): nl1 and
+// u21 are the second event's.
 template <int PREC>
 struct EventDraw {
-    using Real = typename pick_type<PREC == LIK_FP32_MIXED, float, double>::type;
+    using Real = double;
     Real nl, u2;
+};
+template <>
+struct EventDraw<LIK_FP32_MIXED> {
+    using Real = float;
+    Real nl, u2, nl1, u21;
 };
 
 // A 53-bit integer as binary64, exactly: hi 2^32 + lo < 2^53 is representable,
@@ -176,11 +183,14 @@ __device__ __forceinline__ EventDraw<PREC> draw_from_block(const Block4 &b) {
     EventDraw<PREC> r;
     // u1 = (z + 1) 2^-k in (0, 1] and u2 = z' 2^-k in [0, 1), each formed
     // exactly (every intermediate value is representable)
-    if (PREC == LIK_FP32_MIXED) {
-        // the leading 24 bits of the binary64 uniforms' words
-        const float u1 = __builtin_fmaf((float)(b.w1 >> 8), 0x1p-24f, 0x1p-24f);
-        r.nl = (Real)(-flog_pos(u1));
-        r.u2 = (Real)((float)(b.w3 >> 8) * 0x1p-24f);
+    if constexpr (PREC == LIK_FP32_MIXED) {
+        // the leading 24 bits of words 0, 1 (event n) and 2, 3 (event n + 1)
+        const float u1 = __builtin_fmaf((float)(b.w0 >> 8), 0x1p-24f, 0x1p-24f);
+        r.nl = -flog_pos(u1);
+        r.u2 = (float)(b.w1 >> 8) * 0x1p-24f;
+        const float u1b = __builtin_fmaf((float)(b.w2 >> 8), 0x1p-24f, 0x1p-24f);
+        r.nl1 = -flog_pos(u1b);
+        r.u21 = (float)(b.w3 >> 8) * 0x1p-24f;
     } else {
         const uint64_t z1 = ((((uint64_t)b.w1) << 32) | b.w0) >> 11;
         const uint64_t z2 = ((((uint64_t)b.w3) << 32) | b.w2) >> 11;
@@ -191,11 +201,19 @@ __device__ __forceinline__ EventDraw<PREC> draw_from_block(const Block4 &b) {
     return r;
 }
 
-// The draw of event n of particle j (any counter words).
+// The Philox block of event n: n itself in FP64, n / 2 in FP32-mixed (whose
+// events n and n + 1 share a block).
+template <int PREC>
+__device__ __forceinline__ uint32_t event_block(uint32_t n) {
+    return PREC == LIK_FP32_MIXED ? n >> 1 : n;
+}
+
+// The draw of event n of particle j (any counter words; n even in
+// FP32-mixed, where it is the draw of events n and n + 1).
 template <int PREC>
 __device__ __forceinline__ EventDraw<PREC> event_draw(uint32_t n, uint32_t j, uint32_t c2,
                                                       uint32_t c3, uint32_t k0, uint32_t k1) {
-    return draw_from_block<PREC>(philox4x32_10(n, j, c2, c3, k0, k1));
+    return draw_from_block<PREC>(philox4x32_10(event_block<PREC>(n), j, c2, c3, k0, k1));
 }
 
 // The same where c2, c3 and the key are wave-uniform (one work item's
@@ -204,14 +222,16 @@ template <int PREC>
 __device__ __forceinline__ EventDraw<PREC> event_draw_uniform(uint32_t n, uint32_t j,
                                                               uint32_t c2, uint32_t c3,
                                                               uint32_t k0, uint32_t k1) {
-    return draw_from_block<PREC>(philox4x32_10_event(n, j, c2, c3, k0, k1));
+    return draw_from_block<PREC>(philox4x32_10_event(event_block<PREC>(n), j, c2, c3, k0, k1));
 }
 
 // One direct-method event of one particle (Supplementary I, the "Simulate"
 // step; the SSA of Gillespie 1977): total propensity, then either the end of
 // the particle's interval (no reaction possible, the event cap, or the next
-// event beyond the observation time -- it is discarded) or one event.
-// draw() gives the event's EventDraw (for the particle's current n).
+// event beyond the observation time -- it is discarded) or one event; in
+// FP32-mixed the same again for the block's second draw (two events per
+// call, n even on entry).  draw() gives the EventDraw of the particle's
+// current n.
 // a0_end keeps the last total propensity (a scheduling estimate, stored as
 // binary32 when the particle is).
 // nu_tab: the byte table of net changes in LDS (large networks), else null.
@@ -220,40 +240,63 @@ __device__ __forceinline__ void ssa_event(const NetT &net, const Real *c, int *x
                                           double t_end, uint32_t event_cap, double &clock,
                                           uint32_t &n, int &st, Real &a0_end, bool &have,
                                           const uint32_t *nu_tab, DrawFn &&draw) {
-    // large networks: the rates are read from LDS again at every event (the
-    // compiler would otherwise keep all of them in vector registers)
-    if (LdsNet<RMAX>::on) asm volatile("" ::: "memory");
-    const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
-    a0_end = s;
-    if (!(s > (Real)0)) {
-        have = false;  // no reaction can fire before the observation
-    } else if (n >= event_cap) {
-        st = st > LIK_STATUS_EVENT_CAP ? st : LIK_STATUS_EVENT_CAP;
-        have = false;
-    } else {
-        const EventDraw<PREC> dr = draw();
+    // the total propensity after the last change (large networks: the rates
+    // are read from LDS again at every event, the compiler would otherwise
+    // keep all of them in vector registers)
+    auto total = [&]() -> Real {
+        if (LdsNet<RMAX>::on) asm volatile("" ::: "memory");
+        const Real s = running_sums<NetT, RMAX, Real>(net, c, x, S);
+        a0_end = s;
+        return s;
+    };
+    // whether an event may be drawn: some reaction can fire, and the cap
+    auto may_fire = [&](Real s) -> bool {
+        if (!(s > (Real)0)) {
+            have = false;  // no reaction can fire before the observation
+            return false;
+        }
+        if (n >= event_cap) {
+            st = st > LIK_STATUS_EVENT_CAP ? st : LIK_STATUS_EVENT_CAP;
+            have = false;
+            return false;
+        }
+        return true;
+    };
+    // the event of draw (nl, u2), or the end of the interval
+    auto fire = [&](Real s, Real nl, Real u2) {
         double tau;
         Real target;
-        if (PREC == LIK_FP32_MIXED) {
-            tau = (double)((float)dr.nl / (float)s);
-            target = (Real)((float)dr.u2 * (float)s);
+        if constexpr (PREC == LIK_FP32_MIXED) {
+            tau = (double)((float)nl / (float)s);
+            target = (Real)((float)u2 * (float)s);
         } else {
-            tau = (double)dr.nl / (double)s;
-            target = (Real)((double)dr.u2 * (double)s);
+            tau = (double)nl / (double)s;
+            target = (Real)((double)u2 * (double)s);
         }
         if (clock + tau > t_end) {
             have = false;  // the pending event is discarded
-        } else {
-            if (LdsNet<RMAX>::on) {
-                apply_row<UMAX>(net.U, nu_tab, select_index<NetT, RMAX, Real>(net, S, target), x);
-            } else {
-                uint32_t sel[W];
-                select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
-                apply_change<UMAX, W>(net.U, sel, x);
-            }
-            clock = clock + tau;
-            n = n + 1;
+            return;
         }
+        if (LdsNet<RMAX>::on) {
+            apply_row<UMAX>(net.U, nu_tab, select_index<NetT, RMAX, Real>(net, S, target), x);
+        } else {
+            uint32_t sel[W];
+            select_reaction<NetT, RMAX, W, Real>(net, S, target, sel);
+            apply_change<UMAX, W>(net.U, sel, x);
+        }
+        clock = clock + tau;
+        n = n + 1;
+    };
+    Real s = total();
+    if (!may_fire(s)) return;
+    const EventDraw<PREC> dr = draw();
+    fire(s, dr.nl, dr.u2);
+    if constexpr (PREC == LIK_FP32_MIXED) {
+        // the second event of the block (n was even)
+        if (!have) return;
+        s = total();
+        if (!may_fire(s)) return;
+        fire(s, dr.nl1, dr.u21);
     }
 }
 
@@ -539,9 +582,10 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
     // and D = floor(64 / k), lane l computes the draw of event n + (l mod D)
     // of the running lane of rank floor(l / D), into LDS (the pool's staging
     // area, no longer read); each running lane then takes its next D draws
-    // from there.  A draw depends on (n, j) only, so every event
-    // uses the numbers it would have drawn itself; draws beyond a particle's
-    // end are left unused.
+    // from there (in FP32-mixed a draw serves two events: lane l computes
+    // the block of events n + 2 (l mod D) and n + 2 (l mod D) + 1).  A draw
+    // depends on (n, j) only, so every event uses the numbers it would have
+    // drawn itself; draws beyond a particle's end are left unused.
     using Draw = EventDraw<PREC>;
     Draw *dbuf = reinterpret_cast<Draw *>(pool_x);                    // [64]
     uint32_t *xn = reinterpret_cast<uint32_t *>(dbuf + kPropBlock);  // [32]: running lanes' n
@@ -567,8 +611,9 @@ __device__ __forceinline__ void run_item(const EngineArgs &e, const NetT &net, u
         __syncthreads();
         const int r = (lane * m) >> 16;
         if (r < k)
-            dbuf[lane] = event_draw_uniform<PREC>(xn[r] + (uint32_t)(lane - r * D),
-                                                  (uint32_t)xj[r], c2, c3, k0, k1);
+            dbuf[lane] = event_draw_uniform<PREC>(
+                xn[r] + (uint32_t)((lane - r * D) * (PREC == LIK_FP32_MIXED ? 2 : 1)),
+                (uint32_t)xj[r], c2, c3, k0, k1);
         __syncthreads();
         const int slot = rank * D;
 #pragma unroll 1
