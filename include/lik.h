@@ -77,7 +77,8 @@ extern "C" {
 
 /* arithmetic of the SSA step */
 #define LIK_FP64 0       /* binary64 propensities, event times and clock */
-#define LIK_FP32_MIXED 1 /* binary32 propensities / event times, binary64 clock and weights */
+#define LIK_FP32_MIXED 1 /* binary32 propensities / event times (two events per Philox
+                            block), binary64 clock and weights */
 
 /* propagation kernel variants (lik_eval_opts.kernel) */
 #define LIK_KERNEL_AUTO 0        /* specialised when the batch amortises compiling it */
