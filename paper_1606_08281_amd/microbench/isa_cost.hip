@@ -39,12 +39,18 @@ enum Op {
     kAddU32,       // v_add_u32
     kCvtF64U32,    // v_cvt_f64_u32
     kCmpSelF64,    // v_cmp_gt_f64 + v_cndmask_b32 (a selection step)
+    kFmaF32,       // v_fma_f32 (FP32-mixed: log series, propensities)
+    kCvtF32I32,    // v_cvt_f32_i32 (FP32-mixed: counts to binary32)
+    kRcpF32,       // v_rcp_f32 (the binary32 divide's seed)
+    kFrexpF32,     // v_frexp_mant_f32 (the binary32 log's reduction)
+    kCvtF64F32,    // v_cvt_f64_f32 (FP32-mixed: the event time into the binary64 clock)
     kOps
 };
 static const char *kNames[kOps] = {"v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32", "v_fma_f64",
                                    "v_add_f64",     "v_mul_f64",    "v_rcp_f64",    "f64 divide",
                                    "f32 divide",    "v_bitop3_b32", "v_add_u32",    "v_cvt_f64_u32",
-                                   "cmp+select f64"};
+                                   "cmp+select f64", "v_fma_f32",   "v_cvt_f32_i32", "v_rcp_f32",
+                                   "v_frexp_mant_f32", "v_cvt_f64_f32"};
 
 template <int OP, int CH>
 __device__ __forceinline__ void body(uint64_t *u, double *d, float *f, uint32_t *w,
@@ -81,6 +87,18 @@ __device__ __forceinline__ void body(uint64_t *u, double *d, float *f, uint32_t 
         } else if (OP == kCvtF64U32) {
             asm volatile("v_cvt_f64_u32 %0, %1" : "=v"(d[c]) : "v"(w[c]));
             asm volatile("" : "+v"(w[c]));
+        } else if (OP == kFmaF32) {
+            asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(f[c]) : "v"(f[(c + 1) % CH]), "v"(f[0]));
+        } else if (OP == kCvtF32I32) {
+            asm volatile("v_cvt_f32_i32 %0, %1" : "=v"(f[c]) : "v"(w[c]));
+            asm volatile("" : "+v"(w[c]));
+        } else if (OP == kRcpF32) {
+            asm volatile("v_rcp_f32 %0, %0" : "+v"(f[c]));
+        } else if (OP == kFrexpF32) {
+            asm volatile("v_frexp_mant_f32 %0, %0" : "+v"(f[c]));
+        } else if (OP == kCvtF64F32) {
+            asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(d[c]) : "v"(f[c]));
+            asm volatile("" : "+v"(f[c]));
         } else if (OP == kCmpSelF64) {
             uint64_t m;
             asm volatile("v_cmp_gt_f64 %1, %2, %3\n\tv_cndmask_b32 %0, %0, %4, %1"
@@ -151,7 +169,9 @@ int main() {
               run<kRcpF64>(cyc, sink, &ind[6], &dep[6]) && run<kDivF64>(cyc, sink, &ind[7], &dep[7]) &&
               run<kDivF32>(cyc, sink, &ind[8], &dep[8]) && run<kBitop3>(cyc, sink, &ind[9], &dep[9]) &&
               run<kAddU32>(cyc, sink, &ind[10], &dep[10]) && run<kCvtF64U32>(cyc, sink, &ind[11], &dep[11]) &&
-              run<kCmpSelF64>(cyc, sink, &ind[12], &dep[12]);
+              run<kCmpSelF64>(cyc, sink, &ind[12], &dep[12]) && run<kFmaF32>(cyc, sink, &ind[13], &dep[13]) &&
+              run<kCvtF32I32>(cyc, sink, &ind[14], &dep[14]) && run<kRcpF32>(cyc, sink, &ind[15], &dep[15]) &&
+              run<kFrexpF32>(cyc, sink, &ind[16], &dep[16]) && run<kCvtF64F32>(cyc, sink, &ind[17], &dep[17]);
     if (!ok || hipDeviceSynchronize() != hipSuccess) {
         fprintf(stderr, "run failed\n");
         return 1;
