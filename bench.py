@@ -312,6 +312,10 @@ def main():
                          "(default: the library's)")
     ap.add_argument("--kernel", type=int, default=0,
                     help="0 auto, 1 generic, 2 network-specialised propagation kernel")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="FP32-mixed: skip the binary64 runs of the same batch that the "
+                         "per-result difference is taken against (profiling passes, whose "
+                         "counters must see the timed kernel's launches only)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the likelihood path is built and timed on a "
@@ -388,9 +392,11 @@ def main():
     status = db.status.cpu().numpy()
 
     fp32_error = None
-    if args.precision == 1:
-        # the same seed in binary64: both draw the same random blocks, so the
-        # difference per result is the effect of binary32 arithmetic alone
+    if args.precision == 1 and not args.no_compare:
+        # the same batch and seed in binary64, and again under another seed:
+        # the two precisions draw different random numbers, so FP32-mixed
+        # against FP64 is a Monte-Carlo difference, read beside FP64's own
+        # seed-to-seed difference
         ll32 = db.loglik.cpu().numpy().copy()
         ev32 = db.events.cpu().numpy().copy()
         db64 = lik.DeviceBatch(net, wl.obs_kind, wl.observed, wl.sigma, wl.trajectories,
@@ -446,18 +452,26 @@ def main():
 
     evals = wl.n_theta * args.steps
     model_ope = ops_per_event(wl.net.R, wl.net.U, args.precision)
-    # measured lane-op slots per event (the committed counter record of this
-    # kernel, configuration and sources), else the model count
+    # measured lane-op issue time per event (the committed counter record of
+    # this kernel, configuration and sources), else the model count
     ope, ope_basis = model_ope, "model count at measured instruction costs (no counter record " \
                                 "matches the current kernel sources)"
+    passes = None
     if args.kernel in (0, 2) and not args.tuning and not args.autotune:
         from paper_1606_08281_amd import profsum
         rec_name = f"{kname}_valu_{wl_tag}_{fp}.txt"
         rec = profsum.read_record(os.path.join(ROOT, "profiles", rec_name))
         if rec is not None:
+            passes = float(rec["lane_slots_per_event"])
+        if rec is not None and "lane_time_slots_per_event" in rec:
+            ope = float(rec["lane_time_slots_per_event"])
+            ope_basis = ("measured: SQ_THREAD_CYCLES_VALU / SSA events of this kernel on these "
+                         "sources, issue passes priced at the issue time per pass of its "
+                         "instruction classes (profiles/" + rec_name + ")")
+        elif rec is not None:
             ope = float(rec["lane_slots_per_event"])
             ope_basis = ("measured: SQ_THREAD_CYCLES_VALU / SSA events of this kernel on these "
-                         "sources (profiles/" + rec_name + ")")
+                         "sources, issue passes (profiles/" + rec_name + ")")
     prop_s = tm["propagate_ms"] / 1e3
     # A replayed graph records no per-kernel events: its roofline is taken
     # over the whole step instead (a lower bound for the kernel's).
@@ -503,6 +517,7 @@ def main():
             "basis": basis,
             "ops_per_event": ope,
             "ops_per_event_basis": ope_basis,
+            "issue_passes_per_event": passes,
             "model_ops_per_event": model_ope,
             "model_frac": events * model_ope / prop_s / 1e12 / peak,
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

@@ -44,13 +44,24 @@ enum Op {
     kRcpF32,       // v_rcp_f32 (the binary32 divide's seed)
     kFrexpF32,     // v_frexp_mant_f32 (the binary32 log's reduction)
     kCvtF64F32,    // v_cvt_f64_f32 (FP32-mixed: the event time into the binary64 clock)
+    kCndmask,      // v_cndmask_b32 alone (selections, clamps)
+    kMovB32,       // v_mov_b32 (register copies the allocator leaves in the loop)
+    kMovB64,       // v_mov_b64 (64-bit copies: the clock, a pair of state words)
+    kCmpF64,       // v_cmp_gt_f64 into a scalar mask alone (event time against the horizon)
+    kCmpU32,       // v_cmp_gt_u32 into a scalar mask (counters, bounds)
+    kXorB32,       // v_xor_b32 (Philox key mixing)
+    kLshrB32,      // v_lshrrev_b32 (the uniforms' mantissa bits)
+    kAlignbit,     // v_alignbit_b32 (64-bit word assembly)
+    kDivScaleF64,  // v_div_scale_f64 (the binary64 divide's operand scaling)
     kOps
 };
 static const char *kNames[kOps] = {"v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32", "v_fma_f64",
                                    "v_add_f64",     "v_mul_f64",    "v_rcp_f64",    "f64 divide",
                                    "f32 divide",    "v_bitop3_b32", "v_add_u32",    "v_cvt_f64_u32",
                                    "cmp+select f64", "v_fma_f32",   "v_cvt_f32_i32", "v_rcp_f32",
-                                   "v_frexp_mant_f32", "v_cvt_f64_f32"};
+                                   "v_frexp_mant_f32", "v_cvt_f64_f32", "v_cndmask_b32",
+                                   "v_mov_b32",     "v_mov_b64",    "v_cmp_gt_f64", "v_cmp_gt_u32",
+                                   "v_xor_b32",     "v_lshrrev_b32", "v_alignbit_b32", "v_div_scale_f64"};
 
 template <int OP, int CH>
 __device__ __forceinline__ void body(uint64_t *u, double *d, float *f, uint32_t *w,
@@ -99,6 +110,31 @@ __device__ __forceinline__ void body(uint64_t *u, double *d, float *f, uint32_t 
         } else if (OP == kCvtF64F32) {
             asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(d[c]) : "v"(f[c]));
             asm volatile("" : "+v"(f[c]));
+        } else if (OP == kCndmask) {
+            uint64_t m = 0x5555555555555555ull;
+            asm volatile("v_cndmask_b32 %0, %0, %1, %2" : "+v"(w[c]) : "v"(k), "s"(m));
+        } else if (OP == kMovB32) {
+            asm volatile("v_mov_b32 %0, %1" : "=v"(w[c]) : "v"(w[(c + 1) % CH]));
+        } else if (OP == kMovB64) {
+            asm volatile("v_mov_b64 %0, %1" : "=v"(u[c]) : "v"(u[(c + 1) % CH]));
+        } else if (OP == kCmpF64) {
+            uint64_t m;
+            asm volatile("v_cmp_gt_f64 %0, %1, %2" : "=s"(m) : "v"(d[c]), "v"(d[(c + 1) % CH]));
+            asm volatile("" ::"s"(m));
+        } else if (OP == kCmpU32) {
+            uint64_t m;
+            asm volatile("v_cmp_gt_u32 %0, %1, %2" : "=s"(m) : "v"(w[c]), "v"(k));
+            asm volatile("" ::"s"(m));
+        } else if (OP == kXorB32) {
+            asm volatile("v_xor_b32 %0, %0, %1" : "+v"(w[c]) : "v"(k));
+        } else if (OP == kLshrB32) {
+            asm volatile("v_lshrrev_b32 %0, 1, %0" : "+v"(w[c]));
+        } else if (OP == kAlignbit) {
+            asm volatile("v_alignbit_b32 %0, %0, %1, 7" : "+v"(w[c]) : "v"(k));
+        } else if (OP == kDivScaleF64) {
+            uint64_t m;
+            asm volatile("v_div_scale_f64 %0, %1, %0, %2, %0" : "+v"(d[c]), "=s"(m) : "v"(d[(c + 1) % CH]));
+            asm volatile("" ::"s"(m));
         } else if (OP == kCmpSelF64) {
             uint64_t m;
             asm volatile("v_cmp_gt_f64 %1, %2, %3\n\tv_cndmask_b32 %0, %0, %4, %1"
@@ -171,7 +207,12 @@ int main() {
               run<kAddU32>(cyc, sink, &ind[10], &dep[10]) && run<kCvtF64U32>(cyc, sink, &ind[11], &dep[11]) &&
               run<kCmpSelF64>(cyc, sink, &ind[12], &dep[12]) && run<kFmaF32>(cyc, sink, &ind[13], &dep[13]) &&
               run<kCvtF32I32>(cyc, sink, &ind[14], &dep[14]) && run<kRcpF32>(cyc, sink, &ind[15], &dep[15]) &&
-              run<kFrexpF32>(cyc, sink, &ind[16], &dep[16]) && run<kCvtF64F32>(cyc, sink, &ind[17], &dep[17]);
+              run<kFrexpF32>(cyc, sink, &ind[16], &dep[16]) && run<kCvtF64F32>(cyc, sink, &ind[17], &dep[17]) &&
+              run<kCndmask>(cyc, sink, &ind[18], &dep[18]) && run<kMovB32>(cyc, sink, &ind[19], &dep[19]) &&
+              run<kMovB64>(cyc, sink, &ind[20], &dep[20]) && run<kCmpF64>(cyc, sink, &ind[21], &dep[21]) &&
+              run<kCmpU32>(cyc, sink, &ind[22], &dep[22]) && run<kXorB32>(cyc, sink, &ind[23], &dep[23]) &&
+              run<kLshrB32>(cyc, sink, &ind[24], &dep[24]) && run<kAlignbit>(cyc, sink, &ind[25], &dep[25]) &&
+              run<kDivScaleF64>(cyc, sink, &ind[26], &dep[26]);
     if (!ok || hipDeviceSynchronize() != hipSuccess) {
         fprintf(stderr, "run failed\n");
         return 1;

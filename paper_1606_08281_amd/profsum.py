@@ -14,12 +14,19 @@ the ratio of the copy's known bytes to what the counter read for it.
 
 --valu: a pass with SQ_THREAD_CYCLES_VALU, SQ_ACTIVE_INST_VALU, SQ_INSTS_VALU
 and GRBM_GUI_ACTIVE over one bench step whose JSON line is --valu-bench.
-SQ_THREAD_CYCLES_VALU counts quad-cycles of VALU issue times the lanes
-active in them: one full-rate wave64 instruction with every lane active is
-64, an instruction that takes two issue slots 128.  Divided by the SSA
-events of the launch it is the measured lane-op issue slots per event, the
-per-event work bench.py prices the VALU roofline with.  --isa adds the table
-printed by microbench/isa_cost.hip.
+SQ_THREAD_CYCLES_VALU counts VALU issue passes times the lanes active in
+them: a wave64 instruction with every lane active is 64, whatever its issue
+time, v_rcp_f32 128 and v_rcp_f64 256.  Divided by the SSA events of the
+launch it is the measured lane-op issue passes per event, the
+per-event count of issue passes.  --isa adds the table printed by
+microbench/isa_cost.hip.
+
+--types: two passes with the SQ_INSTS_VALU_<class> counters (INT32, INT64,
+CVT, ADD/MUL/FMA/TRANS per precision; the rest is "other") over one bench
+step, and --mix the isamix JSON of the kernel.  Every class is priced at the
+issue time per pass of its instructions in the event loop: the passes per
+event times that ratio are the lane-op issue time per event (in full-rate
+slots), which bench.py prices the VALU roofline with.
 """
 import argparse
 import csv
@@ -127,6 +134,23 @@ def counter_means(pmc_dir):
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
+def dispatches(pmc_dir, kind):
+    """Number of dispatches of a kernel kind in a --pmc folder."""
+    rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "**",
+                                                      "*counter_collection.csv")))))
+    return len({r["Dispatch_Id"] for r in rows if _kind(r["Kernel_Name"]) == kind})
+
+
+def check_dispatches(pmc_dir, kind, expect):
+    """Counter means are taken per dispatch of a kernel kind: a folder that
+    also holds other launches of the same kernel name (FP32-mixed runs that
+    also ran binary64 batches, say) would mix their counts in."""
+    n = dispatches(pmc_dir, kind)
+    if n != expect:
+        raise SystemExit(f"{pmc_dir}: {n} dispatches of {kind}, the profiled bench step "
+                         f"launches {expect}")
+
+
 def counter_sum(pmc_dir, kind, counter):
     rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "**",
                                                       "*counter_collection.csv")))))
@@ -186,6 +210,39 @@ def valu_work(valu_dir, bench_line, kernel):
     return out
 
 
+TYPE_COUNTERS = ("INT32", "INT64", "CVT", "FMA_F32", "ADD_F32", "MUL_F32", "TRANS_F32",
+                 "FMA_F64", "ADD_F64", "MUL_F64", "TRANS_F64")
+DEFAULT_PASSES = {"TRANS_F64": 4, "TRANS_F32": 2}
+
+
+def issue_time(type_dirs, kernel, mix, events):
+    """Issue time per issue pass of `kernel`'s VALU work: the kernel's own
+    SQ_INSTS_VALU_<class> totals (two --pmc passes), each class priced at the
+    time and passes per instruction of the same class in the event loop's mix
+    (isamix).  A class the loop lacks is priced at one slot per pass."""
+    means = {}
+    for d in type_dirs:
+        for (k, c), (v, n) in counter_means(d).items():
+            if k == kernel:
+                means[c] = v
+    total = means["SQ_INSTS_VALU"]
+    counts = {t: means.get("SQ_INSTS_VALU_" + t, 0.0) for t in TYPE_COUNTERS}
+    counts["other"] = total - sum(counts.values())
+    rows, time, passes = [], 0.0, 0.0
+    for t, n in counts.items():
+        m = mix["per_class"].get(t)
+        if m:
+            p_i, w_i = m["passes"] / m["n"], m["time"] / m["n"]
+        else:
+            p_i = DEFAULT_PASSES.get(t, 1)
+            w_i = float(p_i)
+        time += n * w_i
+        passes += n * p_i
+        rows.append((t, n / events, m["n"] if m else 0, p_i, w_i))
+    return {"rows": rows, "time_per_pass": time / passes, "passes_per_event": passes / events,
+            "insts_per_event": total / events}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
@@ -196,6 +253,10 @@ def main():
     ap.add_argument("--valu-bench", help="bench.py JSON line of the --valu run")
     ap.add_argument("--valu-record", help="record file of the measured VALU work per event")
     ap.add_argument("--isa", help="output of microbench/isa_cost.hip")
+    ap.add_argument("--types", nargs=2, metavar="DIR",
+                    help="two rocprofv3 --pmc folders with the SQ_INSTS_VALU_<class> counters")
+    ap.add_argument("--types-bench", help="bench.py JSON line of the first --types run")
+    ap.add_argument("--mix", help="isamix JSON of the same kernel")
     ap.add_argument("--bench", required=True, help="bench.py JSON line of the same configuration")
     ap.add_argument("--kernel", default="lik_flow_spec", help="kernel whose traffic is recorded")
     ap.add_argument("--title", default="lik_flow_spec — telegraph 1024 theta x 10 traj x "
@@ -206,8 +267,17 @@ def main():
     a = ap.parse_args()
 
     stats = kernel_stats(a.stats)
-    tr = traffic(a.fetch, a.write, a.kernel)
     bench = json.loads(open(a.bench).read().strip().splitlines()[-1])
+    per_step = bench["roofline"]["launches"] // bench["steps"]
+    calls = [s["calls"] for s in stats if s["kernel"] == a.kernel]
+    if calls != [per_step * (bench["steps"] + bench["warmup"])]:
+        raise SystemExit(f"{a.stats}: {a.kernel} calls {calls}, the bench line's steps launch "
+                         f"{per_step * (bench['steps'] + bench['warmup'])}")
+    # every --pmc pass profiles one bench step without warm-up
+    for d in [a.fetch, a.write, a.util, a.valu] + list(a.types or []):
+        if d:
+            check_dispatches(d, a.kernel, per_step)
+    tr = traffic(a.fetch, a.write, a.kernel)
     util = counter_means(a.util) if a.util else {}
     sha = source_sha256()
     lines = [f"# {a.title}", "",
@@ -227,9 +297,7 @@ def main():
     rl = bench["roofline"]
     lines += ["", f"bench.py, same configuration: {bench['value']:.1f} evals/s, "
                   f"{bench['ms_per_step']:.1f} ms per step; {a.kernel} average per launch "
-                  f"{rl['avg_launch_ms']:.3f} ms (HIP events on the launch stream); VALU "
-                  f"fraction {rl['frac']:.3f} of {rl['peak']:.2f} T lane-op/s at "
-                  f"{rl['ops_per_event']} lane-ops per event.", "",
+                  f"{rl['avg_launch_ms']:.3f} ms (HIP events on the launch stream).", "",
               f"HBM traffic of {a.kernel} (rocprofv3 --pmc, one pass per counter):", "",
               f"- copy calibration (1 GiB device-to-device): FETCH_SIZE read "
               f"{tr['fetch_copy_kib']:.0f} KiB -> scale {tr['fetch_scale']:.4f}; WRITE_SIZE read "
@@ -253,6 +321,42 @@ def main():
                   f"- wave64 VALU instructions per event (SQ_INSTS_VALU / events): "
                   f"{vw['wave_insts_per_event']:.3f}",
                   f"- active lanes per VALU issue slot: {vw['lane_utilisation']:.3f}"]
+    if vw is not None and a.types:
+        tb = json.loads(open(a.types_bench).read().strip().splitlines()[-1])
+        ev = tb["events_per_step"] * tb["steps"] / max(tb["roofline"]["launches"], 1)
+        mix = json.load(open(a.mix))
+        it = issue_time(a.types, a.kernel, mix, ev)
+        vw["time_per_pass"] = it["time_per_pass"]
+        vw["lane_time_slots_per_event"] = vw["lane_slots_per_event"] * it["time_per_pass"]
+        lines += ["", f"Issue time of the VALU work (rocprofv3 --pmc SQ_INSTS_VALU_<class>, two "
+                      f"passes; event-loop mix from isamix, loop {mix['loop'][0]}..{mix['loop'][1]}"
+                      f", {mix['valu_instructions']} VALU instructions, {mix['time_per_pass']:.3f} "
+                      "slots per pass):", "",
+                  "SQ_THREAD_CYCLES_VALU credits every wave64 VALU instruction with one issue "
+                  "pass (the transcendental ones four or two); gfx950 issues the plain 32-bit "
+                  "operations in about 0.6 of one.  Each class of the kernel's instructions is "
+                  "priced at the issue time per pass of the same class in the event loop.", "",
+                  "| class | wave64 instructions per event | in the loop | passes each | "
+                  "slots each |", "|---|---|---|---|---|"]
+        for t, n, nl, p_i, w_i in it["rows"]:
+            lines.append(f"| {t} | {n:.4f} | {nl} | {p_i:.2f} | {w_i:.3f} |")
+        lines += ["", f"- issue passes per event from the class counts: "
+                      f"{it['passes_per_event']:.3f} wave64 (SQ_ACTIVE_INST_VALU / events: "
+                      f"{vw['sq_active_inst_valu'] / vw['events_per_launch']:.3f})",
+                  f"- issue time per issue pass: {it['time_per_pass']:.4f}",
+                  f"- lane-op issue time per event: {vw['lane_slots_per_event']:.2f} passes x "
+                  f"{it['time_per_pass']:.4f} = {vw['lane_time_slots_per_event']:.2f} slots"]
+        # the bench line's launches: events per launch at its average launch time
+        ev_b = bench["events_per_step"] * bench["steps"] / max(rl["launches"], 1)
+        rate = ev_b / (rl["avg_launch_ms"] / 1e3)
+        lines.append(f"- VALU fraction of the bench line's launches: {rate:.4g} events/s x "
+                     f"{vw['lane_time_slots_per_event']:.2f} slots / {rl['peak']:.2f} T = "
+                     f"{rate * vw['lane_time_slots_per_event'] / (rl['peak'] * 1e12):.3f} "
+                     f"(issue passes alone: "
+                     f"{rate * vw['lane_slots_per_event'] / (rl['peak'] * 1e12):.3f})")
+        if mix.get("unpriced"):
+            lines.append(f"- instructions of the loop priced at one slot (not timed by the "
+                         f"microbenchmark): {mix['unpriced']}")
     if a.isa:
         lines += ["", "Issue cost of the event loop's instructions on gfx950 "
                       "(microbench/isa_cost.hip, one compute unit):", "", "```"]
@@ -279,8 +383,9 @@ def main():
             f.write(f"source_sha256: {sha}\n")
             for k in ("events_per_launch", "sq_thread_cycles_valu", "sq_active_inst_valu",
                       "sq_insts_valu", "lane_slots_per_event", "wave_insts_per_event",
-                      "lane_utilisation"):
-                f.write(f"{k}: {vw[k]:.6g}\n")
+                      "lane_utilisation", "time_per_pass", "lane_time_slots_per_event"):
+                if k in vw:
+                    f.write(f"{k}: {vw[k]:.6g}\n")
     print(a.out, a.traffic)
 
 
