@@ -285,7 +285,7 @@ def main():
               "interval: SSA work items and each filter's weighing) and k_finish."
               if a.kernel == "lik_flow_spec" else
               "Engine iteration = k_order_count + k_order_scan + k_order_place + "
-              "lik_propagate_spec + k_weigh; 50 iterations per "
+              f"lik_propagate_spec + k_weigh; {per_step} iterations per "
               "bench step."), "", "Commands (repository root on one MI355X, `R` = its path):", "",
              "```"] + open(a.commands).read().strip().splitlines() + ["```", "",
              "Kernel statistics (rocprofv3 --kernel-trace --stats):", "",
