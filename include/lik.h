@@ -157,7 +157,7 @@ typedef struct lik_tuning {
                                 work items per compute unit (>= 1) */
 } lik_tuning;
 
-/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30}) / reads a
+/* Sets (NULL: restores the defaults {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 60}) / reads a
  * network's tuning for lik_eval_batch, lik_eval_batch_device and
  * lik_eval_requests; LIK_EINVAL outside the bounds above.  Not to be called
  * while an evaluation on this network is being enqueued on another thread.

@@ -84,15 +84,16 @@ void lik::timing_end_propagate(hipEvent_t begin, hipStream_t s) {
 
 const lik_tuning *lik::autotune_candidates(int *n) {
     static const lik_tuning cands[] = {
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30},  // default: flow schedule
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 32000, 30},
-        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 0, 30},      // flow, first come first served
-        {1, 4, 1024, 1, 1, 0, 160, 0, 1, 16000, 30},
-        {1, 6, 1536, 1, 1, 0, 160, 0, 0, 16000, 30},  // one launch sequence per interval
-        {1, 4, 1024, 1, 1, 0, 160, 0, 0, 16000, 30},
-        {2, 6, 2048, 1, 1, 0, 160, 0, 0, 16000, 30},
-        {1, 1, 0, 1, 1, 0, 0, 0, 0, 16000, 30},       // one group of 64 particles per wavefront
-        {1, 1, 0, 1, 1, 0, 0, 1, 0, 16000, 30},       // persistent wavefronts (R <= 16)
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 60},  // default: flow schedule
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30},  // flow, shorter queue
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 32000, 60},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 1, 0, 60},      // flow, first come first served
+        {1, 4, 1024, 1, 1, 0, 160, 0, 1, 16000, 60},
+        {1, 6, 1536, 1, 1, 0, 160, 0, 0, 16000, 60},  // one launch sequence per interval
+        {1, 4, 1024, 1, 1, 0, 160, 0, 0, 16000, 60},
+        {2, 6, 2048, 1, 1, 0, 160, 0, 0, 16000, 60},
+        {1, 1, 0, 1, 1, 0, 0, 0, 0, 16000, 60},       // one group of 64 particles per wavefront
+        {1, 1, 0, 1, 1, 0, 0, 1, 0, 16000, 60},       // persistent wavefronts (R <= 16)
     };
     *n = (int)(sizeof(cands) / sizeof(cands[0]));
     return cands;

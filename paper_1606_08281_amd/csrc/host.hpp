@@ -15,7 +15,7 @@
 
 namespace lik {
 // Work partitioning used unless a caller sets another (lik_network_set_tuning).
-constexpr lik_tuning kDefaultTuning = {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 30};
+constexpr lik_tuning kDefaultTuning = {1, 6, 1536, 1, 1, 0, 160, 0, 1, 16000, 60};
 }  // namespace lik
 
 struct lik_network {

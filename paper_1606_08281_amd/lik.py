@@ -491,7 +491,7 @@ def eval_requests(requests, tuning=None, kernel=KERNEL_AUTO):
     if tuning is not None:
         t = dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1,
                  priority=0, items_per_cu=160, persistent=0, schedule=1, urgent_events=16000,
-                 backlog_per_cu=30)
+                 backlog_per_cu=60)
         t.update(tuning)
         tp = Tuning(**{k: int(v) for k, v in t.items()})
     _check(lib().lik_eval_requests(arr, len(requests), None if tp is None else ctypes.byref(tp),
@@ -529,7 +529,7 @@ class Server:
         if tuning is not None:
             t = dict(pool_min=1, pool_max=6, pool_events=1536, pool_first=1, refill_min=1,
                      priority=0, items_per_cu=160, persistent=0, schedule=1,
-                     urgent_events=16000, backlog_per_cu=30)
+                     urgent_events=16000, backlog_per_cu=60)
             t.update(tuning)
             self._tuning = Tuning(**{k: int(v) for k, v in t.items()})
             tp = ctypes.addressof(self._tuning)

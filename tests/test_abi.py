@@ -133,7 +133,7 @@ def test_tuning_set_get_and_bounds():
     net = lik.Network(*[np.asarray(a) for a in (W.telegraph().orders, W.telegraph().stoich)])
     default = {"pool_min": 1, "pool_max": 6, "pool_events": 1536, "pool_first": 1,
                "refill_min": 1, "priority": 0, "items_per_cu": 160, "persistent": 0,
-               "schedule": 1, "urgent_events": 16000, "backlog_per_cu": 30}
+               "schedule": 1, "urgent_events": 16000, "backlog_per_cu": 60}
     assert net.tuning() == default
     assert net.set_tuning(pool_min=1, pool_max=16, pool_events=100, pool_first=3,
                           refill_min=9, priority=1, items_per_cu=0, persistent=1,
