@@ -86,7 +86,7 @@ def lib():
         L.orc_eval.restype = ctypes.c_int
         L.orc_trace_filter.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.orc_trace_filter.restype = ctypes.c_int
-        L.orc_ssa_paths.argtypes = [vp, vp, u32, vp, dbl, dbl, i32, vp, vp]
+        L.orc_ssa_paths.argtypes = [vp, vp, u32, vp, dbl, dbl, i32, vp, vp, vp]
         L.orc_ssa_paths.restype = ctypes.c_int
         L.orc_ode_eval.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_ode_eval.restype = ctypes.c_int
@@ -225,16 +225,19 @@ def trace_filter(prob, i, m):
             "loglik": ll.value, "events": ev.value, "status": st}
 
 
-def ssa_paths(prob, c, x0, t_start, t_end, n_paths, theta_id=0):
-    """n_paths independent direct-method SSA paths from x0 (no filtering)."""
+def ssa_paths(prob, c, x0, t_start, t_end, n_paths, theta_id=0, clocks=False):
+    """n_paths independent direct-method SSA paths from x0 (no filtering):
+    (final states, event counts, status), and with clocks=True each path's
+    clock (time of its last event) after them."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     x0 = np.ascontiguousarray(x0, dtype=np.int32)
     states = np.zeros((n_paths, prob.U), dtype=np.int32)
     ev = np.zeros(n_paths, dtype=np.uint64)
+    clk = np.zeros(n_paths, dtype=np.float64)
     st = lib().orc_ssa_paths(ctypes.byref(prob.c), c.ctypes.data, int(theta_id),
                              x0.ctypes.data, float(t_start), float(t_end), int(n_paths),
-                             states.ctypes.data, ev.ctypes.data)
-    return states, ev, st
+                             states.ctypes.data, ev.ctypes.data, clk.ctypes.data)
+    return (states, ev, st, clk) if clocks else (states, ev, st)
 
 
 # -- deterministic models (ode_oracle.c) -------------------------------------

@@ -288,7 +288,7 @@ void orc_propensities(const orc_problem *P, const double *c, const int32_t *x,
 /* ------------------------------------------------------------------------ */
 static uint64_t ssa_interval(const orc_problem *P, const double *c, int32_t *x,
                              double t_start, double t_end, uint32_t slot,
-                             uint32_t c2, uint32_t theta_id, int *status)
+                             uint32_t c2, uint32_t theta_id, int *status, double *clock_out)
 {
     int U = P->n_species, R = P->n_reactions;
     double a[256], S[256];
@@ -354,6 +354,7 @@ static uint64_t ssa_interval(const orc_problem *P, const double *c, int32_t *x,
         }
         n = n + 1;
     }
+    if (clock_out) *clock_out = clock;   /* time of the last event, t_start if none */
     return n;
 }
 
@@ -480,7 +481,7 @@ static void *simulate_span(void *arg)
         int st;
         int32_t *xj = s->x + (size_t)j * U;
         s->events += ssa_interval(s->P, s->c, xj, s->t_start, s->t_end, (uint32_t)j, s->c2,
-                                  s->theta_id, &st);
+                                  s->theta_id, &st, NULL);
         for (int u = 0; u < U; ++u)
             if (xj[u] > ORC_COUNT_LIMIT) st = st > ORC_COUNT_OVERFLOW ? st : ORC_COUNT_OVERFLOW;
         if (st > s->worst) s->worst = st;
@@ -695,17 +696,20 @@ int orc_trace_filter(const orc_problem *P, int i, int m, int32_t *states, double
 
 /* Plain SSA paths (no observations): n_paths particles from x0 over
  * [t_start, t_end], particle slot j, interval index 0 of trajectory 0.
- * Output states [n_paths][U] and per-path event counts. */
+ * Output states [n_paths][U], per-path event counts and (clock_out not
+ * NULL) each path's clock: the time of its last event, the sum of its
+ * waiting times from t_start. */
 int orc_ssa_paths(const orc_problem *P, const double *c, uint32_t theta_id,
                   const int32_t *x0, double t_start, double t_end, int32_t n_paths,
-                  int32_t *states_out, uint64_t *events_out)
+                  int32_t *states_out, uint64_t *events_out, double *clock_out)
 {
     int U = P->n_species;
     for (int j = 0; j < n_paths; ++j) {
         int32_t *xj = states_out + (size_t)j * U;
         for (int u = 0; u < U; ++u) xj[u] = x0[u];
         int st;
-        events_out[j] = ssa_interval(P, c, xj, t_start, t_end, (uint32_t)j, 0u, theta_id, &st);
+        events_out[j] = ssa_interval(P, c, xj, t_start, t_end, (uint32_t)j, 0u, theta_id, &st,
+                                     clock_out ? clock_out + j : NULL);
         if (st != ORC_OK) return st;
     }
     return 0;

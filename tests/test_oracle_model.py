@@ -10,7 +10,9 @@
   is Poisson, pure death is Binomial, a two-state switch has an explicit
   occupation probability, pure immigration counts events as a Poisson
   process) and against the truncated CME for second-order reactions;
-  conservation laws along paths.  Every one of these runs in both
+  conservation laws along paths; the random-number stream of each mode
+  (which Philox words an event's uniforms come from, and how they are
+  rounded), recomputed path by path, clocks included.  Every one of these runs in both
   arithmetic modes: the binary64 step and the FP32-mixed step (binary32
   propensities, uniforms and waiting times, binary64 clock), whose event
   loop is a separate branch of the oracle.
@@ -143,11 +145,13 @@ def test_fp32_mixed_takes_half_a_block_per_event(orc):
     # 2p + 1 of a path share block p = (p, path, 0, theta_id << 2) under key
     # (seed), the first taking u1, u2 from words 0, 1 and the second from
     # words 2, 3, the leading 24 bits of each.  Two birth reactions, so that
-    # both the waiting times (u1) and the choice of reaction (u2) are checked.
+    # both the waiting times (u1) and the choice of reaction (u2) are checked;
+    # each path's clock, the binary64 sum of its binary32 waiting times, is
+    # compared bit for bit, so that a uniform off by half an ulp shows.
     rates, t_end, n_paths, theta_id, seed = (2.0, 1.0), 3.0, 150, 7, 5
     P = _problem(orc, [[0, 0], [0, 0]], [[1, 0], [0, 1]], precision=1, seed=seed)
-    states, ev, st = orc.ssa_paths(P, list(rates), [0, 0], 0.0, t_end, n_paths,
-                                   theta_id=theta_id)
+    states, ev, st, clk = orc.ssa_paths(P, list(rates), [0, 0], 0.0, t_end, n_paths,
+                                        theta_id=theta_id, clocks=True)
     assert st == 0
     key = [seed & 0xFFFFFFFF, seed >> 32]
     a = [np.float32(r) for r in rates]          # float(c) * float(1) for order 0
@@ -167,6 +171,41 @@ def test_fp32_mixed_takes_half_a_block_per_event(orc):
             clock += float(tau)
             n += 1
         assert int(ev[j]) == n and list(states[j]) == x, (j, n, x)
+        assert clk[j] == clock, (j, clk[j], clock)
+    assert ev.mean() > 5
+
+
+def test_fp64_takes_a_block_per_event(orc):
+    # The binary64 stream layout, recomputed from Philox blocks (pinned to
+    # rocRAND) and the binary64 log (pinned to mpmath): event n of a path
+    # takes block (n, path, 0, theta_id << 2) under key (seed), u1 from the
+    # leading 53 bits of words 1:0 plus one ulp (so in (0, 1]) and u2 from the
+    # leading 53 bits of words 3:2; the waiting time is -log(u1) / a0 and the
+    # reaction the first whose running sum exceeds u2 a0.  Events, states and
+    # each path's clock are compared exactly.
+    rates, t_end, n_paths, theta_id, seed = (2.0, 1.0), 3.0, 150, 11, 9
+    P = _problem(orc, [[0, 0], [0, 0]], [[1, 0], [0, 1]], precision=0, seed=seed)
+    states, ev, st, clk = orc.ssa_paths(P, list(rates), [0, 0], 0.0, t_end, n_paths,
+                                        theta_id=theta_id, clocks=True)
+    assert st == 0
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    a0 = rates[0] + rates[1]
+    for j in range(n_paths):
+        clock, n, x = 0.0, 0, [0, 0]
+        while True:
+            w = [int(v) for v in orc.philox([n, j, 0, theta_id << 2], key)]
+            z1 = ((w[1] << 32) | w[0]) >> 11
+            z2 = ((w[3] << 32) | w[2]) >> 11
+            u1 = (z1 + 1) * 2.0**-53
+            u2 = z2 * 2.0**-53
+            tau = -orc.log(u1) / a0
+            if clock + tau > t_end:
+                break
+            r = 0 if rates[0] > u2 * a0 else 1
+            x[r] += 1
+            clock += tau
+            n += 1
+        assert int(ev[j]) == n and list(states[j]) == x and clk[j] == clock, (j, n, x)
     assert ev.mean() > 5
 
 
