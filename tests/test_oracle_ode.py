@@ -3,9 +3,11 @@ Reaction Networks", deterministic formulation; Results, deterministic models;
 Supplementary "Egf-Ras-Raf-Mek-Erk model").
 
 * closed forms: immigration-death rate equations (exponential relaxation),
-  Michaelis-Menten degradation (implicit solution, root-found by scipy), and
-  an input-driven production with a piecewise-constant input (piecewise
-  exponential relaxation through the breakpoints);
+  Michaelis-Menten degradation (implicit solution, root-found by scipy), an
+  input-driven production with a piecewise-constant input (piecewise
+  exponential relaxation through the breakpoints), and pure input-driven
+  production, which a Runge-Kutta step integrates exactly between
+  breakpoints (so its error stays at rounding level whatever the tolerance);
 * a network with every rate-law factor against scipy's DOP853 at tight
   tolerances, integrated piece by piece between breakpoints;
 * the log-likelihood is the normal log-density of the observations around
@@ -83,6 +85,38 @@ def test_piecewise_input_relaxation(orc):
     states, _, _, st = orc.ode_solve(P, 0, 0)
     assert st == 0
     assert np.allclose(states[:, 0], [exact(tt) for tt in t], rtol=1e-9)
+
+
+def test_input_driven_production_is_exact_between_breakpoints(orc):
+    # x' = k u(t) with u piecewise constant: between breakpoints the right-hand
+    # side is constant, every stage of an explicit Runge-Kutta step equals it
+    # and the step is exact, so x(t) = x0 + k * integral of u to rounding, at
+    # any tolerance.  A step that carried the first stage over from before a
+    # breakpoint (the old input's slope) would be accepted once its error
+    # estimate fell under the loose tolerance, leaving an error of that size.
+    k, x0 = 1.7, 3.0
+    t_in, u_in = np.array([0.7, 1.9, 2.2, 4.1]), np.array([5.0, 0.25, 9.0, 2.0])
+    model = {"U": 1, "V": 1, "terms": [{"to": 0, "rate_param": 0, "factors": [(INP, 0, 0)]}],
+             "x0_param": [-1], "sd_const": 1.0}
+    t = np.array([0.5, 1.0, 2.0, 2.3, 3.0, 4.1, 5.0, 7.5])
+
+    def exact(tt):
+        area, tc, u = 0.0, 0.0, 0.0
+        for tb, ub in zip(np.r_[t_in, np.inf], np.r_[u_in, 0.0]):
+            te = min(tb, tt)
+            area += u * (te - tc)
+            if tt <= tb:
+                return x0 + k * area
+            tc, u = tb, ub
+        return x0 + k * area
+    for rtol, atol in ((1e-4, 1e-4), (1e-6, 1e-6)):
+        P = orc.OdeProblem(model, [[k]], [{"t_obs": t, "y": np.zeros(len(t)), "x0": [x0],
+                                           "t_in": t_in, "u_in": u_in}], rtol=rtol, atol=atol)
+        states, steps, _, st = orc.ode_solve(P, 0, 0)
+        assert st == 0
+        want = np.array([exact(tt) for tt in t])
+        assert np.max(np.abs(states[:, 0] - want)) <= 1e-12 * np.max(np.abs(want)), \
+            (rtol, states[:, 0] - want)
 
 
 def every_factor_model():
