@@ -12,7 +12,8 @@
   process) and against the truncated CME for second-order reactions;
   conservation laws along paths; the random-number stream of each mode
   (which Philox words an event's uniforms come from, and how they are
-  rounded), recomputed path by path, clocks included.  Every one of these runs in both
+  rounded), recomputed path by path, clocks included; reaction choices put
+  on the boundary of the second uniform.  Every one of these runs in both
   arithmetic modes: the binary64 step and the FP32-mixed step (binary32
   propensities, uniforms and waiting times, binary64 clock), whose event
   loop is a separate branch of the oracle.
@@ -207,6 +208,90 @@ def test_fp64_takes_a_block_per_event(orc):
             n += 1
         assert int(ev[j]) == n and list(states[j]) == x and clk[j] == clock, (j, n, x)
     assert ev.mean() > 5
+
+
+def _event_uniforms(orc, precision, seed, theta_id, j, n):
+    """(u1, u2) of event n of path j under the stream layout of each mode:
+    binary64 takes block n, 53 leading bits of words 1:0 and 3:2; FP32-mixed
+    takes half of block n >> 1, 24 leading bits of each word."""
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    if precision == 1:
+        w = [int(v) for v in orc.philox([n >> 1, j, 0, theta_id << 2], key)]
+        h = 2 * (n & 1)
+        return (np.float32(((w[h] >> 8) + 1) * 2.0**-24),
+                np.float32((w[h + 1] >> 8) * 2.0**-24))
+    w = [int(v) for v in orc.philox([n, j, 0, theta_id << 2], key)]
+    return (((((w[1] << 32) | w[0]) >> 11) + 1) * 2.0**-53,
+            (((w[3] << 32) | w[2]) >> 11) * 2.0**-53)
+
+
+def _two_births_path(orc, precision, k1, t_end, seed, theta_id, j, u2_at=None):
+    """Path j of the two-birth network with rates (k1, 1 - k1), whose total
+    propensity is exactly 1 in both modes, recomputed event by event; u2_at =
+    (n, value) replaces event n's second uniform (a planted deviation)."""
+    f = np.float32 if precision == 1 else float
+    a1 = f(k1)
+    a0 = f(a1 + f(1.0 - k1))
+    assert a0 == 1.0
+    clock, n, x = 0.0, 0, [0, 0]
+    while True:
+        u1, u2 = _event_uniforms(orc, precision, seed, theta_id, j, n)
+        if u2_at is not None and u2_at[0] == n:
+            u2 = f(u2_at[1])
+        if precision == 1:
+            tau = float(np.float32(-np.float32(orc.logf(u1))) / a0)
+        else:
+            tau = -orc.log(u1) / a0
+        if clock + tau > t_end:
+            break
+        x[0 if a1 > f(u2 * a0) else 1] += 1
+        clock += tau
+        n += 1
+    return n, x
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_reaction_choice_on_the_boundary(orc, precision):
+    # The second uniform only picks the reaction: the first whose running sum
+    # exceeds u2 a0.  With random rates a wrong rounding of u2 moves a choice
+    # with probability of about one grid step per event, which no path count
+    # resolves.  Here the boundary is put on the uniform itself: two birth
+    # reactions with rates (b, 1 - b), exact in both modes, so a0 = 1 and the
+    # first reaction fires iff u2 < b.  With b = u2 of a chosen event, the
+    # correct u2 takes the second reaction and any smaller one the first;
+    # with b one grid step above u2 (u2 >= 1/2, where that step is the ulp),
+    # the correct u2 takes the first reaction and any larger one the second.
+    # Each case is checked to tell the planted neighbour from the correct
+    # value; the oracle's path must agree with the correct one.
+    f32 = precision == 1
+    grid = 2.0**-24 if f32 else 2.0**-53
+    seed, theta_id, t_end = 13, 3, 6.0
+    cases = {"below": 0, "above": 0}
+    for j in range(48):
+        for n in range(4):                 # both halves of an FP32-mixed block
+            _, u2 = _event_uniforms(orc, precision, seed, theta_id, j, n)
+            u2 = float(u2)
+            for side, b, planted in (("below", u2, np.nextafter(u2, 0.0)),
+                                     ("above", u2 + grid, u2 + grid)):
+                if cases[side] >= 8 or u2 == 0.0 or (side == "above" and u2 < 0.5):
+                    continue
+                if f32:
+                    planted = float(np.nextafter(np.float32(u2), np.float32(0.0))) \
+                        if side == "below" else planted
+                want = _two_births_path(orc, precision, b, t_end, seed, theta_id, j)
+                if want[0] <= n:
+                    continue                # the event falls after t_end
+                bad = _two_births_path(orc, precision, b, t_end, seed, theta_id, j,
+                                       u2_at=(n, planted))
+                assert bad != want, (side, j, n)
+                P = _problem(orc, [[0, 0], [0, 0]], [[1, 0], [0, 1]],
+                             precision=precision, seed=seed)
+                states, ev, st = orc.ssa_paths(P, [b, 1.0 - b], [0, 0], 0.0, t_end, j + 1,
+                                               theta_id=theta_id)
+                assert st == 0
+                assert (int(ev[j]), list(states[j])) == want, (side, j, n, b)
+                cases[side] += 1
+    assert cases == {"below": 8, "above": 8}
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
