@@ -358,6 +358,56 @@ def test_count_overflow(orc, precision, kernel):
     assert np.array_equal(got["filter_events"], ref["events"])   # the stopped ones too
 
 
+def _boundary_batch(orc, precision, n_theta, H, seed, t1):
+    """Rate vectors (b, 1 - b) of two birth reactions (total propensity exactly
+    1), each putting one event of one particle of the first interval on the
+    second uniform's boundary: b at that event's u2 (any smaller u2 flips the
+    choice) or, for u2 >= 1/2, one grid step above it (any larger u2 does).
+    Row i is stream theta_id i; the first interval of trajectory 0 uses the
+    same counters as a plain path (c2 = 0), so the uniforms are those of the
+    oracle's pinned stream layout."""
+    from tests.test_oracle_model import _event_uniforms, _two_births_path
+    grid = 2.0**-24 if precision == 1 else 2.0**-53
+    theta = []
+    for i in range(n_theta):
+        side = "below" if i % 2 == 0 else "above"
+        for k in range(4 * H):
+            j, n = (i * 7 + k) % H, k % 4
+            u2 = float(_event_uniforms(orc, precision, seed, i, j, n)[1])
+            if u2 == 0.0 or (side == "above" and u2 < 0.5):
+                continue
+            b = u2 if side == "below" else u2 + grid
+            if _two_births_path(orc, precision, b, t1, seed, i, j)[0] > n:
+                theta.append([b, 1.0 - b])
+                break
+        else:
+            raise AssertionError(("no boundary event", i))
+    return np.array(theta)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_reaction_choice_on_the_boundary(orc, precision, kernel, schedule):
+    # every rate vector puts one event of the first interval exactly on the
+    # second uniform's boundary (the oracle is pinned there); the GPU path,
+    # its drain draws included (40 particles), must take the same choices:
+    # same final counts, same log-likelihoods
+    H, t1 = 40, 4.0
+    net = W.Network("two births", ["A", "B"], [[0, 0], [0, 0]], [[1, 0], [0, 1]])
+    tr = {"t_obs": np.array([t1, 2 * t1]), "y": np.array([[2.0], [4.5]]), "t0": 0.0,
+          "x0": np.zeros(2, np.int32)}
+    wl = W.Workload("two births", net, W.OBS_GAUSSIAN, [0], 1.0, np.ones((1, 2)), [tr], H)
+    theta = _boundary_batch(orc, precision, 24, H, wl.seed, t1)
+    ids = np.arange(len(theta), dtype=np.uint32)
+    _say("boundary choices precision", precision, "kernel", kernel, "schedule", schedule)
+    got = _gpu(wl, theta=theta, theta_ids=ids, precision=precision, kernel=kernel,
+               tuning=dict(schedule=schedule))
+    ref = _oracle(orc, wl, theta=theta, theta_ids=ids, precision=precision)
+    assert np.all(ref["status"] == 0)
+    assert_parity(got, ref, abs_tol=FP32_ABS if precision else None)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_fp32_rates_beyond_binary32(orc, kernel):
     # a rate beyond the binary32 range is a bad rate vector for the
