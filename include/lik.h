@@ -474,33 +474,6 @@ int lik_timing_enable(int enable);
 int lik_timing_read(lik_timing *out);
 
 /*
- * lik_get_stats -- what the calling thread's last successful lik_eval_batch
- * did, the figures a throughput report needs (SSA events per second; the
- * likelihood of Supplementary I is the product over trajectories, so a
- * theta's events are those of its M filters):
- *   out: its sizes, the SSA events it applied in all, the device time from
- *     its first upload to its last download (HIP events on the call's
- *     stream) and its host time.
- *   events_per_theta [cap] host or NULL: events of theta i summed over its
- *     trajectories, for i < min(cap, n_theta).
- * Counted for every call, whether or not it asked for lik_aux outputs.
- * Thread-local; a call that fails leaves the previous record in place.
- * Returns LIK_EINVAL if out is NULL, cap is negative or the thread has made
- * no successful lik_eval_batch call with n_theta > 0.
- */
-typedef struct lik_stats {
-    int32_t n_theta;
-    int32_t n_traj;
-    int32_t n_particles;
-    int32_t precision;          /* LIK_FP64 or LIK_FP32_MIXED */
-    uint64_t events;            /* SSA events applied over the call */
-    double device_ms;           /* stream time: uploads, kernels, downloads */
-    double host_ms;             /* host time of the whole call */
-} lik_stats;
-
-int lik_get_stats(lik_stats *out, uint64_t *events_per_theta, int32_t cap);
-
-/*
  * lik_autotune_device -- times lik_eval_batch_device on these exact buffers
  * for a fixed set of candidate tunings (synchronising `stream` after each),
  * keeps the fastest as the network's tuning and writes it to *chosen (may be

@@ -5,7 +5,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <chrono>
 #include <mutex>
 #include <new>
 #include <string>
@@ -19,14 +18,6 @@ using namespace lik;
 
 namespace {
 thread_local std::string g_err;
-
-// the calling thread's last successful lik_eval_batch (lik_get_stats)
-struct CallStats {
-    bool valid = false;
-    lik_stats s{};
-    std::vector<uint64_t> per_theta;
-};
-thread_local CallStats g_stats;
 }  // namespace
 
 int lik::fail(int code, const std::string &msg) {
@@ -868,7 +859,6 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
     rc = check_host_data(net, obs, data, n_theta, opts ? opts->theta_ids : nullptr);
     if (rc) return rc;
 
-    const auto t_host0 = std::chrono::steady_clock::now();
     const size_t F = (size_t)n_theta * M;
     const size_t ws = lik_workspace_size(net, n_theta, M, n_particles);
     const size_t sz_theta = (size_t)n_theta * net->R * 8;
@@ -877,7 +867,7 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
     const size_t sz_y = (size_t)total * P * 8, sz_t0 = (size_t)M * 8, sz_x0 = (size_t)M * U * 4;
     const size_t sz_x0h = data->x0_hi ? sz_x0 : 0;
     const size_t sz_ll = (size_t)n_theta * 8, sz_st = (size_t)n_theta * 4;
-    const size_t sz_ev = F * 8;   // always: the call's event counts (lik_get_stats)
+    const size_t sz_ev = (aux && aux->filter_events) ? F * 8 : 0;
     const size_t sz_fl = (aux && aux->filter_loglik) ? F * 8 : 0;
     const size_t sz_fs = (aux && aux->final_state) ? F * U * n_particles * 4 : 0;
     const size_t sizes[] = {sz_theta, sz_ids, sz_off, sz_t, sz_y, sz_t0, sz_x0, sz_x0h,
@@ -909,16 +899,9 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
     void *d_ws = take(ws);
 
     hipStream_t s = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<uint64_t> h_ev(F);
     rc = LIK_OK;
     do {
         if ((e = hipStreamCreate(&s)) != hipSuccess) { rc = hip_fail(e, "hipStreamCreate"); break; }
-        if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess ||
-            (e = hipEventRecord(ev0, s)) != hipSuccess) {
-            rc = hip_fail(e, "event");
-            break;
-        }
         struct { void *d; const void *h; size_t n; } up[] = {
             {d_theta, theta, sz_theta}, {d_ids, opts ? opts->theta_ids : nullptr, sz_ids},
             {d_off, data->obs_offsets, sz_off}, {d_t, data->t_obs, sz_t}, {d_y, data->y, sz_y},
@@ -931,13 +914,13 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
         lik_eval_opts o = opts ? *opts : lik_eval_opts{LIK_FP64, LIK_KERNEL_AUTO, 0, nullptr, 0, 0};
         o.theta_ids = sz_ids ? d_ids : nullptr;
         lik_data dd = {M, d_off, d_t, d_y, d_t0, d_x0, sz_x0h ? d_x0h : nullptr};
-        lik_aux da = {d_ev, sz_fl ? d_fl : nullptr, sz_fs ? d_fs : nullptr};
+        lik_aux da = {sz_ev ? d_ev : nullptr, sz_fl ? d_fl : nullptr, sz_fs ? d_fs : nullptr};
         rc = lik_eval_batch_device(net, obs, &o, n_theta, d_theta, &dd, data->obs_offsets,
-                                   n_particles, seed, d_ll, d_st, &da, d_ws, ws, s);
+                                   n_particles, seed, d_ll, d_st, aux ? &da : nullptr, d_ws, ws, s);
         if (rc) break;
         struct { void *h; const void *d; size_t n; } down[] = {
             {loglik_out, d_ll, sz_ll}, {status_out, d_st, status_out ? sz_st : 0},
-            {h_ev.data(), d_ev, sz_ev},
+            {aux ? aux->filter_events : nullptr, d_ev, sz_ev},
             {aux ? aux->filter_loglik : nullptr, d_fl, sz_fl},
             {aux ? aux->final_state : nullptr, d_fs, sz_fs}};
         for (auto &d : down) {
@@ -945,49 +928,11 @@ int lik_eval_batch(lik_network_t net, const lik_obs_model *obs, const lik_eval_o
             if ((e = hipMemcpyAsync(d.h, d.d, d.n, hipMemcpyDeviceToHost, s)) != hipSuccess) break;
         }
         if (e != hipSuccess) { rc = hip_fail(e, "copy to host"); break; }
-        if ((e = hipEventRecord(ev1, s)) != hipSuccess) { rc = hip_fail(e, "event"); break; }
         if ((e = hipStreamSynchronize(s)) != hipSuccess) { rc = hip_fail(e, "synchronize"); break; }
-        float dev_ms = 0.0f;
-        if ((e = hipEventElapsedTime(&dev_ms, ev0, ev1)) != hipSuccess) {
-            rc = hip_fail(e, "hipEventElapsedTime");
-            break;
-        }
-        if (aux && aux->filter_events) memcpy(aux->filter_events, h_ev.data(), sz_ev);
-        CallStats &cs = g_stats;
-        cs.per_theta.assign((size_t)n_theta, 0);
-        uint64_t all = 0;
-        for (size_t f = 0; f < F; ++f) {
-            cs.per_theta[f / (size_t)M] += h_ev[f];
-            all += h_ev[f];
-        }
-        cs.s.n_theta = n_theta;
-        cs.s.n_traj = M;
-        cs.s.n_particles = n_particles;
-        cs.s.precision = opts ? opts->precision : LIK_FP64;
-        cs.s.events = all;
-        cs.s.device_ms = dev_ms;
-        cs.s.host_ms = std::chrono::duration<double, std::milli>(
-                           std::chrono::steady_clock::now() - t_host0).count();
-        cs.valid = true;
     } while (0);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
     if (s) (void)hipStreamDestroy(s);
     (void)hipFree(dev);
     return rc;
-}
-
-int lik_get_stats(lik_stats *out, uint64_t *events_per_theta, int32_t cap) {
-    if (!out) return fail(LIK_EINVAL, "out is NULL");
-    if (cap < 0) return fail(LIK_EINVAL, "cap is negative");
-    const CallStats &cs = g_stats;
-    if (!cs.valid) return fail(LIK_EINVAL, "no successful lik_eval_batch call on this thread");
-    *out = cs.s;
-    if (events_per_theta) {
-        const size_t n = std::min((size_t)cap, cs.per_theta.size());
-        std::copy(cs.per_theta.begin(), cs.per_theta.begin() + n, events_per_theta);
-    }
-    return LIK_OK;
 }
 
 }  // extern "C"

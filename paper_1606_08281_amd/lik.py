@@ -29,8 +29,7 @@ EXPORTED = ["lik_create_network", "lik_destroy_network", "lik_network_precompile
             "lik_server_create",
             "lik_server_submit", "lik_server_wait", "lik_server_cancel", "lik_server_stats_get",
             "lik_server_destroy",
-            "lik_timing_enable", "lik_timing_read", "lik_get_stats", "lik_last_error",
-            "lik_version",
+            "lik_timing_enable", "lik_timing_read", "lik_last_error", "lik_version",
             "lik_network_set_tuning", "lik_network_get_tuning", "lik_autotune_device",
             "lik_eval_requests", "lik_precompile_requests", "lik_autotune_requests",
             "lik_ode_create", "lik_ode_destroy", "lik_ode_eval", "lik_ode_precompile",
@@ -65,13 +64,6 @@ class EvalOpts(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("propagate_ms", ctypes.c_double), ("propagate_launches", ctypes.c_int64),
                 ("weigh_ms", ctypes.c_double), ("weigh_launches", ctypes.c_int64)]
-
-
-class Stats(ctypes.Structure):
-    _fields_ = [("n_theta", ctypes.c_int32), ("n_traj", ctypes.c_int32),
-                ("n_particles", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("events", ctypes.c_uint64), ("device_ms", ctypes.c_double),
-                ("host_ms", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -187,8 +179,6 @@ def lib():
         L.lik_timing_enable.restype = ctypes.c_int
         L.lik_timing_read.argtypes = [vp]
         L.lik_timing_read.restype = ctypes.c_int
-        L.lik_get_stats.argtypes = [vp, vp, i32]
-        L.lik_get_stats.restype = ctypes.c_int
         L.lik_last_error.restype = ctypes.c_char_p
         L.lik_version.restype = ctypes.c_char_p
         _lib = L
@@ -214,20 +204,6 @@ def timing_read():
     _check(lib().lik_timing_read(ctypes.byref(t)))
     return {"propagate_ms": t.propagate_ms, "propagate_launches": t.propagate_launches,
             "weigh_ms": t.weigh_ms, "weigh_launches": t.weigh_launches}
-
-
-def get_stats(cap=None):
-    """lik_get_stats: the calling thread's last successful lik_eval_batch as a
-    dict (sizes, events, device_ms, host_ms) with events_per_theta [n]
-    (n = cap, default the call's n_theta)."""
-    st = Stats()
-    _check(lib().lik_get_stats(ctypes.byref(st), None, 0))
-    n = st.n_theta if cap is None else int(cap)
-    per = np.zeros(max(n, 0), dtype=np.uint64)
-    _check(lib().lik_get_stats(ctypes.byref(st), per.ctypes.data if n > 0 else None, n))
-    out = {k: getattr(st, k) for k, _ in Stats._fields_}
-    out["events_per_theta"] = per
-    return out
 
 
 def _tuning_dict(t):

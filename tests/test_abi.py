@@ -115,28 +115,6 @@ def test_empty_batch_is_ok_without_device():
     assert out["loglik"].shape == (0,)
 
 
-def test_stats_need_a_successful_call_on_the_thread():
-    # lik_get_stats is thread-local and records only calls that ran (an empty
-    # batch or a call refused on the host leaves no record)
-    import threading
-    wl, a = _args(theta=np.zeros((0, 2)))
-    net = lik.Network(wl.net.orders, wl.net.stoich)
-    errs = []
-
-    def run():
-        lik.eval_batch(net, **a)
-        with pytest.raises(lik.LikError) as ei:
-            lik.get_stats()
-        errs.append(ei.value.code)
-        with pytest.raises(lik.LikError):
-            lik.get_stats(cap=-1)
-
-    t = threading.Thread(target=run)
-    t.start()
-    t.join()
-    assert errs == [lik.LIK_EINVAL]
-
-
 def test_precompile_specialized_kernels_without_gpu(tmp_path, monkeypatch):
     # run-time specialisation compiles with hipRTC for gfx950; no device needed
     monkeypatch.setenv("LIK_KERNEL_CACHE", str(tmp_path))
