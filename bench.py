@@ -21,11 +21,15 @@ The VALU roofline is priced with the lane-op issue slots per SSA event that
 rocprofv3 measured on the same kernel sources (SQ_THREAD_CYCLES_VALU divided
 by the launch's events, from the committed profile record); where no such
 record matches the sources, with the model count of the event's operations
-at their measured gfx950 issue costs.
+at their measured gfx950 issue costs.  Beside the whole-run rate the line
+carries each timed step's device time (median, min, max, spread: HIP events
+on the launch stream between steps) and the clocks and power rocm-smi reports
+right after the timed steps.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -214,13 +218,17 @@ def bench_erk(args):
     steps_sum.zero_()
     lik.timing_read()
     lik.timing_enable(True)
+    mark, step_summary = step_clock(torch, args.steps, torch.cuda.current_stream())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    mark()
     for k in range(args.steps):
         db.run(theta, **kw)
         steps_sum.add_(db.steps[:n * len(trajs)].to(torch.float64).sum())
+        mark()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    dev_state = device_state()
     lik.timing_enable(False)
     tm = lik.timing_read()
     say(f"{args.steps} steps done")
@@ -247,6 +255,8 @@ def bench_erk(args):
                                "piecewise-constant EGF input patterns x 60 FRET observations; "
                                "Dormand-Prince 5(4), rtol 1e-6, atol 1e-9", "n_theta": n},
         "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
+        "step_ms": step_summary(),
+        "device": dev_state,
         "solver_steps_per_eval": steps_total / (n * args.steps),
         "host_entry_point": {"evals_per_s": n / host_s, "ms": host_s * 1e3,
                              "path": "lik_ode_eval: host buffers, input copies, allocation and "
@@ -283,6 +293,45 @@ def bench_erk(args):
                                "sample": f"the whole batch ({n} theta, all 6 patterns); "
                                          f"{ct:.1f} s wall on {nth} threads"}
     print(json.dumps(out), flush=True)
+
+
+def step_clock(torch, n_steps, stream):
+    """HIP events recorded on the launch stream before the first timed step
+    and after each one: per-step device times with no host synchronisation
+    inside the timed region.  mark() after each step; summary() once the
+    stream has been synchronised."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_steps + 1)]
+    state = {"k": 0}
+
+    def mark():
+        ev[state["k"]].record(stream)
+        state["k"] += 1
+
+    def summary():
+        ms = [a.elapsed_time(b) for a, b in zip(ev[:-1], ev[1:])]
+        med = float(np.median(ms))
+        return {"median": med, "min": float(min(ms)), "max": float(max(ms)),
+                "spread": float((max(ms) - min(ms)) / med) if med > 0 else None,
+                "each": [round(float(v), 3) for v in ms],
+                "basis": "HIP events between consecutive timed steps on the launch stream"}
+
+    return mark, summary
+
+
+def device_state():
+    """Clocks and power as rocm-smi reports them, read once right after the
+    timed steps (a child process; null fields if the tool is unavailable)."""
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showmaxpower",
+                            "--json"], capture_output=True, text=True, timeout=30)
+        txt = r.stdout[r.stdout.find("{"):]
+        d = json.loads(txt) if txt else {}
+        card = next((v for k, v in d.items() if k.startswith("card")), {})
+        keep = {k: v for k, v in card.items()
+                if any(w in k.lower() for w in ("clk", "clock", "power"))}
+        return {"rocm_smi": keep or None}
+    except (OSError, ValueError, subprocess.SubprocessError) as e:
+        return {"rocm_smi": None, "error": str(e)[:200]}
 
 
 def main():
@@ -377,14 +426,18 @@ def main():
 
     lik.timing_read()
     lik.timing_enable(True)
+    mark, step_summary = step_clock(torch, args.steps, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    mark()
     for k in range(args.steps):
         db.run(theta, wl.seed + k, stream=stream)
         count_events()
+        mark()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print(f"[bench] {args.steps} steps done", flush=True, file=sys.stderr)
+    dev_state = device_state()
     events = int(ev_sum.item())
     max_per_particle = float(ev_max.item()) / wl.n_particles
     lik.timing_enable(False)
@@ -501,6 +554,8 @@ def main():
             "kernel": ["auto", "generic", "specialised"][args.kernel],
             "graph": bool(args.graph),
         },
+        "step_ms": step_summary(),
+        "device": dev_state,
         "reaction_events_per_s": events / elapsed,
         "events_per_step": events // args.steps,
         "max_events_per_particle": max_per_particle,
