@@ -29,6 +29,7 @@ right after the timed steps.
 import argparse
 import json
 import os
+import shutil
 import subprocess
 import sys
 import time
@@ -320,10 +321,20 @@ def step_clock(torch, n_steps, stream):
 
 def device_state():
     """Clocks and power as rocm-smi reports them, read once right after the
-    timed steps (a child process; null fields if the tool is unavailable)."""
+    timed steps (a child process; null fields if the tool is unavailable).
+    The tool is a Python script: it runs under this interpreter, so no
+    launcher process (its `env` line) stands between; and it is not started
+    at all under a profiler, whose preloaded library the child would inherit."""
+    preload = os.environ.get("LD_PRELOAD", "")
+    if "rocprof" in preload or any(k.startswith("ROCPROF") for k in os.environ):
+        return {"rocm_smi": None, "skipped": "running under a profiler"}
     try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showmaxpower",
-                            "--json"], capture_output=True, text=True, timeout=30)
+        tool = shutil.which("rocm-smi")
+        if tool is None:
+            raise FileNotFoundError("rocm-smi not on PATH")
+        r = subprocess.run([sys.executable, os.path.realpath(tool), "--showclocks",
+                            "--showpower", "--showmaxpower", "--json"],
+                           capture_output=True, text=True, timeout=30)
         txt = r.stdout[r.stdout.find("{"):]
         d = json.loads(txt) if txt else {}
         card = next((v for k, v in d.items() if k.startswith("card")), {})

@@ -1,7 +1,9 @@
 """Host logic of bench.py that needs no GPU: the per-step summary and the
 reading of rocm-smi's clocks and power."""
 import json
+import shutil
 import subprocess
+import sys
 import types
 
 import bench
@@ -41,10 +43,13 @@ def test_device_state_keeps_clocks_and_power(monkeypatch):
     out = "WARNING: something\n" + json.dumps(report)
 
     def fake_run(cmd, **kw):
-        assert cmd[0] == "rocm-smi" and "--json" in cmd
+        # the script under this interpreter: no `env` launcher in between
+        assert cmd[0] == sys.executable and cmd[1].endswith("rocm_smi.py") and "--json" in cmd
         return types.SimpleNamespace(stdout=out, returncode=0)
 
     monkeypatch.setattr(subprocess, "run", fake_run)
+    monkeypatch.setattr(shutil, "which", lambda name: "/opt/rocm/libexec/rocm_smi/rocm_smi.py")
+    monkeypatch.delenv("LD_PRELOAD", raising=False)
     got = bench.device_state()["rocm_smi"]
     assert set(got) == {"sclk clock speed:", "mclk clock speed:",
                         "Current Socket Graphics Package Power (W)",
@@ -52,9 +57,16 @@ def test_device_state_keeps_clocks_and_power(monkeypatch):
 
 
 def test_device_state_without_the_tool(monkeypatch):
-    def missing(cmd, **kw):
-        raise FileNotFoundError("rocm-smi")
-
-    monkeypatch.setattr(subprocess, "run", missing)
+    monkeypatch.setattr(shutil, "which", lambda name: None)
+    monkeypatch.delenv("LD_PRELOAD", raising=False)
     got = bench.device_state()
     assert got["rocm_smi"] is None and "rocm-smi" in got["error"]
+
+
+def test_device_state_not_read_under_a_profiler(monkeypatch):
+    def never(cmd, **kw):
+        raise AssertionError("no child process under a profiler")
+
+    monkeypatch.setattr(subprocess, "run", never)
+    monkeypatch.setenv("LD_PRELOAD", "/opt/rocm/lib/rocprofiler-sdk/librocprofiler-sdk-tool.so")
+    assert bench.device_state()["rocm_smi"] is None
