@@ -153,3 +153,46 @@ def test_uneven_batch_one_launch_sampled(orc):
         ref = orc.evaluate(P)
         assert np.array_equal(st[k], ref["status"])
         assert np.all(np.abs(ll[k] - ref["loglik"]) <= REL * np.abs(ref["loglik"]))
+
+
+def test_requests_on_the_reaction_boundary(orc):
+    # every request is one rate vector that puts one event of its first
+    # interval exactly on the second uniform's boundary (the construction of
+    # the batch-path test); both precisions in one launch, each request
+    # against the oracle, with a margin that a flipped choice would break
+    from paper_1606_08281_amd import lik
+    from tests.test_gpu_parity import _boundary_batch
+    H, t1 = 40, 4.0
+    wl_net = W.Network("two births", ["A", "B"], [[0, 0], [0, 0]], [[1, 0], [0, 1]])
+    tr = {"t_obs": np.array([t1, 2 * t1]), "y": np.array([[2.0], [4.5]]), "t0": 0.0,
+          "x0": np.zeros(2, np.int32)}
+    net = lik.Network(wl_net.orders, wl_net.stoich)
+    reqs, refs = [], []
+    for precision in (0, 1):
+        theta = _boundary_batch(orc, precision, 16, H, W.SEED_FILTER, t1)
+        f = np.float32 if precision else float
+        flipped = theta.copy()
+        for i in range(len(theta)):
+            b = f(theta[i, 0])
+            b2 = float(np.nextafter(b, f(1.0) if i % 2 == 0 else f(0.0)))
+            flipped[i] = [b2, 1.0 - b2]
+
+        def oracle(th):
+            P = orc.Problem(wl_net.orders, wl_net.stoich, W.OBS_GAUSSIAN, [0], 1.0, th, [tr],
+                            H, W.SEED_FILTER, precision=precision,
+                            theta_ids=np.arange(len(th), dtype=np.uint32))
+            return orc.evaluate(P)["loglik"]
+
+        ref, ref_flip = oracle(theta), oracle(flipped)
+        assert np.all(np.abs(ref_flip - ref) > 10 * REL * np.abs(ref)), precision
+        for i in range(len(theta)):
+            reqs.append(dict(net=net, obs_kind=W.OBS_GAUSSIAN, observed=[0], sigma=1.0,
+                             theta=theta[i:i + 1], trajectories=[tr], n_particles=H,
+                             seed=W.SEED_FILTER, precision=precision, event_cap=0,
+                             theta_ids=np.array([i])))
+            refs.append(ref[i])
+    _say("eval_requests on the reaction boundary")
+    ll, st, _ = lik.eval_requests(reqs)
+    for k, want in enumerate(refs):
+        assert st[k][0] == 0, k
+        assert abs(ll[k][0] - want) <= REL * abs(want), (k, ll[k][0], want)
