@@ -158,8 +158,9 @@ def test_uneven_batch_one_launch_sampled(orc):
 def test_requests_on_the_reaction_boundary(orc):
     # every request is one rate vector that puts one event of its first
     # interval exactly on the second uniform's boundary (the construction of
-    # the batch-path test); both precisions in one launch, each request
-    # against the oracle, with a margin that a flipped choice would break
+    # the batch-path test); one launch per precision (a call takes one), each
+    # request against the oracle, with a margin that a flipped choice would
+    # break
     from paper_1606_08281_amd import lik
     from tests.test_gpu_parity import _boundary_batch
     H, t1 = 40, 4.0
@@ -167,8 +168,8 @@ def test_requests_on_the_reaction_boundary(orc):
     tr = {"t_obs": np.array([t1, 2 * t1]), "y": np.array([[2.0], [4.5]]), "t0": 0.0,
           "x0": np.zeros(2, np.int32)}
     net = lik.Network(wl_net.orders, wl_net.stoich)
-    reqs, refs = [], []
     for precision in (0, 1):
+        reqs, refs = [], []
         theta = _boundary_batch(orc, precision, 16, H, W.SEED_FILTER, t1)
         f = np.float32 if precision else float
         flipped = theta.copy()
@@ -191,8 +192,8 @@ def test_requests_on_the_reaction_boundary(orc):
                              seed=W.SEED_FILTER, precision=precision, event_cap=0,
                              theta_ids=np.array([i])))
             refs.append(ref[i])
-    _say("eval_requests on the reaction boundary")
-    ll, st, _ = lik.eval_requests(reqs)
-    for k, want in enumerate(refs):
-        assert st[k][0] == 0, k
-        assert abs(ll[k][0] - want) <= REL * abs(want), (k, ll[k][0], want)
+        _say("eval_requests on the reaction boundary, precision", precision)
+        ll, st, _ = lik.eval_requests(reqs)
+        for k, want in enumerate(refs):
+            assert st[k][0] == 0, k
+            assert abs(ll[k][0] - want) <= REL * abs(want), (k, ll[k][0], want)
